@@ -1,0 +1,263 @@
+"""FP64 CPU oracle for one MPPI iteration -- Python wrapper.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline leg use this module; the product package never imports it.  The
+arithmetic lives in ``mppi_oracle.c`` (plain C, binary64) next to this file,
+which shares no code with the HIP library.
+
+Every entry point takes plain parameters: a ``params`` mapping (the keys
+produced by the seeded scene generator: K, T, dt, wheelbase, lam, gamma,
+sigma, u_min, u_max, v_max, w_track, w_speed, w_effort, w_coll, d_safe_c,
+d_safe_0, ego_r, ego_off, seed) and float64 numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mppi_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+OK, E_INVALID, E_NONFINITE = 0, -1, -4
+
+
+class OrcCfg(ctypes.Structure):
+    _fields_ = [
+        ("K", ctypes.c_int32), ("T", ctypes.c_int32),
+        ("dt", ctypes.c_double), ("wheelbase", ctypes.c_double),
+        ("lam", ctypes.c_double), ("gamma", ctypes.c_double),
+        ("sigma_a", ctypes.c_double), ("sigma_d", ctypes.c_double),
+        ("a_min", ctypes.c_double), ("a_max", ctypes.c_double),
+        ("d_min", ctypes.c_double), ("d_max", ctypes.c_double),
+        ("v_max", ctypes.c_double),
+        ("w_track", ctypes.c_double), ("w_speed", ctypes.c_double),
+        ("w_effort", ctypes.c_double), ("w_coll", ctypes.c_double),
+        ("d_safe_c", ctypes.c_double), ("d_safe_0", ctypes.c_double),
+        ("n_ego", ctypes.c_int32), ("ego_r", ctypes.c_double),
+        ("ego_off", ctypes.c_double * 4),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+def build(force: bool = False) -> str:
+    """Compile ``mppi_oracle.c`` into ``liboracle.so`` (gcc, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            L = ctypes.CDLL(_LIB)
+            dp = ctypes.POINTER(ctypes.c_double)
+            cp = ctypes.POINTER(OrcCfg)
+            u32p = ctypes.POINTER(ctypes.c_uint32)
+            L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+            L.orc_uniform.argtypes = [ctypes.c_uint32]
+            L.orc_uniform.restype = ctypes.c_double
+            L.orc_box_muller.argtypes = [ctypes.c_double, ctypes.c_double, dp]
+            L.orc_noise.argtypes = [cp, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, dp]
+            L.orc_apply_limits.argtypes = [cp, dp, dp, ctypes.c_double, dp]
+            L.orc_dynamics.argtypes = [cp, dp, dp, dp]
+            L.orc_stage_cost.argtypes = [cp, dp, ctypes.c_int, dp, ctypes.c_int, dp, dp, dp,
+                                         ctypes.c_int, dp]
+            L.orc_stage_cost.restype = ctypes.c_double
+            L.orc_rollout.argtypes = [cp, dp, dp, ctypes.c_int, dp, ctypes.c_int, dp,
+                                      ctypes.c_uint64, dp, dp, dp]
+            L.orc_simulate.argtypes = [cp, dp, dp, ctypes.c_int, dp, ctypes.c_int, dp, dp,
+                                       dp, dp, dp]
+            L.orc_weights.argtypes = [dp, ctypes.c_int, ctypes.c_double, dp, dp, dp]
+            L.orc_update.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, dp]
+            L.orc_iteration.argtypes = [cp, dp, dp, ctypes.c_int, dp, ctypes.c_int, dp,
+                                        ctypes.c_uint64, dp, dp, dp, dp, dp]
+            _lib = L
+    return _lib
+
+
+def _dp(a):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def make_cfg(p) -> OrcCfg:
+    c = OrcCfg()
+    c.K, c.T = int(p["K"]), int(p["T"])
+    c.dt, c.wheelbase = float(p["dt"]), float(p["wheelbase"])
+    c.lam, c.gamma = float(p["lam"]), float(p["gamma"])
+    c.sigma_a, c.sigma_d = float(p["sigma"][0]), float(p["sigma"][1])
+    c.a_min, c.d_min = float(p["u_min"][0]), float(p["u_min"][1])
+    c.a_max, c.d_max = float(p["u_max"][0]), float(p["u_max"][1])
+    c.v_max = float(p["v_max"])
+    c.w_track, c.w_speed = float(p["w_track"]), float(p["w_speed"])
+    c.w_effort, c.w_coll = float(p["w_effort"]), float(p["w_coll"])
+    c.d_safe_c, c.d_safe_0 = float(p["d_safe_c"]), float(p["d_safe_0"])
+    offs = list(p["ego_off"])
+    c.n_ego = len(offs)
+    c.ego_r = float(p["ego_r"])
+    for i, o in enumerate(offs):
+        c.ego_off[i] = float(o)
+    c.seed = int(p["seed"])
+    return c
+
+
+def philox(ctr, key):
+    """Philox4x32-10 of one 128-bit counter under a 64-bit key -> 4 uint32."""
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def uniform(r: int) -> float:
+    return lib().orc_uniform(int(r) & 0xFFFFFFFF)
+
+
+def box_muller(u1: float, u2: float):
+    z = np.zeros(2)
+    lib().orc_box_muller(float(u1), float(u2), _dp(z))
+    return z
+
+
+def noise(p, n_iter: int, k: int, t: int):
+    """Raw (unclamped) perturbation of step t of sample k at iteration n_iter."""
+    c = make_cfg(p)
+    e = np.zeros(2)
+    lib().orc_noise(ctypes.byref(c), int(n_iter), int(k), int(t), _dp(e))
+    return e
+
+
+def apply_limits(p, U_t, eps, v):
+    c = make_cfg(p)
+    U_t, eps = _f64(U_t), _f64(eps)
+    out = np.zeros(2)
+    lib().orc_apply_limits(ctypes.byref(c), _dp(U_t), _dp(eps), float(v), _dp(out))
+    return out
+
+
+def dynamics(p, x, u):
+    c = make_cfg(p)
+    x, u = _f64(x), _f64(u)
+    out = np.zeros(4)
+    lib().orc_dynamics(ctypes.byref(c), _dp(x), _dp(u), _dp(out))
+    return out
+
+
+def stage_cost(p, waypoints, circles, x_new, U_t, eps, t):
+    """Stage cost on the new state; returns (cost, (c_dist, c_speed, q_u, c_safe))."""
+    c = make_cfg(p)
+    wp = _f64(waypoints, (-1, 4))
+    ci = _f64(circles, (-1, 5)) if len(circles) else np.zeros((0, 5))
+    xn, U_t, eps = _f64(x_new), _f64(U_t), _f64(eps)
+    parts = np.zeros(4)
+    v = lib().orc_stage_cost(ctypes.byref(c), _dp(wp), wp.shape[0], _dp(ci), ci.shape[0],
+                             _dp(xn), _dp(U_t), _dp(eps), int(t), _dp(parts))
+    return v, parts
+
+
+def simulate(p, x0, waypoints, circles, U, eps=None):
+    """Deterministic rollout of one control sequence U (+ optional eps).
+    Returns (states [T+1][4], stage costs [T], parts [T][4])."""
+    c = make_cfg(p)
+    T = c.T
+    wp = _f64(waypoints, (-1, 4))
+    ci = _f64(circles, (-1, 5)) if len(circles) else np.zeros((0, 5))
+    U = _f64(U, (T, 2))
+    e = None if eps is None else _f64(eps, (T, 2))
+    x0 = _f64(x0)
+    states = np.zeros((T + 1, 4))
+    costs = np.zeros(T)
+    parts = np.zeros((T, 4))
+    rc = lib().orc_simulate(ctypes.byref(c), _dp(x0), _dp(wp), wp.shape[0], _dp(ci),
+                            ci.shape[0], _dp(U), _dp(e), _dp(states), _dp(costs), _dp(parts))
+    if rc != OK:
+        raise ValueError("orc_simulate: status %d" % rc)
+    return states, costs, parts
+
+
+def rollout(p, x0, waypoints, circles, U, n_iter=0, eps_in=None):
+    """All K rollouts.  Returns (S [K], eps_eff [T][K][2])."""
+    c = make_cfg(p)
+    K, T = c.K, c.T
+    wp = _f64(waypoints, (-1, 4))
+    ci = _f64(circles, (-1, 5)) if len(circles) else np.zeros((0, 5))
+    U = _f64(U, (T, 2))
+    x0 = _f64(x0)
+    ein = None if eps_in is None else _f64(eps_in, (T, K, 2))
+    S = np.zeros(K)
+    eps = np.zeros((T, K, 2))
+    rc = lib().orc_rollout(ctypes.byref(c), _dp(x0), _dp(wp), wp.shape[0], _dp(ci), ci.shape[0],
+                           _dp(U), int(n_iter), _dp(ein), _dp(S), _dp(eps))
+    if rc != OK:
+        raise ValueError("orc_rollout: status %d" % rc)
+    return S, eps
+
+
+def weights(S, lam):
+    """Normalised weights, S_min and log Z.  Raises on all-non-finite."""
+    S = _f64(S)
+    w = np.zeros(S.shape[0])
+    smin = ctypes.c_double()
+    logz = ctypes.c_double()
+    rc = lib().orc_weights(_dp(S), S.shape[0], float(lam), _dp(w), ctypes.byref(smin),
+                           ctypes.byref(logz))
+    if rc == E_NONFINITE:
+        raise FloatingPointError("every sample cost is non-finite")
+    if rc != OK:
+        raise ValueError("orc_weights: status %d" % rc)
+    return w, smin.value, logz.value
+
+
+def update(U, w, eps):
+    """Returns U + sum_k w_k eps[:, k, :] (a new array)."""
+    U = _f64(U).copy()
+    T = U.shape[0]
+    w = _f64(w)
+    K = w.shape[0]
+    eps = _f64(eps, (T, K, 2))
+    lib().orc_update(_dp(U), T, K, _dp(w), _dp(eps))
+    return U
+
+
+def iteration(p, x0, waypoints, circles, U, n_iter=0):
+    """One MPPI iteration.  Returns dict(U, S, w, eps, s_min, log_z)."""
+    c = make_cfg(p)
+    K, T = c.K, c.T
+    wp = _f64(waypoints, (-1, 4))
+    ci = _f64(circles, (-1, 5)) if len(circles) else np.zeros((0, 5))
+    Un = _f64(U, (T, 2)).copy()
+    x0 = _f64(x0)
+    S = np.zeros(K)
+    w = np.zeros(K)
+    eps = np.zeros((T, K, 2))
+    smin = ctypes.c_double()
+    logz = ctypes.c_double()
+    rc = lib().orc_iteration(ctypes.byref(c), _dp(x0), _dp(wp), wp.shape[0], _dp(ci),
+                             ci.shape[0], _dp(Un), int(n_iter), _dp(S), _dp(w), _dp(eps),
+                             ctypes.byref(smin), ctypes.byref(logz))
+    if rc == E_NONFINITE:
+        raise FloatingPointError("every sample cost is non-finite")
+    if rc != OK:
+        raise ValueError("orc_iteration: status %d" % rc)
+    return dict(U=Un, S=S, w=w, eps=eps, s_min=smin.value, log_z=logz.value)
