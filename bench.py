@@ -1,0 +1,224 @@
+#!/usr/bin/env python3
+"""Benchmark of one MPPI iteration on one MI355X.
+
+A step is one MPPI iteration (noise generation, rollouts, costs, weights and
+the control update) of the sine-lane single instance: K = 8192 samples,
+T = 100 steps, dt = 0.05 s, 221 waypoints, 20 obstacles x 3 circles (half
+moving), warm-started (U and the Philox counter carry over between steps).
+The scene is staged in HBM before the timed region (``mppi_set_scene``) and
+every timed step is ``mppi_step_resident``.
+
+Prints one JSON line: throughput in rollout-steps/s (K*T per iteration over
+the HIP-event time of the timed region), the roofline of the fused iteration
+kernel (algorithmic FP32 flops per launch over its HIP-event duration), the
+plain one-at-a-time replan latency percentiles, the host-buffer (PCIe
+inclusive) rate, and the FP64 CPU oracle timed on the host on a bounded
+sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 20]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
+METRIC = "rollout-steps/s (K=8192,T=100) + p99 replan latency, served vs plain MPPI"
+KERNEL_SRC = os.path.join(ROOT, "paper_2308_01654_amd", "csrc", "mppi_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_iteration_c1.json")
+
+
+def flops_per_rollout_step(n_wp, n_c, n_ego):
+    """Algorithmic FP32 flops of one rollout step (FMA = 2, transcendental = 1):
+    73 for noise, noise check, dynamics, speed/effort/obstacle post-processing
+    and the compensated sum; 6 per waypoint; 7 per ego-circle x obstacle-circle
+    pair."""
+    return 73 + 6 * n_wp + 7 * n_ego * n_c
+
+
+class HipEvents:
+    """hipEvent timing on a given stream through the HIP runtime the library
+    itself links (found in this process's memory map)."""
+
+    def __init__(self):
+        paths = [l.split()[-1] for l in open("/proc/self/maps") if "libamdhip64" in l]
+        if not paths:
+            raise RuntimeError("HIP runtime not loaded")
+        H = ctypes.CDLL(paths[0])
+        vp = ctypes.c_void_p
+        H.hipEventCreate.argtypes = [ctypes.POINTER(vp)]
+        H.hipEventRecord.argtypes = [vp, vp]
+        H.hipEventSynchronize.argtypes = [vp]
+        H.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), vp, vp]
+        H.hipEventDestroy.argtypes = [vp]
+        self.H = H
+
+    def event(self):
+        e = ctypes.c_void_p()
+        assert self.H.hipEventCreate(ctypes.byref(e)) == 0
+        return e
+
+    def record(self, e, stream):
+        assert self.H.hipEventRecord(e, ctypes.c_void_p(stream)) == 0
+
+    def elapsed_ms(self, a, b):
+        assert self.H.hipEventSynchronize(b) == 0
+        ms = ctypes.c_float()
+        assert self.H.hipEventElapsedTime(ctypes.byref(ms), a, b) == 0
+        return float(ms.value)
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic(n_launch_units):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(sc, seconds):
+    """The FP64 oracle, unchanged, on the host cores: full iterations of the
+    same workload, repeated until `seconds` have passed (at least one)."""
+    from oracle import oracle as O
+    p = sc["params"]
+    U = np.zeros((p["T"], 2))
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        U = O.iteration(p, sc["x0"], sc["waypoints"], sc["circles"], U, n_iter=n)["U"]
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return dict(value=p["K"] * p["T"] * n / el, unit="rollout-steps/s", cores=O.max_threads(),
+                kind="oracle",
+                sample="%d warm-started FP64 oracle iteration(s) of the K=%d, T=%d sine-lane "
+                       "instance in %.1f s" % (n, p["K"], p["T"], el))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per sample (0 = library choice)")
+    ap.add_argument("--latency-iters", type=int, default=200)
+    args = ap.parse_args(argv)
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs the iteration on a single "
+              "MI355X (--gpus 1); multi-GPU runs are not part of it.", file=sys.stderr)
+        return 2
+
+    from paper_2308_01654_amd import mppi, scenes
+    sc = scenes.c1()
+    p = sc["params"]
+    K, T = p["K"], p["T"]
+    n_wp, n_c, n_ego = len(sc["waypoints"]), len(sc["circles"]), len(p["ego_off"])
+    x0, wp, circ = sc["x0"], sc["waypoints"], sc["circles"]
+
+    pl = mppi.Planner(p, lanes=args.lanes)
+    ev = HipEvents()
+    stream = pl.stream()
+    pl.set_scene(x0, wp, circ)
+    for _ in range(args.warmup):
+        pl.step_resident(x0)
+    pl.sync()
+
+    # ---- timed region: inputs resident in HBM, one iteration per step ----
+    pl.set_profiling(True)
+    e0, e1 = ev.event(), ev.event()
+    ev.record(e0, stream)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pl.step_resident(x0)
+    ev.record(e1, stream)
+    pl.sync()
+    t1 = time.perf_counter()
+    prof = pl.profile()
+    pl.set_profiling(False)
+    ms = ev.elapsed_ms(e0, e1)
+    ms_per_step = ms / args.steps
+    value = K * T * args.steps / (ms * 1e-3)
+    st = pl.stats()
+
+    kern_ms = prof["iter_ms"] / max(prof["iter_launches"], 1)
+    F = flops_per_rollout_step(n_wp, n_c, n_ego)
+    achieved = F * K * T / (kern_ms * 1e-3) / 1e12
+    roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS,
+                    unit="TFLOP/s", frac=round(achieved / PEAK_FP32_TFLOPS, 4),
+                    traffic=load_traffic(K * T),
+                    kernel="k_iteration (fused sample/rollout/cost/weight/update)",
+                    kernel_ms=round(kern_ms, 5), flops_per_rollout_step=F,
+                    lanes_per_sample=st["lanes"])
+
+    # ---- plain one-at-a-time replan latency (host call to controls on host) ----
+    lat = []
+    for _ in range(args.latency_iters):
+        a = time.perf_counter()
+        pl.step_resident(x0)
+        pl.controls()
+        lat.append((time.perf_counter() - a) * 1e3)
+    lat = np.array(lat)
+    # ---- host-buffer rate: scene converted and copied on every step ----
+    pl.sync()
+    a = time.perf_counter()
+    for _ in range(50):
+        pl.step(x0, wp, circ)
+    pl.sync()
+    pcie_value = K * T * 50 / (time.perf_counter() - a)
+    pl.close()
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "rollout-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sine-lane single instance, K=8192, T=100, dt=0.05, 221 waypoints, "
+                               "20 obstacles x 3 circles (10 moving), 3 ego circles, warm-started",
+                   "K": K, "T": T, "n_waypoints": n_wp, "n_circles": n_c},
+        "roofline": roofline,
+        "latency_ms": {"plain_p50": round(float(np.percentile(lat, 50)), 4),
+                       "plain_p99": round(float(np.percentile(lat, 99)), 4),
+                       "plain_p999": round(float(np.percentile(lat, 99.9)), 4)},
+        "wall_s_timed": round(t1 - t0, 4),
+        "host_staged_value": round(pcie_value, 1),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

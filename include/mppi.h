@@ -1,0 +1,212 @@
+/*
+ * mppi.h -- C ABI of an MI355X (gfx950) library that runs the sampling-based
+ * motion planner of Testouri, Elghazaly and Frank, "Towards a Safe Real-Time
+ * Motion Planning Framework for Autonomous Driving Systems: A Model
+ * Predictive Path Integral Approach" (arXiv 2308.01654).
+ *
+ * One call of mppi_step is one MPPI iteration (Algorithm 1, from the noise
+ * generation through the input update):
+ *   - draw K perturbation sequences eps_k in R^{T x 2} (Philox4x32-10 +
+ *     Box-Muller, counter = (k, t/2, n_lo, n_hi), key = seed);
+ *   - apply the noise check of Sec. III-A (clamp into [u_min, u_max], cap the
+ *     acceleration so that v never exceeds v_max, braking bound last);
+ *   - roll out the kinematic bicycle of eq. (5) (state x, y, yaw, v; controls
+ *     acceleration and steering angle; explicit Euler) for T steps;
+ *   - accumulate the Sec. III input cost and the Sec. IV-C state costs on
+ *     every new state: tracking (squared distance to the closest waypoint),
+ *     speed (against that waypoint's reference speed) and the obstacle cost
+ *     over circle-approximated obstacles with the safety distance
+ *     d_safe = d_safe_c v + d_safe_0;
+ *   - weights w_k = exp(-(S_k - S_min)/lambda) / sum_j exp(-(S_j - S_min)/lambda)
+ *     and the update U_t += sum_k w_k eps_eff[k][t] (eq. (update-input)).
+ * The problem tuple P = <V, S, B, J> of Sec. II-A maps onto the two structs:
+ * mppi_config holds the vehicle model V, the objective J and the sampling
+ * parameters; mppi_scene holds the scene S (obstacle circles) and the road
+ * boundary B (reference waypoints).
+ *
+ * Conventions for every function:
+ *   - Return value: MPPI_OK (0) or a negative mppi_status.  On error the
+ *     handle's controls U, iteration counter n and stored results are left
+ *     unchanged, and mppi_last_error() describes the failure.
+ *   - Pointers are host pointers unless stated otherwise.  Every input array
+ *     is copied before the call returns; the caller keeps ownership and may
+ *     free or reuse it at once.  Outputs go into caller buffers whose length
+ *     (in elements) is passed explicitly; a buffer that is too small gives
+ *     MPPI_E_INVALID and nothing is written.
+ *   - The library owns all device memory and releases it in mppi_destroy.
+ *   - Work is enqueued on the handle's HIP stream; calls that return data to
+ *     the host synchronize that stream.  A device failure is sticky
+ *     (MPPI_E_DEVICE) and makes the handle unusable.
+ *   - A handle is not thread-safe; distinct handles may be used from distinct
+ *     threads.  No C++ exception crosses this interface.
+ *   - Arrays are row-major, float64 unless stated otherwise.
+ */
+#ifndef MPPI_H
+#define MPPI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mppi_status;
+#define MPPI_OK            0
+#define MPPI_E_INVALID   (-1) /* bad argument, size or value                     */
+#define MPPI_E_NOMEM     (-2) /* device or host allocation failed                */
+#define MPPI_E_DEVICE    (-3) /* HIP runtime / kernel failure (sticky)           */
+#define MPPI_E_NONFINITE (-4) /* every sample cost was non-finite; U unchanged   */
+#define MPPI_E_BUSY      (-5) /* reserved for queue-capacity refusals            */
+#define MPPI_E_NOT_READY (-6) /* result not available yet                        */
+
+/* Vehicle model, objective and sampling parameters (Sec. II-A, Sec. III,
+ * Sec. IV-C, Table I).  Bounds may be +-INFINITY to disable them. */
+typedef struct mppi_config {
+    int32_t K;             /* samples per iteration (Alg. 1: M), 1..2^24              */
+    int32_t T;             /* horizon steps, 1..2048                                   */
+    double dt;             /* step length [s], > 0                                     */
+    double wheelbase;      /* l of eq. (5) [m], > 0                                    */
+    double lambda;         /* temperature of the weights, > 0                          */
+    double gamma;          /* alpha = (gamma-1)/(2 gamma) of the input cost, > 0        */
+    double sigma[2];       /* noise std dev of (acceleration, steering), >= 0           */
+    double u_min[2];       /* lower bounds (a_min, delta_min)                           */
+    double u_max[2];       /* upper bounds (a_max, delta_max)                           */
+    double v_max;          /* speed cap of the noise check (target speed v_G)          */
+    double w_track;        /* weight of c_dist                                          */
+    double w_speed;        /* weight of c_speed                                         */
+    double w_effort;       /* R = w_effort * I of the input cost                        */
+    double w_coll;         /* weight of the obstacle cost c_safe_dist                   */
+    double d_safe_c;       /* safe-distance coefficient [s]                             */
+    double d_safe_0;       /* minimal safe distance [m]                                 */
+    int32_t n_ego;         /* ego circles, 0..4                                         */
+    double ego_r;          /* radius of every ego circle [m]                            */
+    double ego_off[4];     /* ego circle centres along the heading from (x, y) [m]      */
+    uint64_t seed;         /* Philox key                                                */
+    int32_t max_waypoints; /* capacity for mppi_scene.n_waypoints, 1..2048              */
+    int32_t max_circles;   /* capacity for mppi_scene.n_circles, 0..1024                */
+} mppi_config;
+
+/* Scene and road model of one request, world coordinates. */
+typedef struct mppi_scene {
+    const double* waypoints; /* [n_waypoints][4]: x, y, yaw, v_ref                    */
+    int32_t n_waypoints;     /* 1..max_waypoints                                        */
+    const double* circles;   /* [n_circles][5]: x, y, r, vx, vy at request time;
+                                the centre moves at (vx, vy); may be NULL if n == 0   */
+    int32_t n_circles;       /* 0..max_circles                                          */
+} mppi_scene;
+
+typedef struct mppi mppi_t;
+
+/* Per-iteration summary of the last completed step. */
+typedef struct mppi_iter_stats {
+    double s_min;      /* S_min of Alg. 1                                           */
+    double log_z;      /* log sum_k exp(-(S_k - S_min)/lambda)                      */
+    double ess;        /* effective sample size 1 / sum_k w_k^2                     */
+    uint64_t n_iter;   /* iteration counter after the step                          */
+    int32_t status;    /* MPPI_OK or MPPI_E_NONFINITE of the last step              */
+    int32_t lanes_per_sample; /* launch shape used by the last step                */
+} mppi_iter_stats;
+
+/* Accumulated device time per kernel while profiling is on (HIP events). */
+typedef struct mppi_profile {
+    double iter_ms;        /* fused sample/rollout/weight/update kernel               */
+    int64_t iter_launches;
+    double aux_ms;         /* every other kernel of the handle                        */
+    int64_t aux_launches;
+} mppi_profile;
+
+/* ---- single planning instance -------------------------------------------- */
+
+/* Create a planning instance.  hip_stream: a hipStream_t of the caller (work
+ * is enqueued on it) or NULL to let the library create its own.  U starts at
+ * zero and the iteration counter n at 0.  Allocates device memory for
+ * K x T perturbations (8 bytes each) plus the scene capacity. */
+mppi_status mppi_create(const mppi_config* cfg, void* hip_stream, mppi_t** out);
+
+/* Release every resource of the handle (synchronizes its stream).  NULL is a
+ * no-op. */
+mppi_status mppi_destroy(mppi_t* h);
+
+/* One MPPI iteration (Alg. 1, noise generation through input update) from
+ * state x0 = (x, y, yaw, v) in the given scene.  Asynchronous: returns after
+ * the work is enqueued.  Uses and then increments the handle's iteration
+ * counter n (the Philox counter); a step whose every sample cost is
+ * non-finite leaves U and n unchanged and is reported by the next
+ * synchronizing call as MPPI_E_NONFINITE. */
+mppi_status mppi_step(mppi_t* h, const double x0[4], const mppi_scene* scene);
+
+/* Stage a scene on the device (the first half of mppi_step): validates it,
+ * converts it to float32 coordinates relative to origin = (x, y) of the given
+ * state (the ego frame) and enqueues the host-to-device copy.  The scene then
+ * stays resident until the next mppi_set_scene / mppi_step. */
+mppi_status mppi_set_scene(mppi_t* h, const double x0[4], const mppi_scene* scene);
+
+/* One MPPI iteration from state x0 (world coordinates) on the resident scene
+ * (the second half of mppi_step); no host-to-device traffic besides the
+ * kernel arguments.  MPPI_E_INVALID if no scene has been set. */
+mppi_status mppi_step_resident(mppi_t* h, const double x0[4]);
+
+/* Wait for the handle's stream; returns the status of the last step. */
+mppi_status mppi_sync(mppi_t* h);
+
+/* Copy U (the nominal controls, [T][2] = (a, delta)) into out; n >= 2T.
+ * Synchronizes; returns the status of the last step. */
+mppi_status mppi_get_controls(mppi_t* h, double* out, size_t n);
+
+/* Replace U ([T][2], n >= 2T, finite). */
+mppi_status mppi_set_controls(mppi_t* h, const double* U, size_t n);
+
+/* Receding-horizon warm start (Alg. 1, shift of the input sequence):
+ * U_t <- U_{t+steps} for t < T - steps, the remaining entries repeat the last
+ * control.  0 <= steps. */
+mppi_status mppi_shift(mppi_t* h, int32_t steps);
+
+/* Checkpoint: U ([T][2], n >= 2T), iteration counter and seed. */
+mppi_status mppi_get_state(mppi_t* h, double* U, size_t n, uint64_t* n_iter, uint64_t* seed);
+/* Restore a checkpoint; the Philox stream continues bit-identically. */
+mppi_status mppi_set_state(mppi_t* h, const double* U, size_t n, uint64_t n_iter);
+
+/* Results of the last step (synchronize).  Costs S_k as float32 [K];
+ * normalised weights as float64 [K]; applied perturbations eps_eff as
+ * float32 [T][K][2]; summary statistics. */
+mppi_status mppi_get_costs(mppi_t* h, float* out, size_t n);
+mppi_status mppi_get_weights(mppi_t* h, double* out, size_t n);
+mppi_status mppi_get_noise(mppi_t* h, float* out, size_t n);
+mppi_status mppi_get_iter_stats(mppi_t* h, mppi_iter_stats* out);
+
+/* Launch shape: lanes cooperating on one sample (1, 2, 4, 8 or 16), or 0 to
+ * let the library pick from its tuning table. */
+mppi_status mppi_set_lanes_per_sample(mppi_t* h, int32_t lanes);
+
+/* The HIP stream the handle enqueues on (as void*). */
+mppi_status mppi_get_stream(mppi_t* h, void** stream);
+
+/* Profiling: when on, every kernel of the handle is bracketed by HIP events
+ * and its device time is accumulated; mppi_get_profile synchronizes and
+ * returns the totals since the last reset (on = 1 resets them). */
+mppi_status mppi_set_profiling(mppi_t* h, int32_t on);
+mppi_status mppi_get_profile(mppi_t* h, mppi_profile* out);
+
+/* ---- Philox words as the rollout consumes them ---------------------------- */
+
+/* Philox4x32-10 (Salmon et al., SC'11) of counters (k, j, n_lo, n_hi) for
+ * k in [k0, k0+nk), j in [j0, j0+nj) under key = seed, computed on the
+ * device by the same function the rollout uses.  out: [nk][nj][4] uint32,
+ * n >= 4 nk nj.  Synchronous. */
+mppi_status mppi_debug_philox(uint64_t seed, uint64_t n_iter, uint32_t k0, uint32_t nk,
+                              uint32_t j0, uint32_t nj, uint32_t* out, size_t n);
+
+/* ---- diagnostics ---------------------------------------------------------- */
+
+const char* mppi_status_str(mppi_status s);
+/* Message of the last failure on the calling thread ("" if none). */
+const char* mppi_last_error(void);
+/* Library version string. */
+const char* mppi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPPI_H */

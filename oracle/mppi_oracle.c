@@ -60,6 +60,7 @@
  * Build: gcc -O2 -fopenmp -shared -fPIC -o liboracle.so mppi_oracle.c -lm
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -79,6 +80,9 @@ typedef struct orc_cfg {
 } orc_cfg;
 
 enum { ORC_OK = 0, ORC_E_INVALID = -1, ORC_E_NONFINITE = -4 };
+
+/* Threads the parallel loops of this oracle use. */
+int orc_max_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------
  * Philox4x32-10 (Salmon et al., SC'11, Section 4.2 / Table 2 constants).
@@ -104,6 +108,13 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
         k0 += PH_W0; k1 += PH_W1;
     }
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Philox of n counters ctr[n][4] under one key; out[n][4]. */
+void orc_philox_batch(const uint32_t* ctr, int64_t n, const uint32_t key[2], uint32_t* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) orc_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
 }
 
 /* The two 32-bit words that drive step t of sample k at iteration n. */
@@ -280,6 +291,52 @@ int orc_rollout(const orc_cfg* c, const double x0[4], const double* wp, int n_wp
             memcpy(x, xn, sizeof x);
         }
         S_out[k] = S;
+    }
+    return ORC_OK;
+}
+
+/*
+ * Rollouts of the selected samples ks[0..nk) only (their noise is the noise
+ * of those sample indices in the full iteration).  eps_in / eps_out are
+ * [T][nk][2]; S_out is [nk].  Used for sampled checks of large iterations.
+ */
+int orc_rollout_samples(const orc_cfg* c, const double x0[4], const double* wp, int n_wp,
+                        const double* circ, int n_c, const double* U, uint64_t n_iter,
+                        const int32_t* ks, int nk, const double* eps_in, double* S_out,
+                        double* eps_out)
+{
+    if (!cfg_ok(c, n_wp, n_c) || nk < 0) return ORC_E_INVALID;
+    const int T = c->T;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < nk; ++i) {
+        const int k = ks[i];
+        double x[4] = { x0[0], x0[1], x0[2], x0[3] };
+        double S = 0.0;
+        for (int t = 0; t < T; ++t) {
+            const double* Ut = U + 2 * t;
+            double e[2], u[2];
+            if (eps_in) {
+                e[0] = eps_in[((size_t)t * nk + i) * 2 + 0];
+                e[1] = eps_in[((size_t)t * nk + i) * 2 + 1];
+                u[0] = Ut[0] + e[0];
+                u[1] = Ut[1] + e[1];
+            } else {
+                double raw[2];
+                orc_noise(c, n_iter, k, t, raw);
+                orc_apply_limits(c, Ut, raw, x[3], u);
+                e[0] = u[0] - Ut[0];
+                e[1] = u[1] - Ut[1];
+            }
+            if (eps_out) {
+                eps_out[((size_t)t * nk + i) * 2 + 0] = e[0];
+                eps_out[((size_t)t * nk + i) * 2 + 1] = e[1];
+            }
+            double xn[4];
+            orc_dynamics(c, x, u, xn);
+            S += orc_stage_cost(c, wp, n_wp, circ, n_c, xn, Ut, e, t, NULL);
+            memcpy(x, xn, sizeof x);
+        }
+        S_out[i] = S;
     }
     return ORC_OK;
 }

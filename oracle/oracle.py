@@ -66,6 +66,8 @@ def lib():
             cp = ctypes.POINTER(OrcCfg)
             u32p = ctypes.POINTER(ctypes.c_uint32)
             L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+            L.orc_max_threads.restype = ctypes.c_int
+            L.orc_philox_batch.argtypes = [u32p, ctypes.c_int64, u32p, u32p]
             L.orc_uniform.argtypes = [ctypes.c_uint32]
             L.orc_uniform.restype = ctypes.c_double
             L.orc_box_muller.argtypes = [ctypes.c_double, ctypes.c_double, dp]
@@ -77,6 +79,9 @@ def lib():
             L.orc_stage_cost.restype = ctypes.c_double
             L.orc_rollout.argtypes = [cp, dp, dp, ctypes.c_int, dp, ctypes.c_int, dp,
                                       ctypes.c_uint64, dp, dp, dp]
+            L.orc_rollout_samples.argtypes = [cp, dp, dp, ctypes.c_int, dp, ctypes.c_int, dp,
+                                              ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.c_int, dp, dp, dp]
             L.orc_simulate.argtypes = [cp, dp, dp, ctypes.c_int, dp, ctypes.c_int, dp, dp,
                                        dp, dp, dp]
             L.orc_weights.argtypes = [dp, ctypes.c_int, ctypes.c_double, dp, dp, dp]
@@ -128,6 +133,20 @@ def philox(ctr, key):
     o = (ctypes.c_uint32 * 4)()
     lib().orc_philox4x32_10(c, k, o)
     return [int(v) for v in o]
+
+
+def philox_batch(ctrs, key):
+    """Philox of many counters: ctrs uint32 [n][4] -> uint32 [n][4]."""
+    c = np.ascontiguousarray(np.asarray(ctrs, dtype=np.uint32).reshape(-1, 4))
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    out = np.zeros_like(c)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    lib().orc_philox_batch(c.ctypes.data_as(u32p), c.shape[0], k, out.ctypes.data_as(u32p))
+    return out
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
 
 
 def uniform(r: int) -> float:
@@ -211,6 +230,28 @@ def rollout(p, x0, waypoints, circles, U, n_iter=0, eps_in=None):
                            _dp(U), int(n_iter), _dp(ein), _dp(S), _dp(eps))
     if rc != OK:
         raise ValueError("orc_rollout: status %d" % rc)
+    return S, eps
+
+
+def rollout_samples(p, x0, waypoints, circles, U, ks, n_iter=0, eps_in=None):
+    """Rollouts of the sample indices ``ks`` only.  Returns (S [nk], eps [T][nk][2])."""
+    c = make_cfg(p)
+    T = c.T
+    ks = np.ascontiguousarray(np.asarray(ks, dtype=np.int32))
+    nk = ks.shape[0]
+    wp = _f64(waypoints, (-1, 4))
+    ci = _f64(circles, (-1, 5)) if len(circles) else np.zeros((0, 5))
+    U = _f64(U, (T, 2))
+    x0 = _f64(x0)
+    ein = None if eps_in is None else _f64(eps_in, (T, nk, 2))
+    S = np.zeros(nk)
+    eps = np.zeros((T, nk, 2))
+    rc = lib().orc_rollout_samples(ctypes.byref(c), _dp(x0), _dp(wp), wp.shape[0], _dp(ci),
+                                   ci.shape[0], _dp(U), int(n_iter),
+                                   ks.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), nk,
+                                   _dp(ein), _dp(S), _dp(eps))
+    if rc != OK:
+        raise ValueError("orc_rollout_samples: status %d" % rc)
     return S, eps
 
 

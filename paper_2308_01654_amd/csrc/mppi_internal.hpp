@@ -1,0 +1,94 @@
+// Internal definitions shared by the HIP kernels and the host runtime of the
+// MPPI library.  Nothing here is part of the public C ABI (include/mppi.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mppi_impl {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wave64)
+constexpr int kMaxEgo = 4;
+constexpr int kMaxT = 2048;
+constexpr int kMaxWaypoints = 2048;
+constexpr int kMaxCircles = 1024;
+constexpr int kMaxK = 1 << 24;
+
+// Per-instance state that stays resident on the device between iterations.
+struct DevState {
+    unsigned long long n_iter;  // Philox counter words 2-3: iteration number
+    unsigned int ticket;        // tiles finished in the running iteration
+    int status;                 // 0 or MPPI_E_NONFINITE of the last iteration
+    double s_min;               // min_k S_k
+    double z;                   // sum_k exp(-(S_k - s_min)/lambda)
+    double log_z;
+    double ess;                 // z^2 / sum_k exp(-2 (S_k - s_min)/lambda)
+};
+
+// Partial results of one tile of samples: tile minimum, shifted exponential
+// sums and the shifted weighted perturbation sums for every (t, control).
+//   [0] m_b  [1] Z_b  [2] Q_b (sum of squares)  [3] unused  [4 + 2t + d] N_b
+constexpr int kPartialHead = 4;
+
+// Everything one launch needs to run one MPPI iteration of one instance.
+// Scene arrays are in the ego frame (x0's position subtracted) and float32.
+struct InstDesc {
+    int K, T, n_wp, n_c;
+    int lanes;            // lanes per sample (G)
+    int n_tiles;          // ceil(K / (kBlock / lanes))
+    float dt, inv_dt, inv_L;
+    float sig_a, sig_d;
+    float a_min, a_max, d_min, d_max, v_max;
+    float w_track, w_speed, w_effort, alpha, w_coll;
+    float d_safe_c, d_safe_0;
+    float ego_off[kMaxEgo];
+    int n_ego;
+    float px0, py0;       // initial position relative to the scene origin
+    float th0, v0;        // initial yaw and speed
+    double lambda;
+    uint32_t key0, key1;  // Philox key = seed
+    // device pointers
+    const float2* wp_xy;  // [n_wp]
+    const float* wp_vref; // [n_wp]
+    const float4* c_pv;   // [n_c] (x, y, vx, vy)
+    const float* c_rr;    // [n_c] r_c + r_ego
+    double* U;            // [T][2]
+    float* S;             // [K]
+    float2* eps;          // [T][K]
+    double* partials;     // [n_tiles][kPartialHead + 2T]
+    double* scales;       // [n_tiles] scratch of the combining tile
+    DevState* st;
+};
+
+// Dynamic LDS layout of the iteration kernel for a given scene size.
+struct LdsLayout {
+    size_t c_pv, wp_xy, U, red, wp_vref, c_rr, omega, total;
+};
+
+inline __host__ __device__ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int spb)
+{
+    LdsLayout L;
+    size_t o = 0;
+    L.c_pv = o;    o += (size_t)n_c * 16;
+    L.wp_xy = o;   o += (size_t)n_wp * 8;
+    L.U = o;       o += (size_t)T * 8;
+    L.red = o;     o += 64 * 8;           // block reduction scratch (doubles)
+    L.wp_vref = o; o += (size_t)n_wp * 4;
+    L.c_rr = o;    o += (size_t)n_c * 4;
+    L.omega = o;   o += (size_t)spb * 4;
+    L.total = align_up(o, 16);
+    return L;
+}
+
+// Launchers (mppi_kernels.hip).  All enqueue on `stream` and return the
+// launch error, if any.
+hipError_t launch_iteration(const InstDesc& d, hipStream_t stream);
+hipError_t launch_weights(const InstDesc& d, double* w_out, hipStream_t stream);
+hipError_t launch_shift(double* U, int T, int steps, hipStream_t stream);
+hipError_t launch_debug_philox(uint32_t key0, uint32_t key1, unsigned long long n_iter,
+                               uint32_t k0, uint32_t nk, uint32_t j0, uint32_t nj,
+                               uint32_t* out, hipStream_t stream);
+
+}  // namespace mppi_impl

@@ -1,0 +1,460 @@
+// HIP kernels (gfx950 / CDNA4) for one MPPI iteration of the planner of
+// arXiv 2308.01654 (Algorithm 1, noise generation through the input update,
+// with the costs of Sec. III and Sec. IV-C).
+//
+// One fused kernel runs the whole iteration.  A workgroup owns a tile of
+// samples; G lanes ("lanes per sample", 1..16) cooperate on one sample:
+//
+//   phase 1  rollout.  The horizon is walked in blocks of G steps.  Lane r of
+//            a group draws the Philox/Box-Muller perturbation of step t0+r,
+//            the G perturbations are exchanged inside the group, and every
+//            lane advances the (cheap) bicycle recursion of all G steps,
+//            keeping the state reached at its own step.  Each lane then
+//            evaluates the (expensive) stage cost of its own step: the
+//            waypoint scan and the ego-circle x obstacle-circle distances,
+//            with the scene staged in LDS and read as wave-uniform
+//            broadcasts.  Costs are Kahan-summed per lane and combined per
+//            sample in float64.  Applied perturbations are stored time-major
+//            [T][K] as float2.
+//   phase 2  tile partials.  Tile minimum m_b, then (float64)
+//            omega_i = exp(-(S_i - m_b)/lambda), Z_b = sum omega_i and, for
+//            every (t, control) column, a Kahan-compensated float32 sum of
+//            omega_i * eps_eff[t][i] over the tile (re-read while L2-hot).
+//   phase 3  combine.  The last tile to finish (agent-scope ticket) merges
+//            the tile partials in tile order with the rescale
+//            exp(-(m_b - m)/lambda), and updates U in float64:
+//            U_t += N_t / Z (eq. (update-input)).  It bumps the iteration
+//            counter and records S_min, log Z and the effective sample size.
+//
+// The tile order of the combine is fixed, so results do not depend on which
+// workgroup finishes first.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "mppi_internal.hpp"
+
+namespace mppi_impl {
+
+// ----------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
+// 4x32 S-box (two 32x32->64 multiplies, xor with the other half and the key)
+// with a Weyl-sequence key schedule.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+                       (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Gaussian perturbation (before the noise check) of step t of sample k at
+// iteration n: counter (k, t/2, n_lo, n_hi); words (r0, r1) for even t and
+// (r2, r3) for odd t; u = ((r >> 9) + 1/2) 2^-23 is exact in float32;
+// Box-Muller with the angle taken in revolutions by the hardware sin/cos.
+__device__ __forceinline__ float2 draw_noise(const InstDesc& d, int k, int t,
+                                             unsigned long long n)
+{
+    const uint4 r = philox4x32_10(make_uint4((uint32_t)k, (uint32_t)(t >> 1), (uint32_t)n,
+                                             (uint32_t)(n >> 32)),
+                                  d.key0, d.key1);
+    const uint32_t ra = (t & 1) ? r.z : r.x;
+    const uint32_t rb = (t & 1) ? r.w : r.y;
+    const float u1 = ((float)(ra >> 9) + 0.5f) * 0x1p-23f;
+    const float u2 = ((float)(rb >> 9) + 0.5f) * 0x1p-23f;
+    // -2 ln u1 = -2 ln(2) log2(u1)
+    const float rho = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
+    return make_float2(d.sig_a * rho * __builtin_amdgcn_cosf(u2),
+                       d.sig_d * rho * __builtin_amdgcn_sinf(u2));
+}
+
+struct Lds {
+    float4* c_pv;
+    float2* wp_xy;
+    float2* U;
+    double* red;
+    float* wp_vref;
+    float* c_rr;
+    float* omega;
+};
+
+__device__ __forceinline__ Lds lds_bind(unsigned char* base, const LdsLayout& L)
+{
+    Lds s;
+    s.c_pv = reinterpret_cast<float4*>(base + L.c_pv);
+    s.wp_xy = reinterpret_cast<float2*>(base + L.wp_xy);
+    s.U = reinterpret_cast<float2*>(base + L.U);
+    s.red = reinterpret_cast<double*>(base + L.red);
+    s.wp_vref = reinterpret_cast<float*>(base + L.wp_vref);
+    s.c_rr = reinterpret_cast<float*>(base + L.c_rr);
+    s.omega = reinterpret_cast<float*>(base + L.omega);
+    return s;
+}
+
+// Stage cost on the state reached at step t (Sec. III input cost, Sec. IV-C
+// tracking, speed and obstacle costs).  Every lane of the wave runs the same
+// waypoint and circle loops, so the LDS reads are broadcasts.
+template <int NE>
+__device__ __forceinline__ float stage_cost(const InstDesc& d, const Lds& s, float x, float y,
+                                            float c, float sn, float v, float Ua, float Ud,
+                                            float ea, float ed, int t)
+{
+    // c_dist = min_j ||P - W_j||^2; reference speed of the closest waypoint
+    float best = INFINITY;
+    int bj = 0;
+    for (int j = 0; j < d.n_wp; ++j) {
+        const float2 w = s.wp_xy[j];
+        const float dx = x - w.x;
+        const float dy = y - w.y;
+        const float dd = fmaf(dy, dy, dx * dx);
+        if (dd < best) {
+            best = dd;
+            bj = j;
+        }
+    }
+    const float dv = v - s.wp_vref[bj];
+    // q_u = w_effort (alpha eps.eps + U.eps + U.U / 2)
+    const float q = d.w_effort * (d.alpha * fmaf(ea, ea, ed * ed) + fmaf(Ua, ea, Ud * ed) +
+                                  0.5f * fmaf(Ua, Ua, Ud * Ud));
+    float cost = fmaf(d.w_track, best, fmaf(d.w_speed, dv * dv, q));
+    if (NE > 0 && d.n_c > 0) {
+        float ex[NE > 0 ? NE : 1], ey[NE > 0 ? NE : 1];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            ex[e] = fmaf(d.ego_off[e], c, x);
+            ey[e] = fmaf(d.ego_off[e], sn, y);
+        }
+        const float tau = (float)(t + 1) * d.dt;
+        float d_obj = INFINITY;
+        for (int i = 0; i < d.n_c; ++i) {
+            const float4 p = s.c_pv[i];
+            const float rr = s.c_rr[i];
+            const float ox = fmaf(tau, p.z, p.x);
+            const float oy = fmaf(tau, p.w, p.y);
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+                const float dx = ex[e] - ox;
+                const float dy = ey[e] - oy;
+                d_obj = fminf(d_obj, __builtin_amdgcn_sqrtf(fmaf(dy, dy, dx * dx)) - rr);
+            }
+        }
+        const float g = fmaf(d.d_safe_c, v, d.d_safe_0) - d_obj;
+        const float c_safe = g > 0.0f ? g * g : 0.0f;
+        cost = fmaf(d.w_coll, c_safe, cost);
+    }
+    return cost;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Block-wide reductions over kBlock threads; every thread gets the result.
+// The combination order is fixed (xor tree inside a wave, waves in order).
+__device__ __forceinline__ double block_sum(double v, double* red)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int i = 1; i < kBlock / 64; ++i) r += red[i];
+    return r;
+}
+
+__device__ __forceinline__ double block_min(double v, double* red)
+{
+    v = wave_min(v);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int i = 1; i < kBlock / 64; ++i) r = fmin(r, red[i]);
+    return r;
+}
+
+template <int G, int NE>
+__device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
+{
+    const int tid = threadIdx.x;
+    constexpr int SPB = kBlock / G;  // samples per tile
+    const int T = d.T;
+    const int K = d.K;
+    const LdsLayout L = lds_layout(d.n_wp, d.n_c, T, SPB);
+    const Lds s = lds_bind(smem, L);
+
+    for (int i = tid; i < d.n_c; i += kBlock) {
+        s.c_pv[i] = d.c_pv[i];
+        s.c_rr[i] = d.c_rr[i];
+    }
+    for (int i = tid; i < d.n_wp; i += kBlock) {
+        s.wp_xy[i] = d.wp_xy[i];
+        s.wp_vref[i] = d.wp_vref[i];
+    }
+    for (int i = tid; i < T; i += kBlock)
+        s.U[i] = make_float2((float)d.U[2 * i], (float)d.U[2 * i + 1]);
+    const unsigned long long n_iter = d.st->n_iter;
+    __syncthreads();
+
+    // ---------------------------------------------------------------- phase 1
+    const int grp = tid / G;
+    const int r = tid % G;
+    const int k_base = tile * SPB;
+    const int k = k_base + grp;
+    const bool valid = k < K;
+    const int kk = valid ? k : K - 1;  // idle groups replay the last sample
+
+    float x = d.px0, y = d.py0, th = d.th0, v = d.v0;
+    float c = __cosf(th), sn = __sinf(th);
+    float S = 0.0f, comp = 0.0f;  // Kahan pair of this lane's steps
+    for (int t0 = 0; t0 < T; t0 += G) {
+        const int tm = t0 + r;
+        const float2 em = draw_noise(d, kk, tm < T ? tm : T - 1, n_iter);
+        float mx = 0.f, my = 0.f, mc = 1.f, ms = 0.f, mv = 0.f;
+        float mUa = 0.f, mUd = 0.f, mea = 0.f, med = 0.f;
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            const int t = t0 + i;
+            if (G > 1 && t >= T) continue;
+            float ea = em.x, ed = em.y;
+            if (G > 1) {
+                const int src = (tid & ~(G - 1)) + i;
+                ea = __shfl(em.x, src, 64);
+                ed = __shfl(em.y, src, 64);
+            }
+            const float2 Ut = s.U[t];
+            // noise check: bounds, speed cap, braking bound last
+            float a = fminf(fmaxf(Ut.x + ea, d.a_min), d.a_max);
+            a = fminf(a, (d.v_max - v) * d.inv_dt);
+            a = fmaxf(a, d.a_min);
+            const float dl = fminf(fmaxf(Ut.y + ed, d.d_min), d.d_max);
+            // eq. (5), explicit Euler from the old state
+            const float vdt = v * d.dt;
+            const float tn = __tanf(dl);
+            x = fmaf(vdt, c, x);
+            y = fmaf(vdt, sn, y);
+            th = fmaf(vdt * d.inv_L, tn, th);
+            v = fmaf(d.dt, a, v);
+            c = __cosf(th);
+            sn = __sinf(th);
+            if (i == r) {
+                mx = x; my = y; mc = c; ms = sn; mv = v;
+                mUa = Ut.x; mUd = Ut.y;
+                mea = a - Ut.x; med = dl - Ut.y;
+            }
+        }
+        if (tm < T) {
+            const float q = stage_cost<NE>(d, s, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm);
+            const float yk = q - comp;
+            const float tk = S + yk;
+            comp = (tk - S) - yk;
+            S = tk;
+            if (valid) d.eps[(size_t)tm * K + k] = make_float2(mea, med);
+        }
+    }
+
+    // per-sample total over the G lanes (float64)
+    double Sd = (double)S - (double)comp;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) Sd += __shfl_xor(Sd, o, 64);
+    float Sk = (float)Sd;
+    if (!valid || !isfinite(Sk)) Sk = INFINITY;
+    if (valid && r == 0) d.S[k] = (float)Sd;
+
+    // ---------------------------------------------------------------- phase 2
+    const double m_b = block_min((double)Sk, s.red);
+    double om = 0.0;
+    if (r == 0 && isfinite(m_b) && Sk < INFINITY) om = exp(-((double)Sk - m_b) / d.lambda);
+    if (r == 0) s.omega[grp] = (float)om;
+    const double z_b = block_sum(om, s.red);
+    const double q_b = block_sum(om * om, s.red);  // also orders omega stores
+    double* part = d.partials + (size_t)tile * (kPartialHead + 2 * T);
+    const int n_valid = min(SPB, K - k_base);
+    for (int col = tid; col < 2 * T; col += kBlock) {
+        const int t = col >> 1;
+        const float* e = reinterpret_cast<const float*>(d.eps + (size_t)t * K + k_base) + (col & 1);
+        float acc = 0.0f, cp = 0.0f;
+        for (int i = 0; i < n_valid; ++i) {
+            const float yk = s.omega[i] * e[2 * i] - cp;
+            const float tk = acc + yk;
+            cp = (tk - acc) - yk;
+            acc = tk;
+        }
+        part[kPartialHead + col] = (double)acc - (double)cp;
+    }
+    if (tid == 0) {
+        part[0] = m_b;
+        part[1] = z_b;
+        part[2] = q_b;
+        part[3] = 0.0;
+    }
+
+    // ---------------------------------------------------------------- phase 3
+    __threadfence();
+    __syncthreads();
+    unsigned int* flag = reinterpret_cast<unsigned int*>(s.red);
+    if (tid == 0) {
+        const unsigned int prev = __hip_atomic_fetch_add(&d.st->ticket, 1u, __ATOMIC_ACQ_REL,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+        flag[0] = (prev == (unsigned int)(d.n_tiles - 1)) ? 1u : 0u;
+    }
+    __syncthreads();
+    if (flag[0] == 0u) return;
+    __threadfence();
+
+    const int stride = kPartialHead + 2 * T;
+    double m = INFINITY;
+    for (int b = tid; b < d.n_tiles; b += kBlock) m = fmin(m, d.partials[(size_t)b * stride]);
+    m = block_min(m, s.red);
+    if (!isfinite(m)) {
+        if (tid == 0) {
+            d.st->status = -4;  // MPPI_E_NONFINITE: U and n stay unchanged
+            d.st->ticket = 0u;
+        }
+        return;
+    }
+    for (int b = tid; b < d.n_tiles; b += kBlock) {
+        const double mb = d.partials[(size_t)b * stride];
+        d.scales[b] = isfinite(mb) ? exp(-(mb - m) / d.lambda) : 0.0;
+    }
+    __threadfence_block();
+    __syncthreads();
+    double zl = 0.0, ql = 0.0;
+    for (int b = tid; b < d.n_tiles; b += kBlock) {
+        const double sc = d.scales[b];
+        zl += d.partials[(size_t)b * stride + 1] * sc;
+        ql += d.partials[(size_t)b * stride + 2] * sc * sc;
+    }
+    const double Z = block_sum(zl, s.red);
+    const double Q = block_sum(ql, s.red);
+    for (int col = tid; col < 2 * T; col += kBlock) {
+        double acc = 0.0;
+        for (int b = 0; b < d.n_tiles; ++b)
+            acc += d.partials[(size_t)b * stride + kPartialHead + col] * d.scales[b];
+        d.U[col] += acc / Z;
+    }
+    if (tid == 0) {
+        d.st->s_min = m;
+        d.st->z = Z;
+        d.st->log_z = log(Z);
+        d.st->ess = Z * Z / Q;
+        d.st->status = 0;
+        d.st->n_iter = n_iter + 1ull;
+        d.st->ticket = 0u;
+    }
+}
+
+template <int G, int NE>
+__global__ __launch_bounds__(kBlock) void k_iteration(InstDesc d)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    iteration_tile<G, NE>(d, blockIdx.x, smem);
+}
+
+template <int G>
+static hipError_t launch_g(const InstDesc& d, hipStream_t stream)
+{
+    const LdsLayout L = lds_layout(d.n_wp, d.n_c, d.T, kBlock / G);
+    const dim3 grid(d.n_tiles), block(kBlock);
+    switch (d.n_c > 0 ? d.n_ego : 0) {
+    case 0: hipLaunchKernelGGL((k_iteration<G, 0>), grid, block, L.total, stream, d); break;
+    case 1: hipLaunchKernelGGL((k_iteration<G, 1>), grid, block, L.total, stream, d); break;
+    case 2: hipLaunchKernelGGL((k_iteration<G, 2>), grid, block, L.total, stream, d); break;
+    case 3: hipLaunchKernelGGL((k_iteration<G, 3>), grid, block, L.total, stream, d); break;
+    default: hipLaunchKernelGGL((k_iteration<G, 4>), grid, block, L.total, stream, d); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_iteration(const InstDesc& d, hipStream_t stream)
+{
+    switch (d.lanes) {
+    case 1: return launch_g<1>(d, stream);
+    case 2: return launch_g<2>(d, stream);
+    case 4: return launch_g<4>(d, stream);
+    case 8: return launch_g<8>(d, stream);
+    case 16: return launch_g<16>(d, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Normalised weights of the last iteration: w_k = exp(-(S_k - S_min)/lambda)/Z.
+__global__ void k_weights(const float* __restrict__ S, int K, double lambda,
+                          const DevState* __restrict__ st, double* __restrict__ w)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const float sk = S[k];
+    w[k] = isfinite(sk) ? exp(-((double)sk - st->s_min) / lambda) / st->z : 0.0;
+}
+
+hipError_t launch_weights(const InstDesc& d, double* w_out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_weights, dim3((d.K + 255) / 256), dim3(256), 0, stream, d.S, d.K,
+                       d.lambda, d.st, w_out);
+    return hipGetLastError();
+}
+
+// Receding-horizon shift: U_t <- U_{min(t + steps, T-1)}.
+__global__ void k_shift(double* U, int T, int steps)
+{
+    extern __shared__ double buf[];
+    for (int i = threadIdx.x; i < 2 * T; i += blockDim.x) buf[i] = U[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * T; i += blockDim.x) {
+        const int t = min((i >> 1) + steps, T - 1);
+        U[i] = buf[2 * t + (i & 1)];
+    }
+}
+
+hipError_t launch_shift(double* U, int T, int steps, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_shift, dim3(1), dim3(256), (size_t)T * 2 * sizeof(double), stream, U,
+                       T, steps);
+    return hipGetLastError();
+}
+
+__global__ void k_debug_philox(uint32_t key0, uint32_t key1, unsigned long long n_iter,
+                               uint32_t k0, uint32_t nk, uint32_t j0, uint32_t nj, uint32_t* out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (uint64_t)nk * nj) return;
+    const uint32_t k = k0 + (uint32_t)(i / nj);
+    const uint32_t j = j0 + (uint32_t)(i % nj);
+    const uint4 r = philox4x32_10(make_uint4(k, j, (uint32_t)n_iter, (uint32_t)(n_iter >> 32)),
+                                  key0, key1);
+    reinterpret_cast<uint4*>(out)[i] = r;
+}
+
+hipError_t launch_debug_philox(uint32_t key0, uint32_t key1, unsigned long long n_iter,
+                               uint32_t k0, uint32_t nk, uint32_t j0, uint32_t nj,
+                               uint32_t* out, hipStream_t stream)
+{
+    const uint64_t n = (uint64_t)nk * nj;
+    hipLaunchKernelGGL(k_debug_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                       key0, key1, n_iter, k0, nk, j0, nj, out);
+    return hipGetLastError();
+}
+
+}  // namespace mppi_impl

@@ -1,0 +1,101 @@
+"""Staged parity gates between the HIP path and the FP64 oracle.
+
+Tolerances (stated for the floating-point outputs of one iteration):
+  * normalised weights: |w_gpu - w_ref| <= 1e-5 absolute, every sample;
+  * controls: |U_gpu - U_ref| <= 1e-4 * max(|U_ref|, sigma_d) per entry
+    (relative, floored at the noise scale of that control).
+Gates:
+  G0  Philox words bit-exact (debug export, same device function);
+  D1  applied perturbations vs the oracle's from the same Philox words (report);
+  D2  costs S vs the oracle rollout fed the GPU's applied perturbations;
+  G2  weights vs the oracle normaliser fed the GPU's costs;
+  G3  controls vs the oracle update fed the GPU's weights and perturbations
+      from the same previous controls.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import oracle as O
+
+W_TOL = 1e-5
+U_REL = 1e-4
+S_REL = 1e-3     # bound on the relative cost error of the float32 rollout (D2)
+EPS_ABS = 2e-3   # bound on |delta eps_eff| / sigma of the float32 sampler (D1)
+
+
+def u_tol(U_ref, sigma):
+    return U_REL * np.maximum(np.abs(U_ref), np.asarray(sigma, dtype=np.float64)[None, :])
+
+
+def gpu_step(planner, scene, x0=None):
+    """Run one GPU iteration and fetch every output."""
+    U_prev = planner.controls()
+    planner.step(scene["x0"] if x0 is None else x0, scene["waypoints"], scene["circles"])
+    planner.sync()
+    return dict(U_prev=U_prev, U=planner.controls(), S=planner.costs().astype(np.float64),
+                w=planner.weights(), eps=planner.noise().astype(np.float64),
+                stats=planner.stats())
+
+
+def staged(p, scene, g, n_iter, ks=None):
+    """Gates D1, D2, G2, G3 for one GPU iteration ``g`` (from gpu_step) at
+    iteration counter n_iter.  ks: optional sample subset for D1/D2."""
+    x0, wp, ci = scene["x0"], scene["waypoints"], scene["circles"]
+    sig = np.asarray(p["sigma"], dtype=np.float64)
+    rep = {}
+    if ks is None:
+        S_inj, _ = O.rollout(p, x0, wp, ci, g["U_prev"], n_iter=n_iter, eps_in=g["eps"])
+        S_orc, eps_orc = O.rollout(p, x0, wp, ci, g["U_prev"], n_iter=n_iter)
+        S_g, eps_g = g["S"], g["eps"]
+    else:
+        ks = np.asarray(ks)
+        S_inj, _ = O.rollout_samples(p, x0, wp, ci, g["U_prev"], ks, n_iter=n_iter,
+                                     eps_in=g["eps"][:, ks, :])
+        S_orc, eps_orc = O.rollout_samples(p, x0, wp, ci, g["U_prev"], ks, n_iter=n_iter)
+        S_g, eps_g = g["S"][ks], g["eps"][:, ks, :]
+    scale = np.where(sig > 0, sig, 1.0)
+    rep["D1_max_abs_over_sigma"] = float(np.max(np.abs(eps_g - eps_orc) / scale)) if eps_g.size else 0.0
+    rel = np.abs(S_g - S_inj) / np.maximum(np.abs(S_inj), 1e-30)
+    rep["D2_max_rel"] = float(np.max(rel))
+    rep["D2_p99_rel"] = float(np.percentile(rel, 99))
+    rep["beta"] = float(np.max(np.abs(S_g - S_orc)))
+    w_ref, smin, logz = O.weights(g["S"], p["lam"])
+    rep["G2_max_abs"] = float(np.max(np.abs(g["w"] - w_ref)))
+    U_ref = O.update(g["U_prev"], g["w"], g["eps"])
+    rep["G3_max_over_tol"] = float(np.max(np.abs(g["U"] - U_ref) / u_tol(U_ref, sig)))
+    rep["s_min"] = (g["stats"]["s_min"], smin)
+    rep["log_z"] = (g["stats"]["log_z"], logz)
+    rep["ess"] = g["stats"]["ess"]
+    return rep
+
+
+def assert_staged(rep):
+    assert rep["D1_max_abs_over_sigma"] <= EPS_ABS, rep
+    assert rep["D2_max_rel"] <= S_REL, rep
+    assert rep["G2_max_abs"] <= W_TOL, rep
+    assert rep["G3_max_over_tol"] <= 1.0, rep
+    assert abs(rep["s_min"][0] - rep["s_min"][1]) <= 1e-12 * max(1.0, abs(rep["s_min"][1])), rep
+    assert abs(rep["log_z"][0] - rep["log_z"][1]) <= 1e-9, rep
+
+
+def end_to_end(p, scene, g, n_iter):
+    """Fully independent oracle iteration vs the GPU iteration.  Returns the
+    report and whether the benchmark spec's tolerances hold; where they do not, the
+    report carries the cause (cost error beta against lambda and the top-2
+    cost gap of the oracle)."""
+    r = O.iteration(p, scene["x0"], scene["waypoints"], scene["circles"], g["U_prev"],
+                    n_iter=n_iter)
+    sig = np.asarray(p["sigma"], dtype=np.float64)
+    beta = float(np.max(np.abs(g["S"] - r["S"])))
+    srt = np.sort(r["S"])
+    gap = float(srt[1] - srt[0]) if srt.size > 1 else float("inf")
+    dw = float(np.max(np.abs(g["w"] - r["w"])))
+    du = float(np.max(np.abs(g["U"] - r["U"]) / u_tol(r["U"], sig)))
+    # first-order prediction of the weight error from the cost error
+    pred = float(np.max(2.0 * np.maximum(g["w"], r["w"]) * beta / p["lam"]))
+    rep = dict(beta=beta, lam=p["lam"], top2_gap=gap, w_max_abs=dw, U_max_over_tol=du,
+               predicted_w_bound=pred, ess_gpu=g["stats"]["ess"],
+               argmin_same=bool(np.argmin(g["S"]) == np.argmin(r["S"])))
+    ok = dw <= W_TOL and du <= 1.0
+    return rep, ok

@@ -1,0 +1,68 @@
+"""The C-ABI library loads on a machine without a GPU and exports every
+entry point that include/*.h declares; argument validation that needs no
+device works here too."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_2308_01654_amd import mppi, scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DECL = re.compile(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(mppi_[a-z0-9_]+)\s*\(",
+                  re.M)
+
+
+def declared_symbols():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        with open(h) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names.update(DECL.findall(text))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for n in ("mppi_create", "mppi_step", "mppi_get_controls", "mppi_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(mppi.LIB_PATH)
+    missing = [n for n in declared_symbols() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    bound = {name for name, _, _ in mppi.SIGNATURES}
+    assert set(declared_symbols()) <= bound | {n for n in declared_symbols() if n.startswith("mppi_server")}
+
+
+def test_version_and_status_strings():
+    L = mppi.load()
+    assert b"gfx950" in L.mppi_version()
+    assert L.mppi_status_str(mppi.E_NONFINITE) == b"all sample costs non-finite"
+    assert L.mppi_status_str(0) == b"ok"
+
+
+@pytest.mark.parametrize("field,value", [("K", 0), ("T", 0), ("T", 5000), ("dt", 0.0),
+                                         ("lam", -1.0), ("wheelbase", 0.0),
+                                         ("max_waypoints", 0), ("max_circles", -1)])
+def test_invalid_config_rejected_without_device(field, value):
+    cfg = mppi.config_from_params(scenes.c0()["params"])
+    setattr(cfg, field, value)
+    st, h = mppi.mppi_create(cfg)
+    assert st == mppi.E_INVALID
+    assert not h.value
+    assert mppi.load().mppi_last_error()
+
+
+def test_null_handle_calls_fail_cleanly():
+    L = mppi.load()
+    assert L.mppi_sync(None) == mppi.E_INVALID
+    assert L.mppi_destroy(None) == mppi.OK
+    assert L.mppi_step_resident(None, None) == mppi.E_INVALID

@@ -1,0 +1,271 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on MI355X.
+
+Every case prints its name before it runs.  Sizes: the plain single
+iteration (K=1024, T=50), ragged shapes that span several tiles with a
+partial last tile and a partial last block of steps, the sine-lane instance
+(K=8192, T=100, 10 warm-started iterations) and the stress instance
+(K=262144, T=200, 512 circles) at full size with sampled checks.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2308_01654_amd import scenes
+from tests import _parity as P
+
+pytestmark = pytest.mark.gpu
+
+OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+
+
+def _mppi():
+    from paper_2308_01654_amd import mppi
+    mppi.load()  # raises if the HIP library is not built
+    return mppi
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _dump(name, obj):
+    os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, "parity_%s.json" % name), "w") as f:
+        json.dump(obj, f, indent=1, default=float)
+
+
+def test_philox_words_bit_exact_full_stream_c0():
+    """G0: the device Philox (same function the rollout calls) equals the
+    oracle's for every counter of the plain iteration (K=1024, T=50 -> 25
+    counters per sample) at iterations 0 and 7."""
+    mppi = _mppi()
+    for n_iter in (0, 7, (3 << 32) + 5):
+        _say("philox c0 n_iter", n_iter)
+        got = mppi.mppi_debug_philox(0, n_iter, 0, 1024, 0, 25)
+        ctr = np.zeros((1024, 25, 4), dtype=np.uint32)
+        ctr[..., 0] = np.arange(1024)[:, None]
+        ctr[..., 1] = np.arange(25)[None, :]
+        ctr[..., 2] = n_iter & 0xFFFFFFFF
+        ctr[..., 3] = n_iter >> 32
+        ref = O.philox_batch(ctr.reshape(-1, 4), [0, 0]).reshape(1024, 25, 4)
+        assert np.array_equal(got, ref)
+
+
+def test_philox_words_sampled_large():
+    """G0 at the stress size: 2^20 counters (k < 262144, j < 100) bit-exact."""
+    mppi = _mppi()
+    seed = 0x0123456789ABCDEF
+    got = mppi.mppi_debug_philox(seed, 9, 262144 - 10486, 10486, 0, 100)
+    ctr = np.zeros((10486, 100, 4), dtype=np.uint32)
+    ctr[..., 0] = (262144 - 10486 + np.arange(10486))[:, None]
+    ctr[..., 1] = np.arange(100)[None, :]
+    ctr[..., 2] = 9
+    ref = O.philox_batch(ctr.reshape(-1, 4), [seed & 0xFFFFFFFF, seed >> 32]).reshape(got.shape)
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
+def test_c0_staged_parity_all_launch_shapes(lanes):
+    """Plain single iteration, every lanes-per-sample shape."""
+    mppi = _mppi()
+    sc = scenes.c0()
+    p = sc["params"]
+    _say("c0 lanes", lanes)
+    with mppi.Planner(p, lanes=lanes) as pl:
+        g = P.gpu_step(pl, sc)
+        assert g["stats"]["lanes"] == lanes
+        assert g["stats"]["n_iter"] == 1 and g["stats"]["status"] == 0
+        rep = P.staged(p, sc, g, n_iter=0)
+        _dump("c0_lanes%d" % lanes, rep)
+        P.assert_staged(rep)
+
+
+def test_c0_end_to_end():
+    mppi = _mppi()
+    sc = scenes.c0()
+    p = sc["params"]
+    with mppi.Planner(p) as pl:
+        g = P.gpu_step(pl, sc)
+    rep, ok = P.end_to_end(p, sc, g, 0)
+    _dump("c0_e2e", rep)
+    _say("c0 e2e", rep)
+    if not ok:
+        # the only admissible cause: a cost error that the weights amplify
+        # (beta/lambda) or a near-tie of the two best samples
+        assert rep["w_max_abs"] <= max(P.W_TOL, 1.5 * rep["predicted_w_bound"]) or \
+            rep["top2_gap"] <= 2 * rep["beta"], rep
+
+
+@pytest.mark.parametrize("K,T,n_c,lanes", [
+    (1000, 37, 7, 16), (1000, 37, 7, 1), (777, 13, 0, 4), (1, 5, 3, 0), (300, 1, 2, 8),
+    (4097, 64, 33, 2)])
+def test_ragged_shapes(K, T, n_c, lanes):
+    """Partial last tile, partial last block of steps, no circles, K = 1, T = 1."""
+    mppi = _mppi()
+    sc = scenes.tiny(K=K, T=T, n_c=n_c, seed=K + T)
+    p = sc["params"]
+    _say("ragged", K, T, n_c, lanes)
+    with mppi.Planner(p, lanes=lanes) as pl:
+        U0 = np.tile([0.1, -0.02], (T, 1))
+        pl.set_controls(U0)
+        g = P.gpu_step(pl, sc)
+        rep = P.staged(p, sc, g, n_iter=0)
+        P.assert_staged(rep)
+        if K == 1:
+            assert g["w"][0] == 1.0
+            assert np.allclose(g["U"], U0 + g["eps"][:, 0, :], rtol=0, atol=1e-12)
+
+
+def test_single_waypoint_and_unbounded_controls():
+    mppi = _mppi()
+    sc = scenes.tiny(K=512, T=20, n_c=4)
+    inf = float("inf")
+    p = dict(sc["params"], u_min=(-inf, -inf), u_max=(inf, inf), v_max=inf)
+    sc = dict(sc, params=p, waypoints=sc["waypoints"][5:6])
+    with mppi.Planner(p) as pl:
+        g = P.gpu_step(pl, sc)
+        P.assert_staged(P.staged(p, sc, g, n_iter=0))
+
+
+def test_zero_noise_gives_uniform_weights_and_no_update():
+    mppi = _mppi()
+    sc = scenes.tiny(K=2048, T=30, n_c=5)
+    p = dict(sc["params"], sigma=(0.0, 0.0))
+    with mppi.Planner(p) as pl:
+        U0 = np.tile([0.3, 0.01], (30, 1))
+        pl.set_controls(U0)
+        g = P.gpu_step(pl, sc)
+        assert np.all(g["S"] == g["S"][0])
+        assert np.all(g["w"] == 1.0 / 2048)
+        assert np.array_equal(g["U"], U0)
+        assert g["stats"]["ess"] == pytest.approx(2048.0, rel=1e-12)
+
+
+def test_small_lambda_selects_argmin():
+    mppi = _mppi()
+    sc = scenes.tiny(K=1024, T=25, n_c=6)
+    p = dict(sc["params"], lam=1e-6)
+    with mppi.Planner(p) as pl:
+        g = P.gpu_step(pl, sc)
+    k = int(np.argmin(g["S"]))
+    assert g["w"][k] == 1.0
+    assert np.allclose(g["U"], g["U_prev"] + g["eps"][:, k, :], rtol=0, atol=1e-12)
+
+
+def test_all_costs_nonfinite_leaves_state_unchanged():
+    """Forced from the host: a huge tracking weight makes every cost +inf."""
+    mppi = _mppi()
+    sc = scenes.tiny(K=256, T=10, n_c=2)
+    p = dict(sc["params"], w_track=1e38)
+    wp = np.array([[1e6, 1e6, 0.0, 15.0]])
+    with mppi.Planner(p) as pl:
+        U0 = np.tile([0.2, 0.0], (10, 1))
+        pl.set_controls(U0)
+        pl.step(sc["x0"], wp, sc["circles"])
+        with pytest.raises(mppi.MppiError) as ei:
+            pl.sync()
+        assert ei.value.status == mppi.E_NONFINITE
+        U, n, _ = pl.get_state()
+        assert np.array_equal(U, U0) and n == 0
+        # the next good step proceeds from the unchanged state
+        pl.step(sc["x0"], sc["waypoints"], sc["circles"])
+        pl.sync()
+        assert pl.stats()["n_iter"] == 1
+
+
+def test_invalid_arguments_are_rejected():
+    mppi = _mppi()
+    sc = scenes.tiny(K=64, T=8)
+    with mppi.Planner(sc["params"], max_waypoints=64, max_circles=4) as pl:
+        with pytest.raises(mppi.MppiError):
+            pl.step([0, 0, float("nan"), 1.0], sc["waypoints"][:10], sc["circles"])
+        with pytest.raises(mppi.MppiError):
+            pl.step(sc["x0"], sc["waypoints"][:10], np.zeros((5, 5)))   # > max_circles
+        with pytest.raises(mppi.MppiError):
+            pl.step(sc["x0"], np.zeros((0, 4)), sc["circles"])
+        with pytest.raises(mppi.MppiError):
+            pl.shift(-1)
+        # the handle still works
+        pl.step(sc["x0"], sc["waypoints"][:10], sc["circles"])
+        pl.sync()
+
+
+def test_deterministic_and_checkpoint_restore():
+    """Repeated runs are bit-identical; restoring a checkpoint continues the
+    Philox stream bit-identically."""
+    mppi = _mppi()
+    sc = scenes.c1(K=2048, T=60)
+    p = sc["params"]
+    outs = []
+    for rep in range(2):
+        with mppi.Planner(p) as pl:
+            for i in range(3):
+                pl.step(sc["x0"], sc["waypoints"], sc["circles"])
+            U_ck, n_ck, _ = pl.get_state()
+            for i in range(2):
+                pl.step(sc["x0"], sc["waypoints"], sc["circles"])
+            U_end = pl.controls()
+            pl.set_state(U_ck, n_ck)
+            for i in range(2):
+                pl.step(sc["x0"], sc["waypoints"], sc["circles"])
+            assert np.array_equal(pl.controls(), U_end)
+            outs.append(U_end)
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_shift_warm_start():
+    mppi = _mppi()
+    sc = scenes.tiny(K=64, T=6)
+    with mppi.Planner(sc["params"]) as pl:
+        U = np.arange(12, dtype=np.float64).reshape(6, 2)
+        pl.set_controls(U)
+        pl.shift(2)
+        got = pl.controls()
+        assert np.array_equal(got, np.vstack([U[2:], U[5:6], U[5:6]]))
+
+
+def test_c1_ten_warm_iterations_staged():
+    """Sine-lane instance, K=8192, T=100: 10 warm-started iterations, every
+    gate checked per iteration with the oracle re-synced to the GPU's
+    previous controls; the free-running end-to-end result is reported."""
+    mppi = _mppi()
+    sc = scenes.c1()
+    p = sc["params"]
+    reps = []
+    U_free = np.zeros((p["T"], 2))
+    with mppi.Planner(p) as pl:
+        for i in range(sc["iterations"]):
+            _say("c1 iteration", i)
+            g = P.gpu_step(pl, sc)
+            rep = P.staged(p, sc, g, n_iter=i)
+            e2e, ok = P.end_to_end(p, sc, g, i)
+            rep["e2e"] = e2e
+            rep["e2e_ok"] = ok
+            reps.append(rep)
+            P.assert_staged(rep)
+            U_free = O.iteration(p, sc["x0"], sc["waypoints"], sc["circles"], U_free, n_iter=i)["U"]
+        U_gpu = pl.controls()
+    free = float(np.max(np.abs(U_gpu - U_free) / P.u_tol(U_free, p["sigma"])))
+    _dump("c1", dict(iterations=reps, free_running_U_max_over_tol=free))
+
+
+def test_c4_stress_sampled():
+    """Stress instance at full size (K=262144, T=200, 512 circles): weights
+    and update checked on every sample, costs on 192 sampled rollouts."""
+    mppi = _mppi()
+    sc = scenes.c4()
+    p = sc["params"]
+    _say("c4 stress")
+    with mppi.Planner(p) as pl:
+        g = P.gpu_step(pl, sc)
+    ks = np.unique(np.concatenate([
+        np.random.Generator(np.random.PCG64(44)).integers(0, p["K"], size=160),
+        np.argsort(g["S"])[:16], np.argsort(g["S"])[-16:]]))
+    rep = P.staged(p, sc, g, n_iter=0, ks=ks)
+    _dump("c4", rep)
+    P.assert_staged(rep)

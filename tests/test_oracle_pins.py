@@ -493,3 +493,22 @@ def test_brute_force_tiny_iteration():
         for dim in range(2):
             Ut = U0[t, dim] + sum(w[k] * E[t][k][dim] for k in range(K))
             assert abs(float(Ut) - r["U"][t, dim]) <= 1e-12
+
+
+def test_sample_subset_rollout_matches_full():
+    s = scenes.tiny(K=40, T=9, n_c=4)
+    p = s["params"]
+    U0 = np.tile([0.05, -0.01], (9, 1))
+    S, eps = O.rollout(p, s["x0"], s["waypoints"], s["circles"], U0, n_iter=5)
+    ks = [39, 0, 17, 17, 3]
+    S2, eps2 = O.rollout_samples(p, s["x0"], s["waypoints"], s["circles"], U0, ks, n_iter=5)
+    assert np.array_equal(S2, S[ks])
+    assert np.array_equal(eps2, eps[:, ks, :])
+
+
+def test_philox_batch_matches_single():
+    rng = np.random.Generator(np.random.PCG64(12))
+    ctrs = rng.integers(0, 2**32, size=(50, 4), dtype=np.uint64).astype(np.uint32)
+    out = O.philox_batch(ctrs, [0x1234, 0xABCD])
+    for c, o in zip(ctrs, out):
+        assert O.philox(list(c), [0x1234, 0xABCD]) == [int(v) for v in o]
