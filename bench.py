@@ -117,6 +117,49 @@ def cpu_baseline(sc, seconds):
                        "instance in %.1f s" % (n, p["K"], p["T"], el))
 
 
+def probe(steps):
+    """Dispatches for hardware-counter runs: a 256 MiB streaming copy (the
+    calibration reference, 3 dispatches), then `steps` warm-started
+    iterations of the benchmark workload."""
+    from paper_2308_01654_amd import mppi, scenes
+    mppi.check(mppi.load().mppi_bench_copy(256 << 20, 3))
+    sc = scenes.c1()
+    pl = mppi.Planner(sc["params"])
+    pl.set_scene(sc["x0"], sc["waypoints"], sc["circles"])
+    for _ in range(steps):
+        pl.step_resident(sc["x0"])
+    pl.sync()
+    pl.close()
+    print("probe: copy calibration + %d iterations done" % steps, flush=True)
+
+
+def sweep():
+    """Kernel time of one iteration for every lanes-per-sample shape on the
+    plain, sine-lane, stress and paper-shaped workloads (HIP events)."""
+    from paper_2308_01654_amd import mppi, scenes
+    for sc in (scenes.c0(), scenes.c1(), scenes.c4(), scenes.paper_table1()):
+        p = sc["params"]
+        K, T = p["K"], p["T"]
+        F = flops_per_rollout_step(len(sc["waypoints"]), len(sc["circles"]), len(p["ego_off"]))
+        for lanes in (1, 2, 4, 8, 16):
+            pl = mppi.Planner(p, lanes=lanes)
+            pl.set_scene(sc["x0"], sc["waypoints"], sc["circles"])
+            for _ in range(3):
+                pl.step_resident(sc["x0"])
+            pl.sync()
+            n = 20 if K * T < 10**7 else 3
+            pl.set_profiling(True)
+            for _ in range(n):
+                pl.step_resident(sc["x0"])
+            pr = pl.profile()
+            pl.set_profiling(False)
+            ms = pr["iter_ms"] / pr["iter_launches"]
+            print("%-13s K=%-7d T=%-4d lanes=%-2d kernel %.4f ms  %.3e steps/s  %.1f TFLOP/s"
+                  % (sc["name"], K, T, lanes, ms, K * T / (ms * 1e-3), F * K * T / (ms * 1e-3) / 1e12),
+                  flush=True)
+            pl.close()
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,11 +169,21 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per sample (0 = library choice)")
     ap.add_argument("--latency-iters", type=int, default=200)
+    ap.add_argument("--probe", type=int, default=0, metavar="N",
+                    help="only dispatch the counter-calibration copy and N iterations")
+    ap.add_argument("--sweep", action="store_true", help="only run the lanes-per-sample sweep")
     args = ap.parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the iteration on a single "
               "MI355X (--gpus 1); multi-GPU runs are not part of it.", file=sys.stderr)
         return 2
+
+    if args.probe:
+        probe(args.probe)
+        return 0
+    if args.sweep:
+        sweep()
+        return 0
 
     from paper_2308_01654_amd import mppi, scenes
     sc = scenes.c1()

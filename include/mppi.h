@@ -197,6 +197,14 @@ mppi_status mppi_get_profile(mppi_t* h, mppi_profile* out);
 mppi_status mppi_debug_philox(uint64_t seed, uint64_t n_iter, uint32_t k0, uint32_t nk,
                               uint32_t j0, uint32_t nj, uint32_t* out, size_t n);
 
+/* ---- measurement helper ---------------------------------------------------- */
+
+/* Plain device-to-device copy of `bytes` bytes (rounded down to 16), run
+ * `reps` times by a simple streaming kernel on freshly allocated buffers:
+ * the reference dispatch against which hardware traffic counters (bytes
+ * fetched / written per dispatch) are calibrated.  Synchronous. */
+mppi_status mppi_bench_copy(size_t bytes, int32_t reps);
+
 /* ---- diagnostics ---------------------------------------------------------- */
 
 const char* mppi_status_str(mppi_status s);

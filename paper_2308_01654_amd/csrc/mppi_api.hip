@@ -647,4 +647,20 @@ mppi_status mppi_debug_philox(uint64_t seed, uint64_t n_iter, uint32_t k0, uint3
     return MPPI_OK;
 }
 
+mppi_status mppi_bench_copy(size_t bytes, int32_t reps)
+{
+    const size_t n16 = bytes / 16;
+    if (n16 == 0 || reps < 1) return fail(MPPI_E_INVALID, "bytes >= 16 and reps >= 1 required");
+    float4 *a = nullptr, *b = nullptr;
+    hipError_t e = hipMalloc((void**)&a, n16 * 16);
+    if (e == hipSuccess) e = hipMalloc((void**)&b, n16 * 16);
+    if (e == hipSuccess) e = hipMemset(a, 0, n16 * 16);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy(a, b, n16, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    (void)hipFree(a);
+    (void)hipFree(b);
+    if (e != hipSuccess) return fail(MPPI_E_DEVICE, "copy: %s", hipGetErrorString(e));
+    return MPPI_OK;
+}
+
 }  // extern "C"

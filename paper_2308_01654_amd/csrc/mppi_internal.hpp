@@ -87,6 +87,7 @@ inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int sp
 hipError_t launch_iteration(const InstDesc& d, hipStream_t stream);
 hipError_t launch_weights(const InstDesc& d, double* w_out, hipStream_t stream);
 hipError_t launch_shift(double* U, int T, int steps, hipStream_t stream);
+hipError_t launch_copy(const float4* src, float4* dst, size_t n16, hipStream_t stream);
 hipError_t launch_debug_philox(uint32_t key0, uint32_t key1, unsigned long long n_iter,
                                uint32_t k0, uint32_t nk, uint32_t j0, uint32_t nj,
                                uint32_t* out, hipStream_t stream);

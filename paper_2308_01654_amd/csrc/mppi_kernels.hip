@@ -435,6 +435,20 @@ hipError_t launch_shift(double* U, int T, int steps, hipStream_t stream)
     return hipGetLastError();
 }
 
+// Streaming copy used to calibrate traffic counters.
+__global__ void k_copy(const float4* __restrict__ src, float4* __restrict__ dst, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy(const float4* src, float4* dst, size_t n16, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_copy, dim3(4096), dim3(256), 0, stream, src, dst, n16);
+    return hipGetLastError();
+}
+
 __global__ void k_debug_philox(uint32_t key0, uint32_t key1, unsigned long long n_iter,
                                uint32_t k0, uint32_t nk, uint32_t j0, uint32_t nj, uint32_t* out)
 {

@@ -102,6 +102,7 @@ SIGNATURES = [
     ("mppi_get_profile", _i32, [_vp, ctypes.POINTER(Profile)]),
     ("mppi_debug_philox", _i32, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                                  ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _u32p, _sz]),
+    ("mppi_bench_copy", _i32, [_sz, _i32]),
     ("mppi_status_str", ctypes.c_char_p, [_i32]),
     ("mppi_last_error", ctypes.c_char_p, []),
     ("mppi_version", ctypes.c_char_p, []),
