@@ -147,6 +147,21 @@ mppi_status mppi_set_scene(mppi_t* h, const double x0[4], const mppi_scene* scen
  * kernel arguments.  MPPI_E_INVALID if no scene has been set. */
 mppi_status mppi_step_resident(mppi_t* h, const double x0[4]);
 
+/* One MPPI iteration of each of n planning instances in ONE persistent launch
+ * (replayed as a captured HIP graph).  Instances may differ in K, T, scene
+ * size and launch shape; each computes exactly the bits it computes alone,
+ * because its lanes-per-sample shape and tile split depend only on its own
+ * configuration.
+ *   hs      [n] distinct handles that all enqueue on the same HIP stream
+ *   x0s     [n][4] initial states (world coordinates)
+ *   scenes  [n] scenes copied for this call, or NULL to use every handle's
+ *           resident scene (mppi_set_scene); a batch does not change the
+ *           handles' resident scenes
+ * Asynchronous on that stream; results are read per handle as after
+ * mppi_step.  Validation failures leave every handle unchanged. */
+mppi_status mppi_step_batch(mppi_t* const* hs, const double* x0s, const mppi_scene* scenes,
+                            int32_t n);
+
 /* Wait for the handle's stream; returns the status of the last step. */
 mppi_status mppi_sync(mppi_t* h);
 

@@ -1,0 +1,92 @@
+"""Autotuner of the iteration kernel's launch shape (lanes per sample).
+
+For every shape bucket -- K in powers of two, T buckets (<=32, <=64, <=128,
+<=256, >256) and circle-count buckets (0, <=16, <=64, <=256, >256) -- it runs
+a representative sine-lane instance with every lanes-per-sample shape
+(1, 2, 4, 8, 16), times the iteration kernel with HIP events, and writes the
+fastest shape as a line "k_log2 t_bucket c_bucket lanes" of ``tuning.txt``.
+The library reads that file at its first launch (next to libmppi.so, or the
+file named by MPPI_TUNING_FILE).  A bucket's choice depends only on the
+instance's own shape, so an instance computes the same bits alone and inside
+any batch.
+
+Usage (on the GPU): python -m paper_2308_01654_amd.autotune [--out PATH] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+T_REPS = {0: 30, 1: 60, 2: 100, 3: 200, 4: 400}
+C_REPS = {0: 0, 1: 12, 2: 60, 3: 200, 4: 512}
+LANES = (1, 2, 4, 8, 16)
+
+
+def shape_scene(K, T, n_c):
+    from paper_2308_01654_amd import scenes
+    rng = np.random.Generator(np.random.PCG64(K * 1000 + T * 7 + n_c))
+    p = scenes.params(K=K, T=T, dt=0.05, v_max=15.0, seed=17)
+    return dict(params=p, x0=scenes._sine_x0(), waypoints=scenes.sine_lane(v_ref=15.0),
+                circles=scenes.sine_circles(rng, n_c))
+
+
+def time_shape(sc, lanes, reps):
+    from paper_2308_01654_amd import mppi
+    pl = mppi.Planner(sc["params"], lanes=lanes)
+    try:
+        pl.set_scene(sc["x0"], sc["waypoints"], sc["circles"])
+        pl.step_resident(sc["x0"])
+        pl.sync()
+        pl.set_profiling(True)
+        for _ in range(reps):
+            pl.step_resident(sc["x0"])
+        pr = pl.profile()
+        return pr["iter_ms"] / pr["iter_launches"]
+    finally:
+        pl.close()
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--out", default=os.path.join(HERE, "tuning.txt"))
+    ap.add_argument("--k-min", type=int, default=10)
+    ap.add_argument("--k-max", type=int, default=18)
+    ap.add_argument("--t-buckets", default="0,1,2,3")
+    ap.add_argument("--c-buckets", default="0,1,2,3,4")
+    args = ap.parse_args(argv)
+    lines = ["# lanes-per-sample tuning table of the MPPI iteration kernel",
+             "# written by: python -m paper_2308_01654_amd.autotune (HIP-event kernel time, "
+             "fastest of lanes 1/2/4/8/16)",
+             "# columns: k_log2 t_bucket c_bucket lanes   (t: <=32,<=64,<=128,<=256,>256; "
+             "c: 0,<=16,<=64,<=256,>256)"]
+    t0 = time.time()
+    for kb in range(args.k_min, args.k_max + 1):
+        K = 1 << kb
+        for tb in [int(v) for v in args.t_buckets.split(",")]:
+            T = T_REPS[tb]
+            for cb in [int(v) for v in args.c_buckets.split(",")]:
+                sc = shape_scene(K, T, C_REPS[cb])
+                reps = 5 if K * T < 2_000_000 else 2
+                times = {g: time_shape(sc, g, reps) for g in LANES if g <= T}
+                best = min(times, key=times.get)
+                lines.append("%d %d %d %d" % (kb, tb, cb, best))
+                print("K=%-7d T=%-4d circles=%-4d " % (K, T, C_REPS[cb]) +
+                      " ".join("g%d=%.4fms" % (g, ms) for g, ms in times.items()) +
+                      "  -> %d  (%.0fs)" % (best, time.time() - t0), flush=True)
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("wrote", args.out, flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

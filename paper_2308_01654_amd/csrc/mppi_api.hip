@@ -8,7 +8,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -43,6 +46,26 @@ mppi_status fail(mppi_status s, const char* fmt, ...)
                         __FILE__, __LINE__);                                                 \
         }                                                                                    \
     } while (0)
+
+struct GraphEntry {
+    size_t bytes, smem;
+    int grids[kLaneClasses];
+    int buf, shift_blocks;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+// Staging and device arena of batched launches (descriptors + scenes), and
+// the instantiated graphs that replay them.
+struct BatchWs {
+    unsigned char* arena = nullptr;
+    unsigned char* stage[2] = {nullptr, nullptr};
+    size_t cap = 0;
+    hipEvent_t done[2] = {nullptr, nullptr};
+    bool pending[2] = {false, false};
+    int cur = 0;
+    std::vector<GraphEntry> graphs;
+};
 
 struct ProfEvent {
     hipEvent_t a, b;
@@ -81,6 +104,7 @@ struct mppi {
     bool staged_pending[2] = {false, false};
     int cur = 0;
     int max_tiles = 0;
+    BatchWs* batch = nullptr;  // lazily created when this handle leads a batch
     // resident scene
     bool has_scene = false;
     double origin[2] = {0.0, 0.0};
@@ -101,6 +125,74 @@ size_t scene_bytes(int n_wp, int n_c)
 {
     return align_up((size_t)n_c * 16, 16) + align_up((size_t)n_wp * 8, 16) +
            align_up((size_t)n_wp * 4, 16) + align_up((size_t)n_c * 4, 16);
+}
+
+int device_cus()
+{
+    static int n = 0;
+    if (n == 0) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            n = prop.multiProcessorCount;
+        if (n <= 0) n = 256;
+    }
+    return n;
+}
+
+mppi_status validate_scene(const mppi_config& c, const double x0[4], const mppi_scene* sc)
+{
+    if (!x0 || !sc) return fail(MPPI_E_INVALID, "x0 and scene must not be NULL");
+    for (int i = 0; i < 4; ++i)
+        if (!isfinite(x0[i])) return fail(MPPI_E_INVALID, "x0[%d] is not finite", i);
+    const int n_wp = sc->n_waypoints, n_c = sc->n_circles;
+    if (n_wp < 1 || n_wp > c.max_waypoints || !sc->waypoints)
+        return fail(MPPI_E_INVALID, "n_waypoints=%d outside [1, %d] or waypoints NULL", n_wp,
+                    c.max_waypoints);
+    if (n_c < 0 || n_c > c.max_circles || (n_c > 0 && !sc->circles))
+        return fail(MPPI_E_INVALID, "n_circles=%d outside [0, %d] or circles NULL", n_c,
+                    c.max_circles);
+    for (int i = 0; i < 4 * n_wp; ++i)
+        if (!isfinite(sc->waypoints[i])) return fail(MPPI_E_INVALID, "waypoint value not finite");
+    for (int i = 0; i < 5 * n_c; ++i)
+        if (!isfinite(sc->circles[i])) return fail(MPPI_E_INVALID, "circle value not finite");
+    return MPPI_OK;
+}
+
+struct SceneLayout {
+    size_t o_pv, o_xy, o_vr, o_rr, bytes;
+};
+
+SceneLayout scene_layout(int n_wp, int n_c)
+{
+    SceneLayout L;
+    L.o_pv = 0;
+    L.o_xy = L.o_pv + align_up((size_t)n_c * 16, 16);
+    L.o_vr = L.o_xy + align_up((size_t)n_wp * 8, 16);
+    L.o_rr = L.o_vr + align_up((size_t)n_wp * 4, 16);
+    L.bytes = L.o_rr + align_up((size_t)n_c * 4, 16);
+    return L;
+}
+
+// Ego-frame float32 copy of the scene (float64 subtraction of the origin).
+void write_scene(unsigned char* dst, const SceneLayout& L, const mppi_config& c,
+                 const double origin[2], const mppi_scene* sc)
+{
+    float4* pv = reinterpret_cast<float4*>(dst + L.o_pv);
+    float2* xy = reinterpret_cast<float2*>(dst + L.o_xy);
+    float* vr = reinterpret_cast<float*>(dst + L.o_vr);
+    float* rr = reinterpret_cast<float*>(dst + L.o_rr);
+    for (int i = 0; i < sc->n_waypoints; ++i) {
+        const double* w = sc->waypoints + 4 * i;
+        xy[i] = make_float2((float)(w[0] - origin[0]), (float)(w[1] - origin[1]));
+        vr[i] = (float)w[3];
+    }
+    for (int i = 0; i < sc->n_circles; ++i) {
+        const double* o = sc->circles + 5 * i;
+        pv[i] = make_float4((float)(o[0] - origin[0]), (float)(o[1] - origin[1]), (float)o[3],
+                            (float)o[4]);
+        rr[i] = (float)(o[2] + c.ego_r);
+    }
 }
 
 mppi_status validate_config(const mppi_config* c)
@@ -148,7 +240,54 @@ mppi_status usable(mppi_t* h)
     return MPPI_OK;
 }
 
-int auto_lanes(const mppi_config& c)
+// ---- launch-shape tuning table ----------------------------------------------
+// Lines "k_log2 t_bucket c_bucket lanes" written by the autotuner
+// (paper_2308_01654_amd/autotune.py) into tuning.txt next to the library, or
+// the file named by MPPI_TUNING_FILE.  A shape's lanes per sample depends only
+// on its own (K, T, circle count).
+struct TuneEntry {
+    int k, t, c, lanes;
+};
+std::vector<TuneEntry> g_tune;
+std::once_flag g_tune_once;
+
+int k_bucket(int K)
+{
+    int b = 0;
+    while ((1 << b) < K && b < 30) ++b;
+    return b;
+}
+int t_bucket(int T) { return T <= 32 ? 0 : T <= 64 ? 1 : T <= 128 ? 2 : T <= 256 ? 3 : 4; }
+int c_bucket(int n) { return n == 0 ? 0 : n <= 16 ? 1 : n <= 64 ? 2 : n <= 256 ? 3 : 4; }
+
+void load_tuning()
+{
+    std::string path;
+    if (const char* e = getenv("MPPI_TUNING_FILE")) {
+        path = e;
+    } else {
+        Dl_info info;
+        if (dladdr((void*)&load_tuning, &info) && info.dli_fname) {
+            path = info.dli_fname;
+            const size_t slash = path.rfind('/');
+            path = (slash == std::string::npos ? std::string(".") : path.substr(0, slash)) +
+                   "/tuning.txt";
+        }
+    }
+    FILE* f = path.empty() ? nullptr : fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[256];
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        TuneEntry t;
+        if (sscanf(line, "%d %d %d %d", &t.k, &t.t, &t.c, &t.lanes) == 4 &&
+            (t.lanes == 1 || t.lanes == 2 || t.lanes == 4 || t.lanes == 8 || t.lanes == 16))
+            g_tune.push_back(t);
+    }
+    fclose(f);
+}
+
+int heuristic_lanes(const mppi_config& c)
 {
     // Enough lanes to give every SIMD of the 256 CUs two waves.
     const long target = 2L * 256 * 4 * 64;
@@ -156,6 +295,18 @@ int auto_lanes(const mppi_config& c)
     g = std::min(g, 16);
     while (g > 1 && g > c.T) g >>= 1;
     return std::max(g, 1);
+}
+
+int auto_lanes(const mppi_config& c, int n_c)
+{
+    std::call_once(g_tune_once, load_tuning);
+    const int kb = k_bucket(c.K), tb = t_bucket(c.T), cb = c_bucket(n_c);
+    const TuneEntry* best = nullptr;
+    for (const TuneEntry& e : g_tune)
+        if (e.t == tb && e.c == cb && (!best || abs(e.k - kb) < abs(best->k - kb))) best = &e;
+    int g = best ? best->lanes : heuristic_lanes(c);
+    while (g > 1 && g > c.T) g >>= 1;
+    return g;
 }
 
 mppi_status record_launch(mppi_t* h, int kind, hipEvent_t* a)
@@ -228,6 +379,20 @@ void release(mppi_t* h)
     (void)hipFree(h->wbuf);
     (void)hipFree(h->st);
     (void)hipFree(h->scene);
+    if (h->batch) {
+        BatchWs* b = h->batch;
+        for (GraphEntry& g : b->graphs) {
+            (void)hipGraphExecDestroy(g.exec);
+            (void)hipGraphDestroy(g.graph);
+        }
+        (void)hipFree(b->arena);
+        for (int i = 0; i < 2; ++i) {
+            if (b->stage[i]) (void)hipHostFree(b->stage[i]);
+            if (b->done[i]) (void)hipEventDestroy(b->done[i]);
+        }
+        delete b;
+        h->batch = nullptr;
+    }
     for (int i = 0; i < 2; ++i) {
         if (h->staging[i]) (void)hipHostFree(h->staging[i]);
         if (h->staged[i]) (void)hipEventDestroy(h->staged[i]);
@@ -325,81 +490,43 @@ mppi_status mppi_set_scene(mppi_t* h, const double x0[4], const mppi_scene* sc)
 {
     mppi_status s = usable(h);
     if (s != MPPI_OK) return s;
-    const mppi_config& c = h->cfg;
-    if (!x0 || !sc) return fail(MPPI_E_INVALID, "x0 and scene must not be NULL");
-    for (int i = 0; i < 4; ++i)
-        if (!isfinite(x0[i])) return fail(MPPI_E_INVALID, "x0[%d] is not finite", i);
-    const int n_wp = sc->n_waypoints, n_c = sc->n_circles;
-    if (n_wp < 1 || n_wp > c.max_waypoints || !sc->waypoints)
-        return fail(MPPI_E_INVALID, "n_waypoints=%d outside [1, %d] or waypoints NULL", n_wp,
-                    c.max_waypoints);
-    if (n_c < 0 || n_c > c.max_circles || (n_c > 0 && !sc->circles))
-        return fail(MPPI_E_INVALID, "n_circles=%d outside [0, %d] or circles NULL", n_c,
-                    c.max_circles);
-    for (int i = 0; i < 4 * n_wp; ++i)
-        if (!isfinite(sc->waypoints[i])) return fail(MPPI_E_INVALID, "waypoint value not finite");
-    for (int i = 0; i < 5 * n_c; ++i)
-        if (!isfinite(sc->circles[i])) return fail(MPPI_E_INVALID, "circle value not finite");
-
-    // ego-frame staging (float64 subtraction, then float32), double-buffered
+    if ((s = validate_scene(h->cfg, x0, sc)) != MPPI_OK) return s;
     const int b = h->cur;
     if (h->staged_pending[b]) {
         HIP_TRY(hipEventSynchronize(h->staged[b]));
         h->staged_pending[b] = false;
     }
-    unsigned char* stg = h->staging[b];
-    const size_t o_pv = 0;
-    const size_t o_xy = o_pv + align_up((size_t)n_c * 16, 16);
-    const size_t o_vr = o_xy + align_up((size_t)n_wp * 8, 16);
-    const size_t o_rr = o_vr + align_up((size_t)n_wp * 4, 16);
-    const size_t bytes = o_rr + align_up((size_t)n_c * 4, 16);
-    float4* pv = reinterpret_cast<float4*>(stg + o_pv);
-    float2* xy = reinterpret_cast<float2*>(stg + o_xy);
-    float* vr = reinterpret_cast<float*>(stg + o_vr);
-    float* rr = reinterpret_cast<float*>(stg + o_rr);
-    for (int i = 0; i < n_wp; ++i) {
-        const double* w = sc->waypoints + 4 * i;
-        xy[i] = make_float2((float)(w[0] - x0[0]), (float)(w[1] - x0[1]));
-        vr[i] = (float)w[3];
-    }
-    for (int i = 0; i < n_c; ++i) {
-        const double* o = sc->circles + 5 * i;
-        pv[i] = make_float4((float)(o[0] - x0[0]), (float)(o[1] - x0[1]), (float)o[3], (float)o[4]);
-        rr[i] = (float)(o[2] + c.ego_r);
-    }
-    HIP_TRY(hipMemcpyAsync(h->scene, stg, bytes, hipMemcpyHostToDevice, h->stream));
+    const SceneLayout L = scene_layout(sc->n_waypoints, sc->n_circles);
+    const double origin[2] = {x0[0], x0[1]};
+    write_scene(h->staging[b], L, h->cfg, origin, sc);
+    HIP_TRY(hipMemcpyAsync(h->scene, h->staging[b], L.bytes, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipEventRecord(h->staged[b], h->stream));
     h->staged_pending[b] = true;
     h->cur ^= 1;
     h->has_scene = true;
-    h->origin[0] = x0[0];
-    h->origin[1] = x0[1];
-    h->n_wp = n_wp;
-    h->n_c = n_c;
-    h->o_pv = o_pv;
-    h->o_xy = o_xy;
-    h->o_vr = o_vr;
-    h->o_rr = o_rr;
+    h->origin[0] = origin[0];
+    h->origin[1] = origin[1];
+    h->n_wp = sc->n_waypoints;
+    h->n_c = sc->n_circles;
+    h->o_pv = L.o_pv;
+    h->o_xy = L.o_xy;
+    h->o_vr = L.o_vr;
+    h->o_rr = L.o_rr;
     return MPPI_OK;
 }
 
-mppi_status mppi_step_resident(mppi_t* h, const double x0[4])
+// Descriptor of one iteration of handle h from state x0 on the scene at
+// `scene` (device), staged relative to `origin`.
+void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double origin[2],
+               const unsigned char* scene, const SceneLayout& L, int n_wp, int n_c, int shift)
 {
-    mppi_status s = usable(h);
-    if (s != MPPI_OK) return s;
     const mppi_config& c = h->cfg;
-    if (!h->has_scene) return fail(MPPI_E_INVALID, "no scene has been set");
-    if (!x0) return fail(MPPI_E_INVALID, "x0 must not be NULL");
-    for (int i = 0; i < 4; ++i)
-        if (!isfinite(x0[i])) return fail(MPPI_E_INVALID, "x0[%d] is not finite", i);
-
-    InstDesc d;
     memset(&d, 0, sizeof d);
     d.K = c.K;
     d.T = c.T;
-    d.n_wp = h->n_wp;
-    d.n_c = h->n_c;
-    d.lanes = h->lanes_req ? h->lanes_req : auto_lanes(c);
+    d.n_wp = n_wp;
+    d.n_c = n_c;
+    d.lanes = h->lanes_req ? h->lanes_req : auto_lanes(c, n_c);
     d.n_tiles = (c.K + (kBlock / d.lanes) - 1) / (kBlock / d.lanes);
     d.dt = (float)c.dt;
     d.inv_dt = (float)(1.0 / c.dt);
@@ -420,31 +547,296 @@ mppi_status mppi_step_resident(mppi_t* h, const double x0[4])
     d.d_safe_0 = (float)c.d_safe_0;
     d.n_ego = c.n_ego;
     for (int e = 0; e < kMaxEgo; ++e) d.ego_off[e] = e < c.n_ego ? (float)c.ego_off[e] : 0.f;
-    d.px0 = (float)(x0[0] - h->origin[0]);
-    d.py0 = (float)(x0[1] - h->origin[1]);
+    d.px0 = (float)(x0[0] - origin[0]);
+    d.py0 = (float)(x0[1] - origin[1]);
     d.th0 = (float)x0[2];
     d.v0 = (float)x0[3];
     d.lambda = c.lambda;
     d.key0 = (uint32_t)c.seed;
     d.key1 = (uint32_t)(c.seed >> 32);
-    d.c_pv = reinterpret_cast<const float4*>(h->scene + h->o_pv);
-    d.wp_xy = reinterpret_cast<const float2*>(h->scene + h->o_xy);
-    d.wp_vref = reinterpret_cast<const float*>(h->scene + h->o_vr);
-    d.c_rr = reinterpret_cast<const float*>(h->scene + h->o_rr);
+    d.shift = shift;
+    d.c_pv = reinterpret_cast<const float4*>(scene + L.o_pv);
+    d.wp_xy = reinterpret_cast<const float2*>(scene + L.o_xy);
+    d.wp_vref = reinterpret_cast<const float*>(scene + L.o_vr);
+    d.c_rr = reinterpret_cast<const float*>(scene + L.o_rr);
     d.U = h->U;
     d.S = h->S;
     d.eps = h->eps;
     d.partials = h->partials;
     d.scales = h->scales;
     d.st = h->st;
+}
 
+mppi_status mppi_step_resident(mppi_t* h, const double x0[4])
+{
+    mppi_status s = usable(h);
+    if (s != MPPI_OK) return s;
+    if (!h->has_scene) return fail(MPPI_E_INVALID, "no scene has been set");
+    if (!x0) return fail(MPPI_E_INVALID, "x0 must not be NULL");
+    for (int i = 0; i < 4; ++i)
+        if (!isfinite(x0[i])) return fail(MPPI_E_INVALID, "x0[%d] is not finite", i);
+    SceneLayout L;
+    L.o_pv = h->o_pv;
+    L.o_xy = h->o_xy;
+    L.o_vr = h->o_vr;
+    L.o_rr = h->o_rr;
+    InstDesc d;
+    fill_desc(d, h, x0, h->origin, h->scene, L, h->n_wp, h->n_c, 0);
+    const size_t smem = lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes).total;
     hipEvent_t a = nullptr;
     if ((s = record_launch(h, 0, &a)) != MPPI_OK) return s;
-    HIP_TRY(launch_iteration(d, h->stream));
+    HIP_TRY(launch_batch(d.lanes, active_ego(d.n_ego, d.n_c), &d, nullptr, 0, d.n_tiles, smem,
+                         h->stream));
     if ((s = record_end(h, 0, a)) != MPPI_OK) return s;
     h->last_lanes = d.lanes;
     h->stepped = true;
     return MPPI_OK;
+}
+
+namespace {
+
+size_t pow2_at_least(size_t v, size_t lo)
+{
+    size_t p = lo;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+bool graphs_enabled()
+{
+    static int on = -1;
+    if (on < 0) {
+        const char* e = getenv("MPPI_BATCH_GRAPH");
+        on = (e && e[0] == '0') ? 0 : 1;
+    }
+    return on == 1;
+}
+
+mppi_status ws_create(BatchWs** out)
+{
+    BatchWs* b = new (std::nothrow) BatchWs();
+    if (!b) return fail(MPPI_E_NOMEM, "host allocation failed");
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&b->done[i], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(MPPI_E_DEVICE, "batch workspace: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return MPPI_OK;
+}
+
+void ws_drop_graphs(BatchWs* b)
+{
+    for (GraphEntry& g : b->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    b->graphs.clear();
+}
+
+hipError_t ws_reserve(BatchWs* b, size_t cap, hipStream_t stream)
+{
+    if (b->cap >= cap) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return e;
+    ws_drop_graphs(b);
+    (void)hipFree(b->arena);
+    b->arena = nullptr;
+    for (int i = 0; i < 2; ++i) {
+        if (b->stage[i]) (void)hipHostFree(b->stage[i]);
+        b->stage[i] = nullptr;
+        b->pending[i] = false;
+    }
+    b->cap = 0;
+    if ((e = hipMalloc((void**)&b->arena, cap)) != hipSuccess) return e;
+    for (int i = 0; i < 2; ++i)
+        if ((e = hipHostMalloc((void**)&b->stage[i], cap, hipHostMallocDefault)) != hipSuccess)
+            return e;
+    b->cap = cap;
+    return hipSuccess;
+}
+
+}  // namespace
+
+// Enqueue one iteration of every handle hs[0..n) as one persistent launch on
+// `stream` (captured once per arena/LDS size class as a graph and replayed).
+// scenes == NULL: each handle's resident scene.  shifts: optional per-handle
+// warm-start shift flags.  Used by mppi_step_batch and the server.
+mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, const double* x0s,
+                          const mppi_scene* scenes, const int32_t* shifts, int n, mppi_t* prof)
+{
+    mppi_t* h = prof;  // for HIP_TRY's sticky flag
+    const size_t off_prefix = align_up(sizeof(BatchHdr), 16);
+    const size_t off_descs = align_up(off_prefix + sizeof(int) * (size_t)(n + 1), 16);
+    size_t bytes = align_up(off_descs + sizeof(InstDesc) * (size_t)n, 16);
+    std::vector<SceneLayout> lay(n);
+    std::vector<size_t> soff(n, 0);
+    if (scenes) {
+        for (int i = 0; i < n; ++i) {
+            lay[i] = scene_layout(scenes[i].n_waypoints, scenes[i].n_circles);
+            soff[i] = bytes;
+            bytes += align_up(lay[i].bytes, 16);
+        }
+    }
+    const size_t bucket = pow2_at_least(bytes, 64 << 10);
+    HIP_TRY(ws_reserve(ws, bucket, stream));
+    const BatchHdr* hdr_dev = reinterpret_cast<const BatchHdr*>(ws->arena);  // after reserve
+    const int b = ws->cur;
+    if (ws->pending[b]) {
+        HIP_TRY(hipEventSynchronize(ws->done[b]));
+        ws->pending[b] = false;
+    }
+    unsigned char* host = ws->stage[b];
+    // longest tiles first
+    std::vector<int> order(n);
+    std::vector<double> work(n);
+    for (int i = 0; i < n; ++i) {
+        const mppi_config& c = hs[i]->cfg;
+        const int nw = scenes ? scenes[i].n_waypoints : hs[i]->n_wp;
+        const int nc = scenes ? scenes[i].n_circles : hs[i]->n_c;
+        order[i] = i;
+        work[i] = (double)c.T * (73.0 + 6.0 * nw + 7.0 * c.n_ego * nc);
+    }
+    std::vector<int> cls(n);
+    for (int i = 0; i < n; ++i) {
+        const int nc = scenes ? scenes[i].n_circles : hs[i]->n_c;
+        const int g = hs[i]->lanes_req ? hs[i]->lanes_req : auto_lanes(hs[i]->cfg, nc);
+        const int gi = g == 1 ? 0 : g == 2 ? 1 : g == 4 ? 2 : g == 8 ? 3 : 4;
+        cls[i] = 5 * gi + active_ego(hs[i]->cfg.n_ego, nc);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        return cls[a] != cls[c] ? cls[a] < cls[c] : work[a] > work[c];
+    });
+    BatchHdr* hdr = reinterpret_cast<BatchHdr*>(host);
+    int* prefix = reinterpret_cast<int*>(host + off_prefix);
+    InstDesc* descs = reinterpret_cast<InstDesc*>(host + off_descs);
+    long total = 0;
+    size_t smem = 0;
+    int any_shift = 0;
+    for (int j = 0; j < n; ++j) {
+        const int i = order[j];
+        mppi_t* hi = hs[i];
+        const double* x0 = x0s + 4 * i;
+        const int sh = shifts ? (shifts[i] ? 1 : 0) : 0;
+        if (scenes) {
+            const double origin[2] = {x0[0], x0[1]};
+            write_scene(host + soff[i], lay[i], hi->cfg, origin, &scenes[i]);
+            fill_desc(descs[j], hi, x0, origin, ws->arena + soff[i], lay[i], scenes[i].n_waypoints,
+                      scenes[i].n_circles, sh);
+        } else {
+            SceneLayout L;
+            L.o_pv = hi->o_pv;
+            L.o_xy = hi->o_xy;
+            L.o_vr = hi->o_vr;
+            L.o_rr = hi->o_rr;
+            fill_desc(descs[j], hi, x0, hi->origin, hi->scene, L, hi->n_wp, hi->n_c, sh);
+        }
+        prefix[j] = (int)total;
+        total += descs[j].n_tiles;
+        smem = std::max(smem, lds_layout(descs[j].n_wp, descs[j].n_c, descs[j].T,
+                                         kBlock / descs[j].lanes).total);
+        any_shift |= sh;
+    }
+    if (total > (1L << 30)) return fail(MPPI_E_INVALID, "batch too large");
+    prefix[n] = (int)total;
+    hdr->n_inst = n;
+    hdr->total_tiles = (int)total;
+    hdr->off_prefix = (int)off_prefix;
+    hdr->off_descs = (int)off_descs;
+    int grids[kLaneClasses];
+    {
+        int j = 0;
+        for (int c = 0; c < kLaneClasses; ++c) {
+            hdr->cls_begin[c] = j;
+            while (j < n && cls[order[j]] == c) ++j;
+            const int tiles = prefix[j] - prefix[hdr->cls_begin[c]];
+            grids[c] = tiles > 0 ? (int)pow2_at_least((size_t)tiles, 1) : 0;
+        }
+        hdr->cls_begin[kLaneClasses] = n;
+    }
+    const size_t smem_b = align_up(smem, 4096);
+    static const int kClassLanes[5] = {1, 2, 4, 8, 16};
+    auto enqueue_kernels = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int c = 0; c < kLaneClasses && e == hipSuccess; ++c)
+            if (grids[c] > 0)
+                e = launch_batch(kClassLanes[c / 5], c % 5, nullptr, hdr_dev, c, grids[c], smem_b,
+                                 stream);
+        return e;
+    };
+    const int shift_blocks = any_shift ? (int)pow2_at_least((size_t)n, 1) : 0;
+
+    hipEvent_t a = nullptr;
+    mppi_status s = record_launch(prof, 0, &a);
+    if (s != MPPI_OK) return s;
+    if (graphs_enabled()) {
+        GraphEntry* ge = nullptr;
+        for (GraphEntry& g : ws->graphs)
+            if (g.bytes == bucket && g.smem == smem_b && g.buf == b &&
+                g.shift_blocks == shift_blocks && memcmp(g.grids, grids, sizeof grids) == 0)
+                ge = &g;
+        if (!ge) {
+            if (ws->graphs.size() >= 32) ws_drop_graphs(ws);
+            GraphEntry g;
+            g.bytes = bucket;
+            g.smem = smem_b;
+            memcpy(g.grids, grids, sizeof grids);
+            g.buf = b;
+            g.shift_blocks = shift_blocks;
+            g.graph = nullptr;
+            g.exec = nullptr;
+            HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e = hipMemcpyAsync(ws->arena, host, bucket, hipMemcpyHostToDevice, stream);
+            if (e == hipSuccess && shift_blocks) e = launch_shift_batch(hdr_dev, shift_blocks, stream);
+            if (e == hipSuccess) e = enqueue_kernels();
+            hipError_t e2 = hipStreamEndCapture(stream, &g.graph);
+            HIP_TRY(e);
+            HIP_TRY(e2);
+            HIP_TRY(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+            ws->graphs.push_back(g);
+            ge = &ws->graphs.back();
+        }
+        HIP_TRY(hipGraphLaunch(ge->exec, stream));
+    } else {
+        HIP_TRY(hipMemcpyAsync(ws->arena, host, bytes, hipMemcpyHostToDevice, stream));
+        if (shift_blocks) HIP_TRY(launch_shift_batch(hdr_dev, shift_blocks, stream));
+        HIP_TRY(enqueue_kernels());
+    }
+    if ((s = record_end(prof, 0, a)) != MPPI_OK) return s;
+    HIP_TRY(hipEventRecord(ws->done[b], stream));
+    ws->pending[b] = true;
+    ws->cur ^= 1;
+    for (int j = 0; j < n; ++j) {
+        hs[order[j]]->stepped = true;
+        hs[order[j]]->last_lanes = descs[j].lanes;
+    }
+    return MPPI_OK;
+}
+
+mppi_status mppi_step_batch(mppi_t* const* hs, const double* x0s, const mppi_scene* scenes,
+                            int32_t n)
+{
+    if (!hs || !x0s || n < 1) return fail(MPPI_E_INVALID, "handles, states and n >= 1 required");
+    mppi_t* lead = hs[0];
+    mppi_status s;
+    for (int i = 0; i < n; ++i) {
+        if ((s = usable(hs[i])) != MPPI_OK) return s;
+        if (hs[i]->stream != lead->stream)
+            return fail(MPPI_E_INVALID, "every handle of a batch must use the same stream");
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return fail(MPPI_E_INVALID, "handle %d appears twice", i);
+        if (scenes) {
+            if ((s = validate_scene(hs[i]->cfg, x0s + 4 * i, &scenes[i])) != MPPI_OK) return s;
+        } else {
+            if (!hs[i]->has_scene) return fail(MPPI_E_INVALID, "handle %d has no scene", i);
+            for (int k = 0; k < 4; ++k)
+                if (!isfinite(x0s[4 * i + k])) return fail(MPPI_E_INVALID, "x0 not finite");
+        }
+    }
+    if (!lead->batch && (s = ws_create(&lead->batch)) != MPPI_OK) return s;
+    return batch_enqueue(lead->batch, lead->stream, hs, x0s, scenes, nullptr, n, lead);
 }
 
 mppi_status mppi_step(mppi_t* h, const double x0[4], const mppi_scene* sc)

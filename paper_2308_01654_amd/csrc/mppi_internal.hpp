@@ -47,6 +47,7 @@ struct InstDesc {
     float th0, v0;        // initial yaw and speed
     double lambda;
     uint32_t key0, key1;  // Philox key = seed
+    int shift;            // shift U by one step before the iteration (warm start)
     // device pointers
     const float2* wp_xy;  // [n_wp]
     const float* wp_vref; // [n_wp]
@@ -58,6 +59,22 @@ struct InstDesc {
     double* partials;     // [n_tiles][kPartialHead + 2T]
     double* scales;       // [n_tiles] scratch of the combining tile
     DevState* st;
+};
+
+// Header of a batch arena in device memory: followed by the tile prefix
+// (n_inst + 1 ints) at off_prefix and the descriptors at off_descs.
+// Instances are grouped by kernel variant: class c = 5 * lane_index + ne
+// (lane_index 0..4 for 1, 2, 4, 8, 16 lanes per sample; ne = ego circles
+// that meet obstacle circles, 0..4) owns instances [cls_begin[c],
+// cls_begin[c+1]).
+constexpr int kLaneClasses = 25;
+struct BatchHdr {
+    int n_inst;
+    int total_tiles;
+    int off_prefix;
+    int off_descs;
+    int cls_begin[kLaneClasses + 1];
+    int pad[2];
 };
 
 // Dynamic LDS layout of the iteration kernel for a given scene size.
@@ -84,7 +101,15 @@ inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int sp
 
 // Launchers (mppi_kernels.hip).  All enqueue on `stream` and return the
 // launch error, if any.
-hipError_t launch_iteration(const InstDesc& d, hipStream_t stream);
+// Iteration kernel, one workgroup per tile: one instance (d0, hdr_dev ==
+// nullptr) or lanes class `cls` of the batch described by the arena at
+// hdr_dev (lanes is the launch shape of every instance it processes).
+hipError_t launch_batch(int lanes, int ne, const InstDesc* d0, const BatchHdr* hdr_dev, int cls,
+                        int grid, size_t smem, hipStream_t stream);
+
+// Ego circles that take part in the obstacle term of an instance.
+inline int active_ego(int n_ego, int n_c) { return n_c > 0 ? n_ego : 0; }
+hipError_t launch_shift_batch(const BatchHdr* hdr_dev, int n_inst, hipStream_t stream);
 hipError_t launch_weights(const InstDesc& d, double* w_out, hipStream_t stream);
 hipError_t launch_shift(double* U, int T, int steps, hipStream_t stream);
 hipError_t launch_copy(const float4* src, float4* dst, size_t n16, hipStream_t stream);

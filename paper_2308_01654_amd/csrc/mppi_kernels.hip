@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <string.h>
 
 #include "mppi_internal.hpp"
 
@@ -124,7 +125,7 @@ __device__ __forceinline__ float stage_cost(const InstDesc& d, const Lds& s, flo
     const float q = d.w_effort * (d.alpha * fmaf(ea, ea, ed * ed) + fmaf(Ua, ea, Ud * ed) +
                                   0.5f * fmaf(Ua, Ua, Ud * Ud));
     float cost = fmaf(d.w_track, best, fmaf(d.w_speed, dv * dv, q));
-    if (NE > 0 && d.n_c > 0) {
+    if (NE > 0) {
         float ex[NE > 0 ? NE : 1], ey[NE > 0 ? NE : 1];
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
@@ -365,38 +366,95 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     }
 }
 
+// Iteration kernel for one or many instances of one launch shape (G lanes
+// per sample): one workgroup per tile.  Tile w of a batch belongs to the
+// instance whose tile range [prefix[i], prefix[i+1]) contains it; instances
+// are ordered longest tile first, and the hardware dispatcher hands tiles to
+// compute units as they free up.  The lanes-per-sample shape is a property of
+// the instance, so an instance computes the same bits alone or in any batch.
+// Workgroups past the last tile of the class (the grid is rounded up so that
+// captured graphs can be replayed for other batches) return at once.
 template <int G, int NE>
-__global__ __launch_bounds__(kBlock) void k_iteration(InstDesc d)
+__global__ __launch_bounds__(kBlock) void k_batch(InstDesc d0, const BatchHdr* __restrict__ hdr,
+                                                  int cls)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    iteration_tile<G, NE>(d, blockIdx.x, smem);
+    const int w = blockIdx.x;
+    if (!hdr) {
+        if (w < d0.n_tiles) iteration_tile<G, NE>(d0, w, smem);
+        return;
+    }
+    const unsigned char* base = reinterpret_cast<const unsigned char*>(hdr);
+    const int i0 = hdr->cls_begin[cls];
+    const int i1 = hdr->cls_begin[cls + 1];
+    const int* prefix = reinterpret_cast<const int*>(base + hdr->off_prefix);
+    const InstDesc* descs = reinterpret_cast<const InstDesc*>(base + hdr->off_descs);
+    const int gw = w + prefix[i0];
+    if (gw >= prefix[i1]) return;
+    int lo = i0, hi = i1 - 1;  // largest i with prefix[i] <= gw
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= gw) lo = mid; else hi = mid - 1;
+    }
+    iteration_tile<G, NE>(descs[lo], gw - prefix[lo], smem);
 }
 
 template <int G>
-static hipError_t launch_g(const InstDesc& d, hipStream_t stream)
+static hipError_t launch_g(int ne, const InstDesc& a, const BatchHdr* hdr_dev, int cls, int grid,
+                           size_t smem, hipStream_t stream)
 {
-    const LdsLayout L = lds_layout(d.n_wp, d.n_c, d.T, kBlock / G);
-    const dim3 grid(d.n_tiles), block(kBlock);
-    switch (d.n_c > 0 ? d.n_ego : 0) {
-    case 0: hipLaunchKernelGGL((k_iteration<G, 0>), grid, block, L.total, stream, d); break;
-    case 1: hipLaunchKernelGGL((k_iteration<G, 1>), grid, block, L.total, stream, d); break;
-    case 2: hipLaunchKernelGGL((k_iteration<G, 2>), grid, block, L.total, stream, d); break;
-    case 3: hipLaunchKernelGGL((k_iteration<G, 3>), grid, block, L.total, stream, d); break;
-    default: hipLaunchKernelGGL((k_iteration<G, 4>), grid, block, L.total, stream, d); break;
+    const dim3 g(grid), b(kBlock);
+    switch (ne) {
+    case 0: hipLaunchKernelGGL((k_batch<G, 0>), g, b, smem, stream, a, hdr_dev, cls); break;
+    case 1: hipLaunchKernelGGL((k_batch<G, 1>), g, b, smem, stream, a, hdr_dev, cls); break;
+    case 2: hipLaunchKernelGGL((k_batch<G, 2>), g, b, smem, stream, a, hdr_dev, cls); break;
+    case 3: hipLaunchKernelGGL((k_batch<G, 3>), g, b, smem, stream, a, hdr_dev, cls); break;
+    case 4: hipLaunchKernelGGL((k_batch<G, 4>), g, b, smem, stream, a, hdr_dev, cls); break;
+    default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_iteration(const InstDesc& d, hipStream_t stream)
+hipError_t launch_batch(int lanes, int ne, const InstDesc* d0, const BatchHdr* hdr_dev, int cls,
+                        int grid, size_t smem, hipStream_t stream)
 {
-    switch (d.lanes) {
-    case 1: return launch_g<1>(d, stream);
-    case 2: return launch_g<2>(d, stream);
-    case 4: return launch_g<4>(d, stream);
-    case 8: return launch_g<8>(d, stream);
-    case 16: return launch_g<16>(d, stream);
+    InstDesc zero;
+    memset(&zero, 0, sizeof zero);
+    const InstDesc& a = d0 ? *d0 : zero;
+    switch (lanes) {
+    case 1: return launch_g<1>(ne, a, hdr_dev, cls, grid, smem, stream);
+    case 2: return launch_g<2>(ne, a, hdr_dev, cls, grid, smem, stream);
+    case 4: return launch_g<4>(ne, a, hdr_dev, cls, grid, smem, stream);
+    case 8: return launch_g<8>(ne, a, hdr_dev, cls, grid, smem, stream);
+    case 16: return launch_g<16>(ne, a, hdr_dev, cls, grid, smem, stream);
     default: return hipErrorInvalidValue;
     }
+}
+
+// Receding-horizon shift of every instance that asks for it (one workgroup
+// per instance): U_t <- U_{min(t + 1, T-1)}.
+__global__ void k_shift_batch(const BatchHdr* __restrict__ hdr)
+{
+    __shared__ double buf[2 * kMaxT];
+    const InstDesc* descs = reinterpret_cast<const InstDesc*>(
+        reinterpret_cast<const unsigned char*>(hdr) + hdr->off_descs);
+    const int inst = blockIdx.x;
+    if (inst >= hdr->n_inst) return;
+    const InstDesc& d = descs[inst];
+    if (!d.shift) return;
+    const int T = d.T;
+    for (int i = threadIdx.x; i < 2 * T; i += blockDim.x) buf[i] = d.U[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * T; i += blockDim.x) {
+        const int t = min((i >> 1) + 1, T - 1);
+        d.U[i] = buf[2 * t + (i & 1)];
+    }
+}
+
+hipError_t launch_shift_batch(const BatchHdr* hdr_dev, int n_inst, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_shift_batch, dim3(n_inst), dim3(256), 0, stream, hdr_dev);
+    return hipGetLastError();
 }
 
 // Normalised weights of the last iteration: w_k = exp(-(S_k - S_min)/lambda)/Z.

@@ -86,6 +86,7 @@ SIGNATURES = [
     ("mppi_step", _i32, [_vp, _dp, ctypes.POINTER(Scene)]),
     ("mppi_set_scene", _i32, [_vp, _dp, ctypes.POINTER(Scene)]),
     ("mppi_step_resident", _i32, [_vp, _dp]),
+    ("mppi_step_batch", _i32, [ctypes.POINTER(_vp), _dp, ctypes.POINTER(Scene), _i32]),
     ("mppi_sync", _i32, [_vp]),
     ("mppi_get_controls", _i32, [_vp, _dp, _sz]),
     ("mppi_set_controls", _i32, [_vp, _dp, _sz]),
@@ -223,10 +224,37 @@ def mppi_debug_philox(seed, n_iter, k0, nk, j0, nj):
     return out
 
 
+def mppi_step_batch(hs, x0s, scenes):
+    """hs: list of handles; x0s: [n][4]; scenes: list of Scene or None."""
+    n = len(hs)
+    arr = (_vp * n)(*[h.value if isinstance(h, _vp) else h for h in hs])
+    x = np.ascontiguousarray(np.asarray(x0s, dtype=np.float64).reshape(n, 4))
+    sc = None
+    if scenes is not None:
+        sc = (Scene * n)(*scenes)
+    return load().mppi_step_batch(arr, x.ctypes.data_as(_dp), sc, n)
+
+
+def step_batch(planners, x0s, scene_arrays=None):
+    """One batched iteration of several Planners (same stream).  scene_arrays:
+    list of (waypoints, circles) or None for the resident scenes."""
+    keep = []
+    scenes = None
+    if scene_arrays is not None:
+        scenes = []
+        for wp, ci in scene_arrays:
+            s, k = make_scene(wp, ci)
+            scenes.append(s)
+            keep.append(k)
+    check(mppi_step_batch([p.h for p in planners], x0s, scenes))
+    del keep
+
+
 class Planner:
     """One planning instance (owns an mppi_t handle)."""
 
     def __init__(self, params, max_waypoints=2048, max_circles=1024, lanes=0, hip_stream=None):
+        """hip_stream: a hipStream_t (int) to enqueue on, or None for a new one."""
         self.cfg = config_from_params(params, max_waypoints, max_circles)
         self.K, self.T = self.cfg.K, self.cfg.T
         st, h = mppi_create(self.cfg, hip_stream)

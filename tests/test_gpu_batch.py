@@ -1,0 +1,132 @@
+"""Batched iterations: many uneven instances in one persistent launch replayed
+as a HIP graph.  Every instance must compute exactly the bits it computes
+alone; graph replays are checked one by one against eager single-instance
+runs of the same work interleaved between them."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2308_01654_amd import scenes
+from tests import _parity as P
+
+pytestmark = pytest.mark.gpu
+
+
+def _mppi():
+    from paper_2308_01654_amd import mppi
+    mppi.load()
+    return mppi
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+SHAPES = [(1024, 30, 0), (2048, 150, 64), (4096, 77, 13), (8192, 100, 60), (1024, 45, 1),
+          (16384, 31, 40), (3000, 64, 7), (512, 150, 64), (2048, 99, 33), (1, 40, 5)]
+
+
+def _instances():
+    out = []
+    for i, shp in enumerate(SHAPES):
+        sc = scenes.c2_instance(i, shp)
+        out.append(sc)
+    return out
+
+
+def _run_alone(mppi, sc, iters, U0=None):
+    with mppi.Planner(sc["params"]) as pl:
+        if U0 is not None:
+            pl.set_controls(U0)
+        res = []
+        for _ in range(iters):
+            pl.step(sc["x0"], sc["waypoints"], sc["circles"])
+            res.append((pl.controls(), pl.costs(), pl.weights()))
+        return res
+
+
+def test_batch_equals_alone_bitwise_with_graph_replays():
+    mppi = _mppi()
+    insts = _instances()
+    iters = 3
+    _say("alone runs")
+    alone = [_run_alone(mppi, sc, iters) for sc in insts]
+    _say("batched runs")
+    lead = mppi.Planner(insts[0]["params"])
+    pls = [lead] + [mppi.Planner(sc["params"], hip_stream=lead.stream()) for sc in insts[1:]]
+    try:
+        x0s = np.array([sc["x0"] for sc in insts])
+        arrays = [(sc["waypoints"], sc["circles"]) for sc in insts]
+        for it in range(iters):
+            mppi.step_batch(pls, x0s, arrays)
+            # eager single-instance work on another handle between replays
+            _run_alone(mppi, insts[3], 1)
+            bad = []
+            for k, pl in enumerate(pls):
+                U, S, w = alone[k][it]
+                Ub, Sb, wb = pl.controls(), pl.costs(), pl.weights()
+                if not (np.array_equal(Ub, U) and np.array_equal(Sb, S) and np.array_equal(wb, w)):
+                    bad.append((it, k, float(np.max(np.abs(Ub - U))), float(np.max(np.abs(Sb - S))),
+                                int(np.sum(Sb != S)), pl.stats()))
+                assert pl.stats()["n_iter"] == it + 1
+            for b in bad:
+                _say("mismatch", b)
+            assert not bad
+    finally:
+        for pl in pls:
+            pl.close()
+
+
+def test_batch_resident_scenes_and_subset_order():
+    """Resident scenes (no per-call scene copy) and a batch that lists the
+    handles in a different order give the same bits."""
+    mppi = _mppi()
+    insts = _instances()[:6]
+    alone = [_run_alone(mppi, sc, 2) for sc in insts]
+    lead = mppi.Planner(insts[0]["params"])
+    pls = [lead] + [mppi.Planner(sc["params"], hip_stream=lead.stream()) for sc in insts[1:]]
+    try:
+        for pl, sc in zip(pls, insts):
+            pl.set_scene(sc["x0"], sc["waypoints"], sc["circles"])
+        perm = [4, 1, 5, 0, 3, 2]
+        x0s = np.array([insts[k]["x0"] for k in perm])
+        for it in range(2):
+            mppi.step_batch([pls[k] for k in perm], x0s, None)
+            for k in range(len(insts)):
+                assert np.array_equal(pls[k].controls(), alone[k][it][0]), (it, k)
+    finally:
+        for pl in pls:
+            pl.close()
+
+
+def test_batch_staged_parity_against_oracle():
+    mppi = _mppi()
+    insts = [scenes.c2_instance(i, shp) for i, shp in enumerate([(1024, 40, 9), (2048, 33, 0), (777, 61, 20)])]
+    lead = mppi.Planner(insts[0]["params"])
+    pls = [lead] + [mppi.Planner(sc["params"], hip_stream=lead.stream()) for sc in insts[1:]]
+    try:
+        prev = [pl.controls() for pl in pls]
+        mppi.step_batch(pls, np.array([sc["x0"] for sc in insts]),
+                        [(sc["waypoints"], sc["circles"]) for sc in insts])
+        for pl, sc, U_prev in zip(pls, insts, prev):
+            g = dict(U_prev=U_prev, U=pl.controls(), S=pl.costs().astype(np.float64),
+                     w=pl.weights(), eps=pl.noise().astype(np.float64), stats=pl.stats())
+            P.assert_staged(P.staged(sc["params"], sc, g, n_iter=0))
+    finally:
+        for pl in pls:
+            pl.close()
+
+
+def test_batch_rejects_mixed_streams_and_duplicates():
+    mppi = _mppi()
+    a = scenes.tiny(K=64, T=8)
+    with mppi.Planner(a["params"]) as p1, mppi.Planner(a["params"]) as p2:
+        with pytest.raises(mppi.MppiError):
+            mppi.step_batch([p1, p2], np.array([a["x0"], a["x0"]]),
+                            [(a["waypoints"], a["circles"])] * 2)
+        with pytest.raises(mppi.MppiError):
+            mppi.step_batch([p1, p1], np.array([a["x0"], a["x0"]]),
+                            [(a["waypoints"], a["circles"])] * 2)
+        assert p1.stats()["n_iter"] == 0
