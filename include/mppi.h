@@ -203,6 +203,82 @@ mppi_status mppi_get_stream(mppi_t* h, void** stream);
 mppi_status mppi_set_profiling(mppi_t* h, int32_t on);
 mppi_status mppi_get_profile(mppi_t* h, mppi_profile* out);
 
+/* ---- served replanning (continuous batching) -------------------------------
+ * A server owns a table of vehicles and plans for them on one GPU.  Each
+ * vehicle keeps its nominal controls U and its Philox iteration counter on
+ * the device between requests; its first request starts from U = 0 and
+ * every later request first shifts U by one step (the warm start of Alg. 1).
+ * Requests are admitted in arrival order while their scratch memory (applied
+ * noise, costs, partials: about 8 K T bytes) fits the HBM budget, at most one
+ * request per vehicle is in flight, and whenever one of the server's streams
+ * is idle every admissible request is launched as one batch; batches on
+ * different streams overlap on the device.  All server calls are thread-safe. */
+
+typedef struct mppi_server mppi_server_t;
+
+typedef struct mppi_server_config {
+    uint64_t hbm_budget_bytes; /* device scratch for requests in flight, >= 4096     */
+    int32_t n_streams;         /* concurrent batches, 1..8                            */
+    int32_t max_batch;         /* requests per launch, 1..4096                        */
+    int32_t queue_cap;         /* queued + in-flight requests before MPPI_E_BUSY      */
+    int32_t plain;             /* 1: one request at a time, no batching, no overlap   */
+} mppi_server_config;
+
+typedef struct mppi_server_stats {
+    uint64_t submitted, completed, rejected, failed;
+    uint64_t launches;         /* batches launched                                    */
+    double mean_batch;         /* requests per batch                                  */
+    double mean_ms, p50_ms, p99_ms, p999_ms, max_ms; /* completion - arrival          */
+    uint64_t hbm_peak_bytes;   /* peak scratch in use                                 */
+    int32_t max_queue;         /* peak queued + in-flight requests                    */
+} mppi_server_stats;
+
+/* Open-loop load: request i of vehicle vid[i] from state x0[i] in scene
+ * scenes[scene[i]], submitted at arrival_ns[i] after the start (arrivals
+ * nondecreasing).  Latency is measured from the scheduled arrival. */
+typedef struct mppi_replay_plan {
+    int32_t n_requests;
+    const int32_t* vid;           /* [n]                                             */
+    const double* x0;             /* [n][4]                                          */
+    const int32_t* scene;         /* [n] index into scenes                           */
+    const mppi_scene* scenes;     /* [n_scenes]                                      */
+    int32_t n_scenes;
+    const uint64_t* arrival_ns;   /* [n] offsets from the start                      */
+} mppi_replay_plan;
+
+/* Clock of the arrival and completion stamps (steady, nanoseconds). */
+uint64_t mppi_server_now_ns(void);
+mppi_status mppi_server_create(const mppi_server_config* cfg, mppi_server_t** out);
+/* Stops the scheduler after the launched batches finish; frees everything. */
+mppi_status mppi_server_destroy(mppi_server_t* srv);
+/* Add a vehicle with its planner configuration; MPPI_E_NOMEM if one of its
+ * requests could never fit the budget.  Returns its id in *vid. */
+mppi_status mppi_server_add_vehicle(mppi_server_t* srv, const mppi_config* cfg, int32_t* vid);
+/* Queue a replanning request (inputs copied).  t_arrival_ns: arrival stamp
+ * on the mppi_server_now_ns clock (0 = now).  ticket may be NULL (the result
+ * is then discarded).  MPPI_E_BUSY when queue_cap requests are pending. */
+mppi_status mppi_server_submit(mppi_server_t* srv, int32_t vid, const double x0[4],
+                               const mppi_scene* scene, uint64_t t_arrival_ns, uint64_t* ticket);
+/* MPPI_E_NOT_READY until the request completed; then copies its controls
+ * ([T][2], n >= 2T; may be NULL), the completion stamp, forgets the ticket
+ * and returns the request's status. */
+mppi_status mppi_server_poll(mppi_server_t* srv, uint64_t ticket, double* controls, size_t n,
+                             uint64_t* t_done_ns);
+/* Block until no request is queued or in flight. */
+mppi_status mppi_server_wait_idle(mppi_server_t* srv);
+mppi_status mppi_server_get_stats(mppi_server_t* srv, mppi_server_stats* out);
+mppi_status mppi_server_reset_stats(mppi_server_t* srv);
+/* Checkpoint / restore of an idle vehicle: U [T][2], iteration counter and
+ * the number of requests it has run (0 means the next one starts cold). */
+mppi_status mppi_server_get_vehicle_state(mppi_server_t* srv, int32_t vid, double* U, size_t n,
+                                          uint64_t* n_iter, uint64_t* requests);
+mppi_status mppi_server_set_vehicle_state(mppi_server_t* srv, int32_t vid, const double* U,
+                                          size_t n, uint64_t n_iter, uint64_t requests);
+/* Run an open-loop load (blocks until every request completed); latency_ms
+ * [n] receives completion - scheduled arrival (NaN for refused requests). */
+mppi_status mppi_server_replay(mppi_server_t* srv, const mppi_replay_plan* plan,
+                               double* latency_ms);
+
 /* ---- Philox words as the rollout consumes them ---------------------------- */
 
 /* Philox4x32-10 (Salmon et al., SC'11) of counters (k, j, n_lo, n_hi) for

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmppi.so")
-SOURCES = ["mppi_kernels.hip", "mppi_api.hip"]
+SOURCES = ["mppi_kernels.hip", "mppi_api.hip", "mppi_server.hip"]
 ARCH = os.environ.get("MPPI_OFFLOAD_ARCH", "gfx950")
 
 
@@ -26,7 +26,7 @@ def flags():
     return [
         "--offload-arch=%s" % ARCH, "-O3", "-std=c++17", "-fPIC",
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-        "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument",
+        "-pthread", "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument",
     ]
 
 
@@ -53,7 +53,7 @@ def build(verbose: bool = False) -> str:
         if verbose and lines:
             print("\n".join(lines))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=%s" % ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [hipcc(), "--offload-arch=%s" % ARCH, "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

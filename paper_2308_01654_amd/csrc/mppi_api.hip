@@ -1,14 +1,14 @@
 // Host runtime behind the C ABI of include/mppi.h: handle life cycle,
-// validation, ego-frame staging of the scene, kernel launches, result
-// export, checkpointing and profiling.
+// validation, ego-frame staging of the scene, single and batched launches
+// (batches replayed as HIP graphs), result export, checkpointing, the
+// launch-shape tuning table and profiling.
 #include <hip/hip_runtime.h>
+#include <dlfcn.h>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
-
-#include <dlfcn.h>
 
 #include <algorithm>
 #include <mutex>
@@ -16,16 +16,14 @@
 #include <string>
 #include <vector>
 
-#include "../../include/mppi.h"
-#include "mppi_internal.hpp"
+#include "mppi_host.hpp"
 
 using namespace mppi_impl;
 
-namespace {
+namespace mppi_impl {
 
 thread_local std::string g_last_error;
 
-mppi_status fail(mppi_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 mppi_status fail(mppi_status s, const char* fmt, ...)
 {
     char buf[512];
@@ -37,108 +35,16 @@ mppi_status fail(mppi_status s, const char* fmt, ...)
     return s;
 }
 
-#define HIP_TRY(expr)                                                                        \
-    do {                                                                                     \
-        hipError_t e_ = (expr);                                                              \
-        if (e_ != hipSuccess) {                                                              \
-            h->sticky = MPPI_E_DEVICE;                                                       \
-            return fail(MPPI_E_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),      \
-                        __FILE__, __LINE__);                                                 \
-        }                                                                                    \
-    } while (0)
-
-struct GraphEntry {
-    size_t bytes, smem;
-    int grids[kLaneClasses];
-    int buf, shift_blocks;
-    hipGraph_t graph;
-    hipGraphExec_t exec;
-};
-
-// Staging and device arena of batched launches (descriptors + scenes), and
-// the instantiated graphs that replay them.
-struct BatchWs {
-    unsigned char* arena = nullptr;
-    unsigned char* stage[2] = {nullptr, nullptr};
-    size_t cap = 0;
-    hipEvent_t done[2] = {nullptr, nullptr};
-    bool pending[2] = {false, false};
-    int cur = 0;
-    std::vector<GraphEntry> graphs;
-};
-
-struct ProfEvent {
-    hipEvent_t a, b;
-    int kind;  // 0 = iteration kernel, 1 = auxiliary
-};
-
-int next_pow2(long v)
+size_t pow2_at_least(size_t v, size_t lo)
 {
-    int p = 1;
-    while (p < v && p < (1 << 30)) p <<= 1;
+    size_t p = lo;
+    while (p < v) p <<= 1;
     return p;
 }
 
-}  // namespace
+static size_t scene_bytes(int n_wp, int n_c) { return scene_layout(n_wp, n_c).bytes; }
 
-struct mppi {
-    mppi_config cfg;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    int lanes_req = 0;   // 0 = automatic
-    int last_lanes = 0;
-    mppi_status sticky = MPPI_OK;
-    // device memory
-    double* U = nullptr;
-    float* S = nullptr;
-    float2* eps = nullptr;
-    double* partials = nullptr;
-    double* scales = nullptr;
-    double* wbuf = nullptr;    // [K] weights export
-    DevState* st = nullptr;
-    unsigned char* scene = nullptr;
-    size_t scene_cap = 0;
-    // pinned staging, double-buffered
-    unsigned char* staging[2] = {nullptr, nullptr};
-    hipEvent_t staged[2] = {nullptr, nullptr};
-    bool staged_pending[2] = {false, false};
-    int cur = 0;
-    int max_tiles = 0;
-    BatchWs* batch = nullptr;  // lazily created when this handle leads a batch
-    // resident scene
-    bool has_scene = false;
-    double origin[2] = {0.0, 0.0};
-    int n_wp = 0, n_c = 0;
-    size_t o_pv = 0, o_xy = 0, o_vr = 0, o_rr = 0;
-    // last step
-    bool stepped = false;
-    // profiling
-    bool prof = false;
-    std::vector<ProfEvent> events;
-    double prof_ms[2] = {0.0, 0.0};
-    int64_t prof_n[2] = {0, 0};
-};
-
-namespace {
-
-size_t scene_bytes(int n_wp, int n_c)
-{
-    return align_up((size_t)n_c * 16, 16) + align_up((size_t)n_wp * 8, 16) +
-           align_up((size_t)n_wp * 4, 16) + align_up((size_t)n_c * 4, 16);
-}
-
-int device_cus()
-{
-    static int n = 0;
-    if (n == 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            n = prop.multiProcessorCount;
-        if (n <= 0) n = 256;
-    }
-    return n;
-}
+// ---- validation ---------------------------------------------------------------
 
 mppi_status validate_scene(const mppi_config& c, const double x0[4], const mppi_scene* sc)
 {
@@ -157,42 +63,6 @@ mppi_status validate_scene(const mppi_config& c, const double x0[4], const mppi_
     for (int i = 0; i < 5 * n_c; ++i)
         if (!isfinite(sc->circles[i])) return fail(MPPI_E_INVALID, "circle value not finite");
     return MPPI_OK;
-}
-
-struct SceneLayout {
-    size_t o_pv, o_xy, o_vr, o_rr, bytes;
-};
-
-SceneLayout scene_layout(int n_wp, int n_c)
-{
-    SceneLayout L;
-    L.o_pv = 0;
-    L.o_xy = L.o_pv + align_up((size_t)n_c * 16, 16);
-    L.o_vr = L.o_xy + align_up((size_t)n_wp * 8, 16);
-    L.o_rr = L.o_vr + align_up((size_t)n_wp * 4, 16);
-    L.bytes = L.o_rr + align_up((size_t)n_c * 4, 16);
-    return L;
-}
-
-// Ego-frame float32 copy of the scene (float64 subtraction of the origin).
-void write_scene(unsigned char* dst, const SceneLayout& L, const mppi_config& c,
-                 const double origin[2], const mppi_scene* sc)
-{
-    float4* pv = reinterpret_cast<float4*>(dst + L.o_pv);
-    float2* xy = reinterpret_cast<float2*>(dst + L.o_xy);
-    float* vr = reinterpret_cast<float*>(dst + L.o_vr);
-    float* rr = reinterpret_cast<float*>(dst + L.o_rr);
-    for (int i = 0; i < sc->n_waypoints; ++i) {
-        const double* w = sc->waypoints + 4 * i;
-        xy[i] = make_float2((float)(w[0] - origin[0]), (float)(w[1] - origin[1]));
-        vr[i] = (float)w[3];
-    }
-    for (int i = 0; i < sc->n_circles; ++i) {
-        const double* o = sc->circles + 5 * i;
-        pv[i] = make_float4((float)(o[0] - origin[0]), (float)(o[1] - origin[1]), (float)o[3],
-                            (float)o[4]);
-        rr[i] = (float)(o[2] + c.ego_r);
-    }
 }
 
 mppi_status validate_config(const mppi_config* c)
@@ -240,27 +110,62 @@ mppi_status usable(mppi_t* h)
     return MPPI_OK;
 }
 
-// ---- launch-shape tuning table ----------------------------------------------
+// ---- scene staging ------------------------------------------------------------
+
+SceneLayout scene_layout(int n_wp, int n_c)
+{
+    SceneLayout L;
+    L.o_pv = 0;
+    L.o_xy = L.o_pv + align_up((size_t)n_c * 16, 16);
+    L.o_vr = L.o_xy + align_up((size_t)n_wp * 8, 16);
+    L.o_rr = L.o_vr + align_up((size_t)n_wp * 4, 16);
+    L.bytes = L.o_rr + align_up((size_t)n_c * 4, 16);
+    return L;
+}
+
+// Ego-frame float32 copy of the scene (float64 subtraction of the origin).
+void write_scene(unsigned char* dst, const SceneLayout& L, const mppi_config& c,
+                 const double origin[2], const mppi_scene* sc)
+{
+    float4* pv = reinterpret_cast<float4*>(dst + L.o_pv);
+    float2* xy = reinterpret_cast<float2*>(dst + L.o_xy);
+    float* vr = reinterpret_cast<float*>(dst + L.o_vr);
+    float* rr = reinterpret_cast<float*>(dst + L.o_rr);
+    for (int i = 0; i < sc->n_waypoints; ++i) {
+        const double* w = sc->waypoints + 4 * i;
+        xy[i] = make_float2((float)(w[0] - origin[0]), (float)(w[1] - origin[1]));
+        vr[i] = (float)w[3];
+    }
+    for (int i = 0; i < sc->n_circles; ++i) {
+        const double* o = sc->circles + 5 * i;
+        pv[i] = make_float4((float)(o[0] - origin[0]), (float)(o[1] - origin[1]), (float)o[3],
+                            (float)o[4]);
+        rr[i] = (float)(o[2] + c.ego_r);
+    }
+}
+
+// ---- launch-shape tuning table ------------------------------------------------
 // Lines "k_log2 t_bucket c_bucket lanes" written by the autotuner
 // (paper_2308_01654_amd/autotune.py) into tuning.txt next to the library, or
 // the file named by MPPI_TUNING_FILE.  A shape's lanes per sample depends only
 // on its own (K, T, circle count).
+
 struct TuneEntry {
     int k, t, c, lanes;
 };
-std::vector<TuneEntry> g_tune;
-std::once_flag g_tune_once;
+static std::vector<TuneEntry> g_tune;
+static std::once_flag g_tune_once;
 
-int k_bucket(int K)
+static int k_bucket(int K)
 {
     int b = 0;
     while ((1 << b) < K && b < 30) ++b;
     return b;
 }
-int t_bucket(int T) { return T <= 32 ? 0 : T <= 64 ? 1 : T <= 128 ? 2 : T <= 256 ? 3 : 4; }
-int c_bucket(int n) { return n == 0 ? 0 : n <= 16 ? 1 : n <= 64 ? 2 : n <= 256 ? 3 : 4; }
+static int t_bucket(int T) { return T <= 32 ? 0 : T <= 64 ? 1 : T <= 128 ? 2 : T <= 256 ? 3 : 4; }
+static int c_bucket(int n) { return n == 0 ? 0 : n <= 16 ? 1 : n <= 64 ? 2 : n <= 256 ? 3 : 4; }
 
-void load_tuning()
+static void load_tuning()
 {
     std::string path;
     if (const char* e = getenv("MPPI_TUNING_FILE")) {
@@ -287,14 +192,13 @@ void load_tuning()
     fclose(f);
 }
 
-int heuristic_lanes(const mppi_config& c)
+static int heuristic_lanes(const mppi_config& c)
 {
     // Enough lanes to give every SIMD of the 256 CUs two waves.
     const long target = 2L * 256 * 4 * 64;
-    int g = next_pow2((target + c.K - 1) / c.K);
-    g = std::min(g, 16);
-    while (g > 1 && g > c.T) g >>= 1;
-    return std::max(g, 1);
+    int g = 1;
+    while (g < 16 && (long)g * c.K < target) g <<= 1;
+    return g;
 }
 
 int auto_lanes(const mppi_config& c, int n_c)
@@ -309,18 +213,20 @@ int auto_lanes(const mppi_config& c, int n_c)
     return g;
 }
 
+// ---- profiling --------------------------------------------------------------------
+
 mppi_status record_launch(mppi_t* h, int kind, hipEvent_t* a)
 {
-    if (!h->prof) return MPPI_OK;
+    (void)kind;
+    if (!h || !h->prof) return MPPI_OK;
     HIP_TRY(hipEventCreate(a));
     HIP_TRY(hipEventRecord(*a, h->stream));
-    (void)kind;
     return MPPI_OK;
 }
 
 mppi_status record_end(mppi_t* h, int kind, hipEvent_t a)
 {
-    if (!h->prof) return MPPI_OK;
+    if (!h || !h->prof) return MPPI_OK;
     hipEvent_t b;
     HIP_TRY(hipEventCreate(&b));
     HIP_TRY(hipEventRecord(b, h->stream));
@@ -328,7 +234,7 @@ mppi_status record_end(mppi_t* h, int kind, hipEvent_t a)
     return MPPI_OK;
 }
 
-mppi_status drain_profile(mppi_t* h)
+static mppi_status drain_profile(mppi_t* h)
 {
     if (h->events.empty()) return MPPI_OK;
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -345,7 +251,7 @@ mppi_status drain_profile(mppi_t* h)
 }
 
 template <typename F>
-mppi_status launch_aux(mppi_t* h, F&& f)
+static mppi_status launch_aux(mppi_t* h, F&& f)
 {
     hipEvent_t a = nullptr;
     mppi_status s = record_launch(h, 1, &a);
@@ -354,17 +260,20 @@ mppi_status launch_aux(mppi_t* h, F&& f)
     return record_end(h, 1, a);
 }
 
-mppi_status sync_status(mppi_t* h)
+static mppi_status sync_status(mppi_t* h)
 {
     HIP_TRY(hipStreamSynchronize(h->stream));
     if (!h->stepped) return MPPI_OK;
     DevState st;
     HIP_TRY(hipMemcpy(&st, h->st, sizeof st, hipMemcpyDeviceToHost));
-    if (st.status != 0) return fail(MPPI_E_NONFINITE, "every sample cost of the last step was non-finite");
+    if (st.status != 0)
+        return fail(MPPI_E_NONFINITE, "every sample cost of the last step was non-finite");
     return MPPI_OK;
 }
 
-void release(mppi_t* h)
+// ---- handles ----------------------------------------------------------------------
+
+void handle_release(mppi_t* h)
 {
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     for (const ProfEvent& e : h->events) {
@@ -380,17 +289,7 @@ void release(mppi_t* h)
     (void)hipFree(h->st);
     (void)hipFree(h->scene);
     if (h->batch) {
-        BatchWs* b = h->batch;
-        for (GraphEntry& g : b->graphs) {
-            (void)hipGraphExecDestroy(g.exec);
-            (void)hipGraphDestroy(g.graph);
-        }
-        (void)hipFree(b->arena);
-        for (int i = 0; i < 2; ++i) {
-            if (b->stage[i]) (void)hipHostFree(b->stage[i]);
-            if (b->done[i]) (void)hipEventDestroy(b->done[i]);
-        }
-        delete b;
+        ws_destroy(h->batch);
         h->batch = nullptr;
     }
     for (int i = 0; i < 2; ++i) {
@@ -400,29 +299,8 @@ void release(mppi_t* h)
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* mppi_version(void) { return "mppi-mi355x 0.1 (gfx950)"; }
-
-const char* mppi_status_str(mppi_status s)
-{
-    switch (s) {
-    case MPPI_OK: return "ok";
-    case MPPI_E_INVALID: return "invalid argument";
-    case MPPI_E_NOMEM: return "out of memory";
-    case MPPI_E_DEVICE: return "device failure";
-    case MPPI_E_NONFINITE: return "all sample costs non-finite";
-    case MPPI_E_BUSY: return "busy";
-    case MPPI_E_NOT_READY: return "not ready";
-    default: return "unknown status";
-    }
-}
-
-const char* mppi_last_error(void) { return g_last_error.c_str(); }
-
-mppi_status mppi_create(const mppi_config* cfg, void* hip_stream, mppi_t** out)
+mppi_status handle_create(const mppi_config* cfg, void* hip_stream, bool with_scratch,
+                          mppi_t** out)
 {
     if (!out) return fail(MPPI_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -435,7 +313,7 @@ mppi_status mppi_create(const mppi_config* cfg, void* hip_stream, mppi_t** out)
     h->max_tiles = (K + (kBlock / 16) - 1) / (kBlock / 16);
     h->scene_cap = scene_bytes(cfg->max_waypoints, cfg->max_circles);
     auto bail = [&](mppi_status st, const char* what, hipError_t e) {
-        release(h);
+        handle_release(h);
         delete h;
         return fail(st, "%s: %s", what, hipGetErrorString(e));
     };
@@ -447,71 +325,39 @@ mppi_status mppi_create(const mppi_config* cfg, void* hip_stream, mppi_t** out)
             return bail(MPPI_E_DEVICE, "hipStreamCreate", e);
         h->own_stream = true;
     }
-    struct { void** p; size_t n; } allocs[] = {
-        {(void**)&h->U, sizeof(double) * 2 * T},
-        {(void**)&h->S, sizeof(float) * K},
-        {(void**)&h->eps, sizeof(float2) * (size_t)T * K},
-        {(void**)&h->partials, sizeof(double) * (size_t)h->max_tiles * (kPartialHead + 2 * T)},
-        {(void**)&h->scales, sizeof(double) * (size_t)h->max_tiles},
-        {(void**)&h->wbuf, sizeof(double) * (size_t)K},
-        {(void**)&h->st, sizeof(DevState)},
-        {(void**)&h->scene, h->scene_cap},
-    };
-    for (auto& a : allocs)
-        if ((e = hipMalloc(a.p, a.n)) != hipSuccess) return bail(MPPI_E_NOMEM, "hipMalloc", e);
-    for (int i = 0; i < 2; ++i) {
-        if ((e = hipHostMalloc((void**)&h->staging[i], h->scene_cap, hipHostMallocDefault)) != hipSuccess)
-            return bail(MPPI_E_NOMEM, "hipHostMalloc", e);
-        if ((e = hipEventCreateWithFlags(&h->staged[i], hipEventDisableTiming)) != hipSuccess)
-            return bail(MPPI_E_DEVICE, "hipEventCreate", e);
+    if ((e = hipMalloc((void**)&h->U, sizeof(double) * 2 * T)) != hipSuccess ||
+        (e = hipMalloc((void**)&h->st, sizeof(DevState))) != hipSuccess)
+        return bail(MPPI_E_NOMEM, "hipMalloc", e);
+    if (with_scratch) {
+        struct { void** p; size_t n; } allocs[] = {
+            {(void**)&h->S, sizeof(float) * K},
+            {(void**)&h->eps, sizeof(float2) * (size_t)T * K},
+            {(void**)&h->partials, sizeof(double) * (size_t)h->max_tiles * (kPartialHead + 2 * T)},
+            {(void**)&h->scales, sizeof(double) * (size_t)h->max_tiles},
+            {(void**)&h->wbuf, sizeof(double) * (size_t)K},
+            {(void**)&h->scene, h->scene_cap},
+        };
+        for (auto& a : allocs)
+            if ((e = hipMalloc(a.p, a.n)) != hipSuccess) return bail(MPPI_E_NOMEM, "hipMalloc", e);
+        for (int i = 0; i < 2; ++i) {
+            if ((e = hipHostMalloc((void**)&h->staging[i], h->scene_cap, hipHostMallocDefault)) !=
+                hipSuccess)
+                return bail(MPPI_E_NOMEM, "hipHostMalloc", e);
+            if ((e = hipEventCreateWithFlags(&h->staged[i], hipEventDisableTiming)) != hipSuccess)
+                return bail(MPPI_E_DEVICE, "hipEventCreate", e);
+        }
+        if ((e = hipMemsetAsync(h->S, 0, sizeof(float) * K, h->stream)) != hipSuccess)
+            return bail(MPPI_E_DEVICE, "initialise device state", e);
     }
     if ((e = hipMemsetAsync(h->U, 0, sizeof(double) * 2 * T, h->stream)) != hipSuccess ||
         (e = hipMemsetAsync(h->st, 0, sizeof(DevState), h->stream)) != hipSuccess ||
-        (e = hipMemsetAsync(h->S, 0, sizeof(float) * K, h->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(h->stream)) != hipSuccess)
         return bail(MPPI_E_DEVICE, "initialise device state", e);
     if (const char* env = getenv("MPPI_LANES_PER_SAMPLE")) {
-        int g = atoi(env);
+        const int g = atoi(env);
         if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16) h->lanes_req = g;
     }
     *out = h;
-    return MPPI_OK;
-}
-
-mppi_status mppi_destroy(mppi_t* h)
-{
-    if (!h) return MPPI_OK;
-    release(h);
-    delete h;
-    return MPPI_OK;
-}
-
-mppi_status mppi_set_scene(mppi_t* h, const double x0[4], const mppi_scene* sc)
-{
-    mppi_status s = usable(h);
-    if (s != MPPI_OK) return s;
-    if ((s = validate_scene(h->cfg, x0, sc)) != MPPI_OK) return s;
-    const int b = h->cur;
-    if (h->staged_pending[b]) {
-        HIP_TRY(hipEventSynchronize(h->staged[b]));
-        h->staged_pending[b] = false;
-    }
-    const SceneLayout L = scene_layout(sc->n_waypoints, sc->n_circles);
-    const double origin[2] = {x0[0], x0[1]};
-    write_scene(h->staging[b], L, h->cfg, origin, sc);
-    HIP_TRY(hipMemcpyAsync(h->scene, h->staging[b], L.bytes, hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(hipEventRecord(h->staged[b], h->stream));
-    h->staged_pending[b] = true;
-    h->cur ^= 1;
-    h->has_scene = true;
-    h->origin[0] = origin[0];
-    h->origin[1] = origin[1];
-    h->n_wp = sc->n_waypoints;
-    h->n_c = sc->n_circles;
-    h->o_pv = L.o_pv;
-    h->o_xy = L.o_xy;
-    h->o_vr = L.o_vr;
-    h->o_rr = L.o_rr;
     return MPPI_OK;
 }
 
@@ -555,6 +401,7 @@ void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double or
     d.key0 = (uint32_t)c.seed;
     d.key1 = (uint32_t)(c.seed >> 32);
     d.shift = shift;
+    d.out_slot = -1;
     d.c_pv = reinterpret_cast<const float4*>(scene + L.o_pv);
     d.wp_xy = reinterpret_cast<const float2*>(scene + L.o_xy);
     d.wp_vref = reinterpret_cast<const float*>(scene + L.o_vr);
@@ -567,42 +414,9 @@ void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double or
     d.st = h->st;
 }
 
-mppi_status mppi_step_resident(mppi_t* h, const double x0[4])
-{
-    mppi_status s = usable(h);
-    if (s != MPPI_OK) return s;
-    if (!h->has_scene) return fail(MPPI_E_INVALID, "no scene has been set");
-    if (!x0) return fail(MPPI_E_INVALID, "x0 must not be NULL");
-    for (int i = 0; i < 4; ++i)
-        if (!isfinite(x0[i])) return fail(MPPI_E_INVALID, "x0[%d] is not finite", i);
-    SceneLayout L;
-    L.o_pv = h->o_pv;
-    L.o_xy = h->o_xy;
-    L.o_vr = h->o_vr;
-    L.o_rr = h->o_rr;
-    InstDesc d;
-    fill_desc(d, h, x0, h->origin, h->scene, L, h->n_wp, h->n_c, 0);
-    const size_t smem = lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes).total;
-    hipEvent_t a = nullptr;
-    if ((s = record_launch(h, 0, &a)) != MPPI_OK) return s;
-    HIP_TRY(launch_batch(d.lanes, active_ego(d.n_ego, d.n_c), &d, nullptr, 0, d.n_tiles, smem,
-                         h->stream));
-    if ((s = record_end(h, 0, a)) != MPPI_OK) return s;
-    h->last_lanes = d.lanes;
-    h->stepped = true;
-    return MPPI_OK;
-}
+// ---- batched launches ---------------------------------------------------------------
 
-namespace {
-
-size_t pow2_at_least(size_t v, size_t lo)
-{
-    size_t p = lo;
-    while (p < v) p <<= 1;
-    return p;
-}
-
-bool graphs_enabled()
+static bool graphs_enabled()
 {
     static int on = -1;
     if (on < 0) {
@@ -627,7 +441,7 @@ mppi_status ws_create(BatchWs** out)
     return MPPI_OK;
 }
 
-void ws_drop_graphs(BatchWs* b)
+static void ws_drop_graphs(BatchWs* b)
 {
     for (GraphEntry& g : b->graphs) {
         (void)hipGraphExecDestroy(g.exec);
@@ -636,7 +450,21 @@ void ws_drop_graphs(BatchWs* b)
     b->graphs.clear();
 }
 
-hipError_t ws_reserve(BatchWs* b, size_t cap, hipStream_t stream)
+void ws_destroy(BatchWs* b)
+{
+    if (!b) return;
+    for (int i = 0; i < 2; ++i)
+        if (b->pending[i]) (void)hipEventSynchronize(b->done[i]);
+    ws_drop_graphs(b);
+    (void)hipFree(b->arena);
+    for (int i = 0; i < 2; ++i) {
+        if (b->stage[i]) (void)hipHostFree(b->stage[i]);
+        if (b->done[i]) (void)hipEventDestroy(b->done[i]);
+    }
+    delete b;
+}
+
+static hipError_t ws_reserve(BatchWs* b, size_t cap, hipStream_t stream)
 {
     if (b->cap >= cap) return hipSuccess;
     hipError_t e = hipStreamSynchronize(stream);
@@ -658,16 +486,11 @@ hipError_t ws_reserve(BatchWs* b, size_t cap, hipStream_t stream)
     return hipSuccess;
 }
 
-}  // namespace
-
-// Enqueue one iteration of every handle hs[0..n) as one persistent launch on
-// `stream` (captured once per arena/LDS size class as a graph and replayed).
-// scenes == NULL: each handle's resident scene.  shifts: optional per-handle
-// warm-start shift flags.  Used by mppi_step_batch and the server.
 mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, const double* x0s,
-                          const mppi_scene* scenes, const int32_t* shifts, int n, mppi_t* prof)
+                          const mppi_scene* scenes, const InstExtra* extra, int n, mppi_t* prof,
+                          double* gather_dev, int slot_doubles)
 {
-    mppi_t* h = prof;  // for HIP_TRY's sticky flag
+    mppi_t* h = prof;  // HIP_TRY marks it unusable on a device failure
     const size_t off_prefix = align_up(sizeof(BatchHdr), 16);
     const size_t off_descs = align_up(off_prefix + sizeof(int) * (size_t)(n + 1), 16);
     size_t bytes = align_up(off_descs + sizeof(InstDesc) * (size_t)n, 16);
@@ -682,29 +505,26 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
     }
     const size_t bucket = pow2_at_least(bytes, 64 << 10);
     HIP_TRY(ws_reserve(ws, bucket, stream));
-    const BatchHdr* hdr_dev = reinterpret_cast<const BatchHdr*>(ws->arena);  // after reserve
+    const BatchHdr* hdr_dev = reinterpret_cast<const BatchHdr*>(ws->arena);
     const int b = ws->cur;
     if (ws->pending[b]) {
         HIP_TRY(hipEventSynchronize(ws->done[b]));
         ws->pending[b] = false;
     }
     unsigned char* host = ws->stage[b];
-    // longest tiles first
-    std::vector<int> order(n);
+
+    // group by kernel variant, longest tiles first inside a group
+    std::vector<int> order(n), cls(n);
     std::vector<double> work(n);
     for (int i = 0; i < n; ++i) {
         const mppi_config& c = hs[i]->cfg;
         const int nw = scenes ? scenes[i].n_waypoints : hs[i]->n_wp;
         const int nc = scenes ? scenes[i].n_circles : hs[i]->n_c;
-        order[i] = i;
-        work[i] = (double)c.T * (73.0 + 6.0 * nw + 7.0 * c.n_ego * nc);
-    }
-    std::vector<int> cls(n);
-    for (int i = 0; i < n; ++i) {
-        const int nc = scenes ? scenes[i].n_circles : hs[i]->n_c;
-        const int g = hs[i]->lanes_req ? hs[i]->lanes_req : auto_lanes(hs[i]->cfg, nc);
+        const int g = hs[i]->lanes_req ? hs[i]->lanes_req : auto_lanes(c, nc);
         const int gi = g == 1 ? 0 : g == 2 ? 1 : g == 4 ? 2 : g == 8 ? 3 : 4;
-        cls[i] = 5 * gi + active_ego(hs[i]->cfg.n_ego, nc);
+        order[i] = i;
+        cls[i] = 5 * gi + active_ego(c.n_ego, nc);
+        work[i] = (double)c.T * (73.0 + 6.0 * nw + 7.0 * c.n_ego * nc);
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
         return cls[a] != cls[c] ? cls[a] < cls[c] : work[a] > work[c];
@@ -714,24 +534,28 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
     InstDesc* descs = reinterpret_cast<InstDesc*>(host + off_descs);
     long total = 0;
     size_t smem = 0;
-    int any_shift = 0;
+    int any_shift = 0, any_out = 0;
     for (int j = 0; j < n; ++j) {
         const int i = order[j];
         mppi_t* hi = hs[i];
         const double* x0 = x0s + 4 * i;
-        const int sh = shifts ? (shifts[i] ? 1 : 0) : 0;
+        const InstExtra* ex = extra ? &extra[i] : nullptr;
+        const int sh = ex && ex->shift ? 1 : 0;
         if (scenes) {
             const double origin[2] = {x0[0], x0[1]};
             write_scene(host + soff[i], lay[i], hi->cfg, origin, &scenes[i]);
             fill_desc(descs[j], hi, x0, origin, ws->arena + soff[i], lay[i], scenes[i].n_waypoints,
                       scenes[i].n_circles, sh);
         } else {
-            SceneLayout L;
-            L.o_pv = hi->o_pv;
-            L.o_xy = hi->o_xy;
-            L.o_vr = hi->o_vr;
-            L.o_rr = hi->o_rr;
-            fill_desc(descs[j], hi, x0, hi->origin, hi->scene, L, hi->n_wp, hi->n_c, sh);
+            fill_desc(descs[j], hi, x0, hi->origin, hi->scene, hi->lay, hi->n_wp, hi->n_c, sh);
+        }
+        if (ex) {
+            descs[j].S = ex->S;
+            descs[j].eps = ex->eps;
+            descs[j].partials = ex->partials;
+            descs[j].scales = ex->scales;
+            descs[j].out_slot = ex->out_slot;
+            any_out |= ex->out_slot >= 0;
         }
         prefix[j] = (int)total;
         total += descs[j].n_tiles;
@@ -757,16 +581,21 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
         hdr->cls_begin[kLaneClasses] = n;
     }
     const size_t smem_b = align_up(smem, 4096);
+    const int n_blocks = (int)pow2_at_least((size_t)n, 1);
+    const int shift_blocks = any_shift ? n_blocks : 0;
+    const int gather_blocks = (gather_dev && any_out) ? n_blocks : 0;
     static const int kClassLanes[5] = {1, 2, 4, 8, 16};
-    auto enqueue_kernels = [&]() -> hipError_t {
-        hipError_t e = hipSuccess;
+    auto enqueue_device_work = [&](size_t copy_bytes) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(ws->arena, host, copy_bytes, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess && shift_blocks) e = launch_shift_batch(hdr_dev, shift_blocks, stream);
         for (int c = 0; c < kLaneClasses && e == hipSuccess; ++c)
             if (grids[c] > 0)
                 e = launch_batch(kClassLanes[c / 5], c % 5, nullptr, hdr_dev, c, grids[c], smem_b,
                                  stream);
+        if (e == hipSuccess && gather_blocks)
+            e = launch_gather(hdr_dev, gather_blocks, gather_dev, slot_doubles, stream);
         return e;
     };
-    const int shift_blocks = any_shift ? (int)pow2_at_least((size_t)n, 1) : 0;
 
     hipEvent_t a = nullptr;
     mppi_status s = record_launch(prof, 0, &a);
@@ -775,23 +604,22 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
         GraphEntry* ge = nullptr;
         for (GraphEntry& g : ws->graphs)
             if (g.bytes == bucket && g.smem == smem_b && g.buf == b &&
-                g.shift_blocks == shift_blocks && memcmp(g.grids, grids, sizeof grids) == 0)
+                g.shift_blocks == shift_blocks + 4096 * gather_blocks &&
+                memcmp(g.grids, grids, sizeof grids) == 0)
                 ge = &g;
         if (!ge) {
-            if (ws->graphs.size() >= 32) ws_drop_graphs(ws);
+            if (ws->graphs.size() >= 64) ws_drop_graphs(ws);
             GraphEntry g;
             g.bytes = bucket;
             g.smem = smem_b;
             memcpy(g.grids, grids, sizeof grids);
             g.buf = b;
-            g.shift_blocks = shift_blocks;
+            g.shift_blocks = shift_blocks + 4096 * gather_blocks;
             g.graph = nullptr;
             g.exec = nullptr;
             HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-            hipError_t e = hipMemcpyAsync(ws->arena, host, bucket, hipMemcpyHostToDevice, stream);
-            if (e == hipSuccess && shift_blocks) e = launch_shift_batch(hdr_dev, shift_blocks, stream);
-            if (e == hipSuccess) e = enqueue_kernels();
-            hipError_t e2 = hipStreamEndCapture(stream, &g.graph);
+            const hipError_t e = enqueue_device_work(bucket);
+            const hipError_t e2 = hipStreamEndCapture(stream, &g.graph);
             HIP_TRY(e);
             HIP_TRY(e2);
             HIP_TRY(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
@@ -800,9 +628,7 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
         }
         HIP_TRY(hipGraphLaunch(ge->exec, stream));
     } else {
-        HIP_TRY(hipMemcpyAsync(ws->arena, host, bytes, hipMemcpyHostToDevice, stream));
-        if (shift_blocks) HIP_TRY(launch_shift_batch(hdr_dev, shift_blocks, stream));
-        HIP_TRY(enqueue_kernels());
+        HIP_TRY(enqueue_device_work(bytes));
     }
     if ((s = record_end(prof, 0, a)) != MPPI_OK) return s;
     HIP_TRY(hipEventRecord(ws->done[b], stream));
@@ -815,6 +641,99 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
     return MPPI_OK;
 }
 
+}  // namespace mppi_impl
+
+// =====================================================================================
+// C ABI
+// =====================================================================================
+
+extern "C" {
+
+const char* mppi_version(void) { return "mppi-mi355x 0.2 (gfx950)"; }
+
+const char* mppi_status_str(mppi_status s)
+{
+    switch (s) {
+    case MPPI_OK: return "ok";
+    case MPPI_E_INVALID: return "invalid argument";
+    case MPPI_E_NOMEM: return "out of memory";
+    case MPPI_E_DEVICE: return "device failure";
+    case MPPI_E_NONFINITE: return "all sample costs non-finite";
+    case MPPI_E_BUSY: return "busy";
+    case MPPI_E_NOT_READY: return "not ready";
+    default: return "unknown status";
+    }
+}
+
+const char* mppi_last_error(void) { return g_last_error.c_str(); }
+
+mppi_status mppi_create(const mppi_config* cfg, void* hip_stream, mppi_t** out)
+{
+    return handle_create(cfg, hip_stream, true, out);
+}
+
+mppi_status mppi_destroy(mppi_t* h)
+{
+    if (!h) return MPPI_OK;
+    handle_release(h);
+    delete h;
+    return MPPI_OK;
+}
+
+mppi_status mppi_set_scene(mppi_t* h, const double x0[4], const mppi_scene* sc)
+{
+    mppi_status s = usable(h);
+    if (s != MPPI_OK) return s;
+    if ((s = validate_scene(h->cfg, x0, sc)) != MPPI_OK) return s;
+    const int b = h->cur;
+    if (h->staged_pending[b]) {
+        HIP_TRY(hipEventSynchronize(h->staged[b]));
+        h->staged_pending[b] = false;
+    }
+    const SceneLayout L = scene_layout(sc->n_waypoints, sc->n_circles);
+    const double origin[2] = {x0[0], x0[1]};
+    write_scene(h->staging[b], L, h->cfg, origin, sc);
+    HIP_TRY(hipMemcpyAsync(h->scene, h->staging[b], L.bytes, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipEventRecord(h->staged[b], h->stream));
+    h->staged_pending[b] = true;
+    h->cur ^= 1;
+    h->has_scene = true;
+    h->origin[0] = origin[0];
+    h->origin[1] = origin[1];
+    h->n_wp = sc->n_waypoints;
+    h->n_c = sc->n_circles;
+    h->lay = L;
+    return MPPI_OK;
+}
+
+mppi_status mppi_step_resident(mppi_t* h, const double x0[4])
+{
+    mppi_status s = usable(h);
+    if (s != MPPI_OK) return s;
+    if (!h->has_scene) return fail(MPPI_E_INVALID, "no scene has been set");
+    if (!x0) return fail(MPPI_E_INVALID, "x0 must not be NULL");
+    for (int i = 0; i < 4; ++i)
+        if (!isfinite(x0[i])) return fail(MPPI_E_INVALID, "x0[%d] is not finite", i);
+    InstDesc d;
+    fill_desc(d, h, x0, h->origin, h->scene, h->lay, h->n_wp, h->n_c, 0);
+    const size_t smem = lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes).total;
+    hipEvent_t a = nullptr;
+    if ((s = record_launch(h, 0, &a)) != MPPI_OK) return s;
+    HIP_TRY(launch_batch(d.lanes, active_ego(d.n_ego, d.n_c), &d, nullptr, 0, d.n_tiles, smem,
+                         h->stream));
+    if ((s = record_end(h, 0, a)) != MPPI_OK) return s;
+    h->last_lanes = d.lanes;
+    h->stepped = true;
+    return MPPI_OK;
+}
+
+mppi_status mppi_step(mppi_t* h, const double x0[4], const mppi_scene* sc)
+{
+    mppi_status s = mppi_set_scene(h, x0, sc);
+    if (s != MPPI_OK) return s;
+    return mppi_step_resident(h, x0);
+}
+
 mppi_status mppi_step_batch(mppi_t* const* hs, const double* x0s, const mppi_scene* scenes,
                             int32_t n)
 {
@@ -823,6 +742,7 @@ mppi_status mppi_step_batch(mppi_t* const* hs, const double* x0s, const mppi_sce
     mppi_status s;
     for (int i = 0; i < n; ++i) {
         if ((s = usable(hs[i])) != MPPI_OK) return s;
+        if (!hs[i]->S) return fail(MPPI_E_INVALID, "handle %d has no iteration buffers", i);
         if (hs[i]->stream != lead->stream)
             return fail(MPPI_E_INVALID, "every handle of a batch must use the same stream");
         for (int j = 0; j < i; ++j)
@@ -836,14 +756,7 @@ mppi_status mppi_step_batch(mppi_t* const* hs, const double* x0s, const mppi_sce
         }
     }
     if (!lead->batch && (s = ws_create(&lead->batch)) != MPPI_OK) return s;
-    return batch_enqueue(lead->batch, lead->stream, hs, x0s, scenes, nullptr, n, lead);
-}
-
-mppi_status mppi_step(mppi_t* h, const double x0[4], const mppi_scene* sc)
-{
-    mppi_status s = mppi_set_scene(h, x0, sc);
-    if (s != MPPI_OK) return s;
-    return mppi_step_resident(h, x0);
+    return batch_enqueue(lead->batch, lead->stream, hs, x0s, scenes, nullptr, n, lead, nullptr, 0);
 }
 
 mppi_status mppi_sync(mppi_t* h)
@@ -932,17 +845,16 @@ mppi_status mppi_get_weights(mppi_t* h, double* out, size_t n)
     if (!out || n < (size_t)h->cfg.K) return fail(MPPI_E_INVALID, "buffer needs K doubles");
     if ((s = sync_status(h)) != MPPI_OK) return s;
     if (!h->stepped) return fail(MPPI_E_NOT_READY, "no step has completed");
-    double* w = h->wbuf;
     InstDesc d;
     memset(&d, 0, sizeof d);
     d.K = h->cfg.K;
     d.S = h->S;
     d.lambda = h->cfg.lambda;
     d.st = h->st;
-    s = launch_aux(h, [&] { return launch_weights(d, w, h->stream); });
+    s = launch_aux(h, [&] { return launch_weights(d, h->wbuf, h->stream); });
     if (s != MPPI_OK) return s;
     HIP_TRY(hipStreamSynchronize(h->stream));
-    HIP_TRY(hipMemcpy(out, w, sizeof(double) * h->cfg.K, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(out, h->wbuf, sizeof(double) * h->cfg.K, hipMemcpyDeviceToHost));
     return MPPI_OK;
 }
 

@@ -1,0 +1,144 @@
+// Host-side internals of the MPPI library shared by the C-ABI runtime
+// (mppi_api.hip) and the request server (mppi_server.hip).  Not part of the
+// public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mppi.h"
+#include "mppi_internal.hpp"
+
+namespace mppi_impl {
+
+mppi_status fail(mppi_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+// A captured batch launch: arena copy + kernels, for one size class.
+struct GraphEntry {
+    size_t bytes, smem;
+    int grids[kLaneClasses];
+    int buf, shift_blocks;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+// Staging and device arena of batched launches (descriptors + scenes), and
+// the instantiated graphs that replay them.
+struct BatchWs {
+    unsigned char* arena = nullptr;
+    unsigned char* stage[2] = {nullptr, nullptr};
+    size_t cap = 0;
+    hipEvent_t done[2] = {nullptr, nullptr};
+    bool pending[2] = {false, false};
+    int cur = 0;
+    std::vector<GraphEntry> graphs;
+};
+
+struct ProfEvent {
+    hipEvent_t a, b;
+    int kind;  // 0 = iteration kernel, 1 = auxiliary
+};
+
+// Offsets of the four scene arrays inside a staged scene block.
+struct SceneLayout {
+    size_t o_pv, o_xy, o_vr, o_rr, bytes;
+};
+
+// Per-instance extras of a batched launch: scratch buffers that replace the
+// handle's own (server vehicles own no scratch), the warm-start shift flag,
+// and the slot of the instance in the gathered result buffer (-1: none).
+struct InstExtra {
+    float* S;
+    float2* eps;
+    double* partials;
+    double* scales;
+    int shift;
+    int out_slot;
+};
+
+}  // namespace mppi_impl
+
+// One planning instance (opaque mppi_t of the C ABI).
+struct mppi {
+    mppi_config cfg;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int lanes_req = 0;  // 0 = tuning table
+    int last_lanes = 0;
+    mppi_status sticky = MPPI_OK;
+    // device memory
+    double* U = nullptr;
+    float* S = nullptr;
+    float2* eps = nullptr;
+    double* partials = nullptr;
+    double* scales = nullptr;
+    double* wbuf = nullptr;  // [K] weights export
+    mppi_impl::DevState* st = nullptr;
+    unsigned char* scene = nullptr;
+    size_t scene_cap = 0;
+    // pinned scene staging, double-buffered
+    unsigned char* staging[2] = {nullptr, nullptr};
+    hipEvent_t staged[2] = {nullptr, nullptr};
+    bool staged_pending[2] = {false, false};
+    int cur = 0;
+    int max_tiles = 0;
+    mppi_impl::BatchWs* batch = nullptr;  // created when this handle leads a batch
+    // resident scene
+    bool has_scene = false;
+    double origin[2] = {0.0, 0.0};
+    int n_wp = 0, n_c = 0;
+    mppi_impl::SceneLayout lay = {0, 0, 0, 0, 0};
+    // last step
+    bool stepped = false;
+    // profiling
+    bool prof = false;
+    std::vector<mppi_impl::ProfEvent> events;
+    double prof_ms[2] = {0.0, 0.0};
+    int64_t prof_n[2] = {0, 0};
+};
+
+namespace mppi_impl {
+
+// Reports a HIP failure as MPPI_E_DEVICE (sticky on handle `h`, if any).
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            if (h) h->sticky = MPPI_E_DEVICE;                                                \
+            return ::mppi_impl::fail(MPPI_E_DEVICE, "%s: %s (%s:%d)", #expr,                 \
+                                     hipGetErrorString(e_), __FILE__, __LINE__);            \
+        }                                                                                    \
+    } while (0)
+
+SceneLayout scene_layout(int n_wp, int n_c);
+void write_scene(unsigned char* dst, const SceneLayout& L, const mppi_config& c,
+                 const double origin[2], const mppi_scene* sc);
+mppi_status validate_scene(const mppi_config& c, const double x0[4], const mppi_scene* sc);
+mppi_status validate_config(const mppi_config* c);
+mppi_status usable(mppi_t* h);
+int auto_lanes(const mppi_config& c, int n_c);
+size_t pow2_at_least(size_t v, size_t lo);
+mppi_status record_launch(mppi_t* h, int kind, hipEvent_t* a);
+mppi_status record_end(mppi_t* h, int kind, hipEvent_t a);
+void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double origin[2],
+               const unsigned char* scene, const SceneLayout& L, int n_wp, int n_c, int shift);
+mppi_status ws_create(BatchWs** out);
+void ws_destroy(BatchWs* b);
+// Create a handle; with_scratch = false leaves S/eps/partials/scales/scene
+// unallocated (server vehicles take them from the request pool).
+mppi_status handle_create(const mppi_config* cfg, void* hip_stream, bool with_scratch,
+                          mppi_t** out);
+void handle_release(mppi_t* h);
+// Enqueue one iteration of hs[0..n) as one launch per kernel variant on
+// `stream`.  scenes == nullptr: resident scenes.  extra: optional per-instance
+// scratch/shift/result slot.  gather_dev: optional device buffer receiving,
+// per instance with out_slot >= 0, U [2T] doubles followed by the status and
+// the iteration counter at slot * slot_doubles.
+mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, const double* x0s,
+                          const mppi_scene* scenes, const InstExtra* extra, int n, mppi_t* prof,
+                          double* gather_dev, int slot_doubles);
+
+}  // namespace mppi_impl

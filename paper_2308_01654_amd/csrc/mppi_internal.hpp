@@ -48,6 +48,7 @@ struct InstDesc {
     double lambda;
     uint32_t key0, key1;  // Philox key = seed
     int shift;            // shift U by one step before the iteration (warm start)
+    int out_slot;         // slot in the gathered results of a batch (-1: none)
     // device pointers
     const float2* wp_xy;  // [n_wp]
     const float* wp_vref; // [n_wp]
@@ -110,6 +111,10 @@ hipError_t launch_batch(int lanes, int ne, const InstDesc* d0, const BatchHdr* h
 // Ego circles that take part in the obstacle term of an instance.
 inline int active_ego(int n_ego, int n_c) { return n_c > 0 ? n_ego : 0; }
 hipError_t launch_shift_batch(const BatchHdr* hdr_dev, int n_inst, hipStream_t stream);
+// Copies, for every instance with out_slot >= 0, U [2T], the status and the
+// iteration counter to out + out_slot * slot_doubles.
+hipError_t launch_gather(const BatchHdr* hdr_dev, int n_inst, double* out, int slot_doubles,
+                         hipStream_t stream);
 hipError_t launch_weights(const InstDesc& d, double* w_out, hipStream_t stream);
 hipError_t launch_shift(double* U, int T, int steps, hipStream_t stream);
 hipError_t launch_copy(const float4* src, float4* dst, size_t n16, hipStream_t stream);

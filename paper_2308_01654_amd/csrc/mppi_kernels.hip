@@ -457,6 +457,30 @@ hipError_t launch_shift_batch(const BatchHdr* hdr_dev, int n_inst, hipStream_t s
     return hipGetLastError();
 }
 
+__global__ void k_gather(const BatchHdr* __restrict__ hdr, double* __restrict__ out,
+                         int slot_doubles)
+{
+    const InstDesc* descs = reinterpret_cast<const InstDesc*>(
+        reinterpret_cast<const unsigned char*>(hdr) + hdr->off_descs);
+    const int inst = blockIdx.x;
+    if (inst >= hdr->n_inst) return;
+    const InstDesc& d = descs[inst];
+    if (d.out_slot < 0) return;
+    double* o = out + (size_t)d.out_slot * slot_doubles;
+    for (int i = threadIdx.x; i < 2 * d.T; i += blockDim.x) o[i] = d.U[i];
+    if (threadIdx.x == 0) {
+        o[2 * d.T] = (double)d.st->status;
+        o[2 * d.T + 1] = (double)d.st->n_iter;
+    }
+}
+
+hipError_t launch_gather(const BatchHdr* hdr_dev, int n_inst, double* out, int slot_doubles,
+                         hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_gather, dim3(n_inst), dim3(256), 0, stream, hdr_dev, out, slot_doubles);
+    return hipGetLastError();
+}
+
 // Normalised weights of the last iteration: w_k = exp(-(S_k - S_min)/lambda)/Z.
 __global__ void k_weights(const float* __restrict__ S, int K, double lambda,
                           const DevState* __restrict__ st, double* __restrict__ w)

@@ -72,6 +72,33 @@ class Profile(ctypes.Structure):
     ]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", ctypes.c_uint64), ("n_streams", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32), ("queue_cap", ctypes.c_int32), ("plain", ctypes.c_int32),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+        ("rejected", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+        ("launches", ctypes.c_uint64), ("mean_batch", ctypes.c_double),
+        ("mean_ms", ctypes.c_double), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+        ("p999_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+        ("hbm_peak_bytes", ctypes.c_uint64), ("max_queue", ctypes.c_int32),
+    ]
+
+
+class ReplayPlan(ctypes.Structure):
+    _fields_ = [
+        ("n_requests", ctypes.c_int32), ("vid", ctypes.POINTER(ctypes.c_int32)),
+        ("x0", ctypes.POINTER(ctypes.c_double)), ("scene", ctypes.POINTER(ctypes.c_int32)),
+        ("scenes", ctypes.POINTER(Scene)), ("n_scenes", ctypes.c_int32),
+        ("arrival_ns", ctypes.POINTER(ctypes.c_uint64)),
+    ]
+
+
 # (name, restype, argtypes) of every exported entry point
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -104,6 +131,18 @@ SIGNATURES = [
     ("mppi_debug_philox", _i32, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                                  ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _u32p, _sz]),
     ("mppi_bench_copy", _i32, [_sz, _i32]),
+    ("mppi_server_now_ns", ctypes.c_uint64, []),
+    ("mppi_server_create", _i32, [ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]),
+    ("mppi_server_destroy", _i32, [_vp]),
+    ("mppi_server_add_vehicle", _i32, [_vp, ctypes.POINTER(Config), ctypes.POINTER(_i32)]),
+    ("mppi_server_submit", _i32, [_vp, _i32, _dp, ctypes.POINTER(Scene), ctypes.c_uint64, _u64p]),
+    ("mppi_server_poll", _i32, [_vp, ctypes.c_uint64, _dp, _sz, _u64p]),
+    ("mppi_server_wait_idle", _i32, [_vp]),
+    ("mppi_server_get_stats", _i32, [_vp, ctypes.POINTER(ServerStats)]),
+    ("mppi_server_reset_stats", _i32, [_vp]),
+    ("mppi_server_get_vehicle_state", _i32, [_vp, _i32, _dp, _sz, _u64p, _u64p]),
+    ("mppi_server_set_vehicle_state", _i32, [_vp, _i32, _dp, _sz, ctypes.c_uint64, ctypes.c_uint64]),
+    ("mppi_server_replay", _i32, [_vp, ctypes.POINTER(ReplayPlan), _dp]),
     ("mppi_status_str", ctypes.c_char_p, [_i32]),
     ("mppi_last_error", ctypes.c_char_p, []),
     ("mppi_version", ctypes.c_char_p, []),
@@ -356,3 +395,114 @@ class Planner:
         check(load().mppi_get_profile(self.h, ctypes.byref(p)))
         return dict(iter_ms=p.iter_ms, iter_launches=p.iter_launches, aux_ms=p.aux_ms,
                     aux_launches=p.aux_launches)
+
+
+class Server:
+    """Continuous-batching replanning server (mppi_server_* of the C ABI)."""
+
+    def __init__(self, hbm_budget_bytes=2 << 30, n_streams=3, max_batch=256, queue_cap=1 << 20,
+                 plain=False):
+        c = ServerConfig(int(hbm_budget_bytes), int(n_streams), int(max_batch), int(queue_cap),
+                         1 if plain else 0)
+        h = _vp()
+        check(load().mppi_server_create(ctypes.byref(c), ctypes.byref(h)))
+        self.h = h
+        self.T = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().mppi_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def add_vehicle(self, params, max_waypoints=2048, max_circles=1024):
+        cfg = config_from_params(params, max_waypoints, max_circles)
+        vid = _i32()
+        check(load().mppi_server_add_vehicle(self.h, ctypes.byref(cfg), ctypes.byref(vid)))
+        self.T[vid.value] = cfg.T
+        return vid.value
+
+    def submit(self, vid, x0, waypoints, circles, t_arrival_ns=0, keep=True):
+        scene, keepalive = make_scene(waypoints, circles)
+        x = np.ascontiguousarray(np.asarray(x0, dtype=np.float64))
+        t = ctypes.c_uint64()
+        check(load().mppi_server_submit(self.h, int(vid), x.ctypes.data_as(_dp),
+                                        ctypes.byref(scene), int(t_arrival_ns),
+                                        ctypes.byref(t) if keep else None))
+        del keepalive
+        return t.value
+
+    def poll(self, ticket, vid):
+        """Returns (controls [T][2], t_done_ns) or None while not ready."""
+        U = np.zeros((self.T[vid], 2))
+        td = ctypes.c_uint64()
+        st = load().mppi_server_poll(self.h, int(ticket), U.ctypes.data_as(_dp), U.size,
+                                     ctypes.byref(td))
+        if st == E_NOT_READY:
+            return None
+        check(st)
+        return U, td.value
+
+    def wait(self, ticket, vid):
+        while True:
+            r = self.poll(ticket, vid)
+            if r is not None:
+                return r
+            check(load().mppi_server_wait_idle(self.h))
+
+    def wait_idle(self):
+        check(load().mppi_server_wait_idle(self.h))
+
+    def stats(self):
+        s = ServerStats()
+        check(load().mppi_server_get_stats(self.h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def reset_stats(self):
+        check(load().mppi_server_reset_stats(self.h))
+
+    def vehicle_state(self, vid):
+        U = np.zeros((self.T[vid], 2))
+        n = ctypes.c_uint64()
+        r = ctypes.c_uint64()
+        check(load().mppi_server_get_vehicle_state(self.h, int(vid), U.ctypes.data_as(_dp), U.size,
+                                                   ctypes.byref(n), ctypes.byref(r)))
+        return U, n.value, r.value
+
+    def set_vehicle_state(self, vid, U, n_iter, requests):
+        U = np.ascontiguousarray(np.asarray(U, dtype=np.float64))
+        check(load().mppi_server_set_vehicle_state(self.h, int(vid), U.ctypes.data_as(_dp), U.size,
+                                                   int(n_iter), int(requests)))
+
+    def replay(self, vids, x0s, scene_idx, scene_pool, arrival_ns):
+        """Open-loop load.  scene_pool: list of (waypoints, circles).
+        Returns latency_ms [n] (NaN for refused requests)."""
+        n = len(vids)
+        vid = np.ascontiguousarray(np.asarray(vids, dtype=np.int32))
+        x = np.ascontiguousarray(np.asarray(x0s, dtype=np.float64).reshape(n, 4))
+        si = np.ascontiguousarray(np.asarray(scene_idx, dtype=np.int32))
+        arr = np.ascontiguousarray(np.asarray(arrival_ns, dtype=np.uint64))
+        keep = []
+        scs = (Scene * len(scene_pool))()
+        for i, (wp, ci) in enumerate(scene_pool):
+            s_, k = make_scene(wp, ci)
+            scs[i] = s_
+            keep.append(k)
+        plan = ReplayPlan(n, vid.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                          x.ctypes.data_as(_dp), si.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                          scs, len(scene_pool), arr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+        lat = np.zeros(n)
+        check(load().mppi_server_replay(self.h, ctypes.byref(plan), lat.ctypes.data_as(_dp)))
+        del keep
+        return lat

@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_binding_covers_every_declared_symbol():
     bound = {name for name, _, _ in mppi.SIGNATURES}
-    assert set(declared_symbols()) <= bound | {n for n in declared_symbols() if n.startswith("mppi_server")}
+    assert set(declared_symbols()) <= bound
 
 
 def test_version_and_status_strings():
@@ -66,3 +66,13 @@ def test_null_handle_calls_fail_cleanly():
     assert L.mppi_sync(None) == mppi.E_INVALID
     assert L.mppi_destroy(None) == mppi.OK
     assert L.mppi_step_resident(None, None) == mppi.E_INVALID
+
+
+def test_invalid_server_config_rejected_without_device():
+    L = mppi.load()
+    import ctypes
+    h = ctypes.c_void_p()
+    for cfg in (mppi.ServerConfig(0, 1, 1, 1, 0), mppi.ServerConfig(1 << 20, 0, 1, 1, 0),
+                mppi.ServerConfig(1 << 20, 1, 0, 1, 0), mppi.ServerConfig(1 << 20, 9, 1, 1, 0)):
+        assert L.mppi_server_create(ctypes.byref(cfg), ctypes.byref(h)) == mppi.E_INVALID
+        assert not h.value
