@@ -160,6 +160,68 @@ def sweep():
             pl.close()
 
 
+def c3_load(n_vehicles, duration_s, pool_size=512, seed=33):
+    """Served load: vehicles with their own (K, T) and seeds replanning at
+    20 Hz with exponential inter-arrival times (mean 50 ms) and a random
+    phase; each request draws a scene from a pool of sine-lane windows with
+    0-48 circles ahead of the vehicle."""
+    from paper_2308_01654_amd import scenes
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pool, pool_x0 = [], []
+    for j in range(pool_size):
+        x = float(rng.uniform(-10.0, 100.0))
+        n_c = int(rng.integers(0, 49))
+        pool.append((scenes.sine_lane(np.floor(x) - 20.0, np.floor(x) + 200.0, 15.0),
+                     scenes.sine_circles(rng, n_c, x + 5.0, x + 120.0)))
+        pool_x0.append(scenes._sine_x0(x, 15.0))
+    vehicles = [scenes.c3_vehicle(v)["params"] for v in range(n_vehicles)]
+    vid, sidx, arr = [], [], []
+    for v in range(n_vehicles):
+        t = rng.uniform(0.0, 0.05)
+        while t < duration_s:
+            vid.append(v)
+            sidx.append(int(rng.integers(0, pool_size)))
+            arr.append(int(t * 1e9))
+            t += rng.exponential(0.05)
+    order = np.argsort(np.asarray(arr), kind="stable")
+    vid = np.asarray(vid)[order]
+    sidx = np.asarray(sidx)[order]
+    arr = np.asarray(arr, dtype=np.uint64)[order]
+    x0 = np.asarray(pool_x0)[sidx]
+    steps = np.array([vehicles[v]["K"] * vehicles[v]["T"] for v in vid], dtype=np.float64)
+    return vehicles, pool, vid, x0, sidx, arr, steps
+
+
+def served(n_vehicles=1000, duration_s=5.0, plain_duration_s=1.0):
+    """p50/p99/p99.9 replan latency of the continuous-batching server and of
+    the plain one-at-a-time path under the same open-loop load."""
+    from paper_2308_01654_amd import mppi
+    out = {}
+    for mode, dur in (("served", duration_s), ("plain", plain_duration_s)):
+        vehicles, pool, vid, x0, sidx, arr, steps = c3_load(n_vehicles, dur)
+        srv = mppi.Server(hbm_budget_bytes=8 << 30, n_streams=3, max_batch=512,
+                          plain=(mode == "plain"))
+        try:
+            vids = [srv.add_vehicle(p) for p in vehicles]
+            t0 = time.perf_counter()
+            lat = srv.replay([vids[v] for v in vid], x0, sidx, pool, arr)
+            wall = time.perf_counter() - t0
+            st = srv.stats()
+        finally:
+            srv.close()
+        ok = np.isfinite(lat)
+        out[mode] = dict(
+            vehicles=n_vehicles, requests=int(len(lat)), offered_rps=round(len(lat) / dur, 1),
+            completed_rps=round(int(ok.sum()) / wall, 1), wall_s=round(wall, 3),
+            p50=round(float(np.percentile(lat[ok], 50)), 3),
+            p99=round(float(np.percentile(lat[ok], 99)), 3),
+            p999=round(float(np.percentile(lat[ok], 99.9)), 3), max=round(float(lat[ok].max()), 3),
+            rollout_steps_per_s=round(float(steps[ok].sum()) / wall, 1),
+            mean_batch=round(st["mean_batch"], 2), hbm_peak_bytes=int(st["hbm_peak_bytes"]),
+            rejected=int(st["rejected"]))
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +234,9 @@ def main(argv=None):
     ap.add_argument("--probe", type=int, default=0, metavar="N",
                     help="only dispatch the counter-calibration copy and N iterations")
     ap.add_argument("--sweep", action="store_true", help="only run the lanes-per-sample sweep")
+    ap.add_argument("--served-seconds", type=float, default=5.0,
+                    help="duration of the served load (0 skips the served comparison)")
+    ap.add_argument("--plain-seconds", type=float, default=1.0)
     args = ap.parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the iteration on a single "
@@ -223,7 +288,7 @@ def main(argv=None):
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS,
                     unit="TFLOP/s", frac=round(achieved / PEAK_FP32_TFLOPS, 4),
                     traffic=load_traffic(K * T),
-                    kernel="k_iteration (fused sample/rollout/cost/weight/update)",
+                    kernel="k_batch<G,NE> (fused sample/rollout/cost/weight/update)",
                     kernel_ms=round(kern_ms, 5), flops_per_rollout_step=F,
                     lanes_per_sample=st["lanes"])
 
@@ -261,12 +326,19 @@ def main(argv=None):
                                "20 obstacles x 3 circles (10 moving), 3 ego circles, warm-started",
                    "K": K, "T": T, "n_waypoints": n_wp, "n_circles": n_c},
         "roofline": roofline,
-        "latency_ms": {"plain_p50": round(float(np.percentile(lat, 50)), 4),
-                       "plain_p99": round(float(np.percentile(lat, 99)), 4),
-                       "plain_p999": round(float(np.percentile(lat, 99.9)), 4)},
+        "latency_ms": {"one_at_a_time_unloaded_p50": round(float(np.percentile(lat, 50)), 4),
+                       "one_at_a_time_unloaded_p99": round(float(np.percentile(lat, 99)), 4),
+                       "one_at_a_time_unloaded_p999": round(float(np.percentile(lat, 99.9)), 4)},
         "wall_s_timed": round(t1 - t0, 4),
         "host_staged_value": round(pcie_value, 1),
     }
+    if args.served_seconds > 0:
+        sv = served(duration_s=args.served_seconds, plain_duration_s=args.plain_seconds)
+        out["latency_ms"].update({"served_p50": sv["served"]["p50"], "served_p99": sv["served"]["p99"],
+                                  "served_p999": sv["served"]["p999"],
+                                  "plain_p50": sv["plain"]["p50"], "plain_p99": sv["plain"]["p99"],
+                                  "plain_p999": sv["plain"]["p999"]})
+        out["served"] = sv
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
     print(json.dumps(out), flush=True)
