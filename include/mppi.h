@@ -194,6 +194,12 @@ mppi_status mppi_get_iter_stats(mppi_t* h, mppi_iter_stats* out);
  * let the library pick from its tuning table. */
 mppi_status mppi_set_lanes_per_sample(mppi_t* h, int32_t lanes);
 
+/* Wave-level culling of the two scans of the stage cost (on by default):
+ * waypoint chunks and obstacle circles that provably cannot change any
+ * lane's tracking minimum or obstacle cost are skipped.  Results are
+ * identical bit for bit; off (0) runs the full scans. */
+mppi_status mppi_set_culling(mppi_t* h, int32_t on);
+
 /* The HIP stream the handle enqueues on (as void*). */
 mppi_status mppi_get_stream(mppi_t* h, void** stream);
 

@@ -401,6 +401,9 @@ void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double or
     d.key0 = (uint32_t)c.seed;
     d.key1 = (uint32_t)(c.seed >> 32);
     d.shift = shift;
+    d.cull = h->no_cull ? 0 : 1;
+    d.ego_ext = 0.f;
+    for (int e = 0; e < c.n_ego; ++e) d.ego_ext = fmaxf(d.ego_ext, (float)fabs(c.ego_off[e]));
     d.out_slot = -1;
     d.c_pv = reinterpret_cast<const float4*>(scene + L.o_pv);
     d.wp_xy = reinterpret_cast<const float2*>(scene + L.o_xy);
@@ -893,6 +896,14 @@ mppi_status mppi_set_lanes_per_sample(mppi_t* h, int32_t lanes)
     if (!(lanes == 0 || lanes == 1 || lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16))
         return fail(MPPI_E_INVALID, "lanes per sample must be 0, 1, 2, 4, 8 or 16");
     h->lanes_req = lanes;
+    return MPPI_OK;
+}
+
+mppi_status mppi_set_culling(mppi_t* h, int32_t on)
+{
+    mppi_status s = usable(h);
+    if (s != MPPI_OK) return s;
+    h->no_cull = on ? 0 : 1;
     return MPPI_OK;
 }
 

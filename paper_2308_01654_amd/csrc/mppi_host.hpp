@@ -67,6 +67,7 @@ struct mppi {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int lanes_req = 0;  // 0 = tuning table
+    int no_cull = 0;    // 1: full waypoint and circle scans
     int last_lanes = 0;
     mppi_status sticky = MPPI_OK;
     // device memory

@@ -48,6 +48,8 @@ struct InstDesc {
     double lambda;
     uint32_t key0, key1;  // Philox key = seed
     int shift;            // shift U by one step before the iteration (warm start)
+    int cull;             // wave-level culling of waypoint chunks and circles
+    float ego_ext;        // max |ego_off|
     int out_slot;         // slot in the gathered results of a batch (-1: none)
     // device pointers
     const float2* wp_xy;  // [n_wp]
@@ -80,8 +82,12 @@ struct BatchHdr {
 
 // Dynamic LDS layout of the iteration kernel for a given scene size.
 struct LdsLayout {
-    size_t c_pv, wp_xy, U, red, wp_vref, c_rr, omega, total;
+    size_t c_pv, wp_box, wp_xy, U, red, wp_vref, c_rr, omega, total;
 };
+
+// Waypoints are grouped in chunks of this many consecutive points; each chunk
+// has an axis-aligned bounding box in LDS for the wave-level culling.
+constexpr int kChunk = 8;
 
 inline __host__ __device__ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -90,6 +96,7 @@ inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int sp
     LdsLayout L;
     size_t o = 0;
     L.c_pv = o;    o += (size_t)n_c * 16;
+    L.wp_box = o;  o += (size_t)((n_wp + kChunk - 1) / kChunk) * 16;
     L.wp_xy = o;   o += (size_t)n_wp * 8;
     L.U = o;       o += (size_t)T * 8;
     L.red = o;     o += 64 * 8;           // block reduction scratch (doubles)

@@ -78,6 +78,7 @@ __device__ __forceinline__ float2 draw_noise(const InstDesc& d, int k, int t,
 
 struct Lds {
     float4* c_pv;
+    float4* wp_box;
     float2* wp_xy;
     float2* U;
     double* red;
@@ -90,6 +91,7 @@ __device__ __forceinline__ Lds lds_bind(unsigned char* base, const LdsLayout& L)
 {
     Lds s;
     s.c_pv = reinterpret_cast<float4*>(base + L.c_pv);
+    s.wp_box = reinterpret_cast<float4*>(base + L.wp_box);
     s.wp_xy = reinterpret_cast<float2*>(base + L.wp_xy);
     s.U = reinterpret_cast<float2*>(base + L.U);
     s.red = reinterpret_cast<double*>(base + L.red);
@@ -147,6 +149,156 @@ __device__ __forceinline__ float stage_cost(const InstDesc& d, const Lds& s, flo
             }
         }
         const float g = fmaf(d.d_safe_c, v, d.d_safe_0) - d_obj;
+        const float c_safe = g > 0.0f ? g * g : 0.0f;
+        cost = fmaf(d.w_coll, c_safe, cost);
+    }
+    return cost;
+}
+
+// Cross-lane move of a float by a DPP control (lanes outside row_mask keep x).
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_f(float x)
+{
+    const int v = __builtin_bit_cast(int, x);
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(v, v, CTRL, ROW_MASK, 0xf, false));
+}
+
+// Wave-wide min / max with DPP: swap neighbours and quad halves, mirror inside
+// half rows and rows (every lane then holds its row's result), broadcast lane
+// 15 into rows 1 and 3 and lane 31 into rows 2 and 3; lane 63 ends with the
+// result of all 64 lanes, which is returned to every lane.
+__device__ __forceinline__ float wave_minf(float x)
+{
+    x = fminf(x, dpp_f<0xB1>(x));       // quad_perm [1,0,3,2]
+    x = fminf(x, dpp_f<0x4E>(x));       // quad_perm [2,3,0,1]
+    x = fminf(x, dpp_f<0x141>(x));      // row_half_mirror
+    x = fminf(x, dpp_f<0x140>(x));      // row_mirror
+    x = fminf(x, dpp_f<0x142, 0xa>(x)); // row_bcast:15
+    x = fminf(x, dpp_f<0x143, 0xc>(x)); // row_bcast:31
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
+}
+
+__device__ __forceinline__ float wave_maxf(float x)
+{
+    x = fmaxf(x, dpp_f<0xB1>(x));
+    x = fmaxf(x, dpp_f<0x4E>(x));
+    x = fmaxf(x, dpp_f<0x141>(x));
+    x = fmaxf(x, dpp_f<0x140>(x));
+    x = fmaxf(x, dpp_f<0x142, 0xa>(x));
+    x = fmaxf(x, dpp_f<0x143, 0xc>(x));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
+}
+
+// The stage cost of stage_cost, with the two scans restricted to what can
+// matter for this wave (all 64 lanes call it; `act` lanes are evaluated).
+// The result is bit-identical to the full scans:
+//  * waypoints: UB = min over chunks of the largest distance^2 between the
+//    wave's position box and the chunk box bounds every lane's nearest
+//    distance^2; a chunk whose smallest distance^2 to the wave box exceeds
+//    UB (with a relative margin far above float32 rounding) holds no
+//    candidate, and the remaining chunks are scanned in index order, so
+//    ties resolve exactly as in the full scan;
+//  * circles: a circle whose centre, swept over the wave's time range, stays
+//    farther than max(d_safe) + r_c + r_ego from the box of the wave's ego
+//    circles cannot make c_safe positive for any lane, so it is skipped.
+template <int NE>
+__device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds& s, bool act,
+                                                   float x, float y, float c, float sn, float v,
+                                                   float Ua, float Ud, float ea, float ed, int t,
+                                                   int t_lo, int t_hi)
+{
+    const int lane = threadIdx.x & 63;
+    const float bxlo = wave_minf(act ? x : INFINITY), bxhi = wave_maxf(act ? x : -INFINITY);
+    const float bylo = wave_minf(act ? y : INFINITY), byhi = wave_maxf(act ? y : -INFINITY);
+
+    const int n_wp = d.n_wp;
+    const int n_ch = (n_wp + kChunk - 1) / kChunk;
+    float ub = INFINITY;
+    for (int base = 0; base < n_ch; base += 64) {
+        float m2 = INFINITY;
+        if (base + lane < n_ch) {
+            const float4 b = s.wp_box[base + lane];
+            const float dx = fmaxf(bxhi - b.x, b.y - bxlo);
+            const float dy = fmaxf(byhi - b.z, b.w - bylo);
+            m2 = fmaf(dy, dy, dx * dx);
+        }
+        ub = fminf(ub, wave_minf(m2));
+    }
+    const float thr = fmaf(ub, 1.0f + 1e-5f, 1e-6f);
+    float best = INFINITY;
+    int bj = 0;
+    for (int base = 0; base < n_ch; base += 64) {
+        bool need = false;
+        if (base + lane < n_ch) {
+            const float4 b = s.wp_box[base + lane];
+            const float gx = fmaxf(fmaxf(b.x - bxhi, bxlo - b.y), 0.0f);
+            const float gy = fmaxf(fmaxf(b.z - byhi, bylo - b.w), 0.0f);
+            need = fmaf(gy, gy, gx * gx) <= thr;
+        }
+        unsigned long long m = __ballot(need);
+        while (m) {
+            const int ch = base + __builtin_ctzll(m);
+            m &= m - 1;
+            const int j1 = min((ch + 1) * kChunk, n_wp);
+            for (int j = ch * kChunk; j < j1; ++j) {
+                const float2 w = s.wp_xy[j];
+                const float dx = x - w.x;
+                const float dy = y - w.y;
+                const float dd = fmaf(dy, dy, dx * dx);
+                if (dd < best) {
+                    best = dd;
+                    bj = j;
+                }
+            }
+        }
+    }
+    const float dv = v - s.wp_vref[bj];
+    const float q = d.w_effort * (d.alpha * fmaf(ea, ea, ed * ed) + fmaf(Ua, ea, Ud * ed) +
+                                  0.5f * fmaf(Ua, Ua, Ud * Ud));
+    float cost = fmaf(d.w_track, best, fmaf(d.w_speed, dv * dv, q));
+    if (NE > 0) {
+        float ex[NE > 0 ? NE : 1], ey[NE > 0 ? NE : 1];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            ex[e] = fmaf(d.ego_off[e], c, x);
+            ey[e] = fmaf(d.ego_off[e], sn, y);
+        }
+        const float ds = fmaf(d.d_safe_c, v, d.d_safe_0);
+        const float dsmax = wave_maxf(act ? ds : -INFINITY);
+        const float exlo = bxlo - d.ego_ext, exhi = bxhi + d.ego_ext;
+        const float eylo = bylo - d.ego_ext, eyhi = byhi + d.ego_ext;
+        const float tau_lo = (float)(t_lo + 1) * d.dt;
+        const float tau_hi = (float)(t_hi + 1) * d.dt;
+        const float tau = (float)(t + 1) * d.dt;
+        float d_obj = INFINITY;
+        for (int base = 0; base < d.n_c; base += 64) {
+            bool need = false;
+            if (base + lane < d.n_c) {
+                const float4 p = s.c_pv[base + lane];
+                const float xa = fmaf(tau_lo, p.z, p.x), xb = fmaf(tau_hi, p.z, p.x);
+                const float ya = fmaf(tau_lo, p.w, p.y), yb = fmaf(tau_hi, p.w, p.y);
+                const float gx = fmaxf(fmaxf(fminf(xa, xb) - exhi, exlo - fmaxf(xa, xb)), 0.0f);
+                const float gy = fmaxf(fmaxf(fminf(ya, yb) - eyhi, eylo - fmaxf(ya, yb)), 0.0f);
+                const float lim = dsmax + s.c_rr[base + lane] + 0.01f;
+                need = lim > 0.0f && fmaf(gy, gy, gx * gx) < lim * lim;
+            }
+            unsigned long long m = __ballot(need);
+            while (m) {
+                const int i = base + __builtin_ctzll(m);
+                m &= m - 1;
+                const float4 p = s.c_pv[i];
+                const float rr = s.c_rr[i];
+                const float ox = fmaf(tau, p.z, p.x);
+                const float oy = fmaf(tau, p.w, p.y);
+#pragma unroll
+                for (int e = 0; e < NE; ++e) {
+                    const float dx = ex[e] - ox;
+                    const float dy = ey[e] - oy;
+                    d_obj = fminf(d_obj, __builtin_amdgcn_sqrtf(fmaf(dy, dy, dx * dx)) - rr);
+                }
+            }
+        }
+        const float g = ds - d_obj;
         const float c_safe = g > 0.0f ? g * g : 0.0f;
         cost = fmaf(d.w_coll, c_safe, cost);
     }
@@ -213,6 +365,17 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         s.wp_xy[i] = d.wp_xy[i];
         s.wp_vref[i] = d.wp_vref[i];
     }
+    for (int c = tid; c * kChunk < d.n_wp; c += kBlock) {
+        float4 b = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+        for (int j = c * kChunk; j < min((c + 1) * kChunk, d.n_wp); ++j) {
+            const float2 w = d.wp_xy[j];
+            b.x = fminf(b.x, w.x);
+            b.y = fmaxf(b.y, w.x);
+            b.z = fminf(b.z, w.y);
+            b.w = fmaxf(b.w, w.y);
+        }
+        s.wp_box[c] = b;  // (x_lo, x_hi, y_lo, y_hi)
+    }
     for (int i = tid; i < T; i += kBlock)
         s.U[i] = make_float2((float)d.U[2 * i], (float)d.U[2 * i + 1]);
     const unsigned long long n_iter = d.st->n_iter;
@@ -265,8 +428,14 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
                 mea = a - Ut.x; med = dl - Ut.y;
             }
         }
-        if (tm < T) {
-            const float q = stage_cost<NE>(d, s, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm);
+        const bool act = tm < T;
+        float q = 0.0f;
+        if (d.cull)
+            q = stage_cost_culled<NE>(d, s, act, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm, t0,
+                                      min(t0 + G, T) - 1);
+        else if (act)
+            q = stage_cost<NE>(d, s, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm);
+        if (act) {
             const float yk = q - comp;
             const float tk = S + yk;
             comp = (tk - S) - yk;
@@ -296,11 +465,20 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         const int t = col >> 1;
         const float* e = reinterpret_cast<const float*>(d.eps + (size_t)t * K + k_base) + (col & 1);
         float acc = 0.0f, cp = 0.0f;
-        for (int i = 0; i < n_valid; ++i) {
-            const float yk = s.omega[i] * e[2 * i] - cp;
-            const float tk = acc + yk;
-            cp = (tk - acc) - yk;
-            acc = tk;
+        // loads issued eight at a time, summed in sample order
+        for (int i0 = 0; i0 < n_valid; i0 += 8) {
+            float ev[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) ev[u] = (i0 + u < n_valid) ? e[2 * (i0 + u)] : 0.0f;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (i0 + u < n_valid) {
+                    const float yk = s.omega[i0 + u] * ev[u] - cp;
+                    const float tk = acc + yk;
+                    cp = (tk - acc) - yk;
+                    acc = tk;
+                }
+            }
         }
         part[kPartialHead + col] = (double)acc - (double)cp;
     }
@@ -351,8 +529,19 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     const double Q = block_sum(ql, s.red);
     for (int col = tid; col < 2 * T; col += kBlock) {
         double acc = 0.0;
-        for (int b = 0; b < d.n_tiles; ++b)
-            acc += d.partials[(size_t)b * stride + kPartialHead + col] * d.scales[b];
+        // eight tile rows in flight, merged in tile order
+        for (int b0 = 0; b0 < d.n_tiles; b0 += 8) {
+            double pv[8], sv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int b = b0 + u;
+                pv[u] = b < d.n_tiles ? d.partials[(size_t)b * stride + kPartialHead + col] : 0.0;
+                sv[u] = b < d.n_tiles ? d.scales[b] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (b0 + u < d.n_tiles) acc += pv[u] * sv[u];
+        }
         d.U[col] += acc / Z;
     }
     if (tid == 0) {

@@ -125,6 +125,7 @@ SIGNATURES = [
     ("mppi_get_noise", _i32, [_vp, _fp, _sz]),
     ("mppi_get_iter_stats", _i32, [_vp, ctypes.POINTER(IterStats)]),
     ("mppi_set_lanes_per_sample", _i32, [_vp, _i32]),
+    ("mppi_set_culling", _i32, [_vp, _i32]),
     ("mppi_get_stream", _i32, [_vp, ctypes.POINTER(_vp)]),
     ("mppi_set_profiling", _i32, [_vp, _i32]),
     ("mppi_get_profile", _i32, [_vp, ctypes.POINTER(Profile)]),
@@ -318,6 +319,9 @@ class Planner:
 
     def __exit__(self, *a):
         self.close()
+
+    def set_culling(self, on):
+        check(load().mppi_set_culling(self.h, 1 if on else 0))
 
     def set_lanes(self, lanes):
         check(load().mppi_set_lanes_per_sample(self.h, int(lanes)))

@@ -269,3 +269,28 @@ def test_c4_stress_sampled():
     rep = P.staged(p, sc, g, n_iter=0, ks=ks)
     _dump("c4", rep)
     P.assert_staged(rep)
+
+
+@pytest.mark.parametrize("name,lanes", [("c0", 16), ("c0", 1), ("c1", 8), ("c1", 2), ("paper_table1", 4),
+                                        ("tiny", 16), ("c4small", 2)])
+def test_culled_scans_bit_identical_to_full_scans(name, lanes):
+    """The wave-level culling of waypoint chunks and obstacle circles changes
+    no bit of the costs, the applied noise or the updated controls."""
+    mppi = _mppi()
+    if name == "c4small":
+        sc = scenes.c4(K=4096, T=200)
+    elif name == "tiny":
+        sc = scenes.tiny(K=3000, T=45, n_c=40, seed=5)
+    else:
+        sc = scenes.by_name(name)
+    p = sc["params"]
+    _say("culling", name, lanes)
+    outs = []
+    for cull in (True, False):
+        with mppi.Planner(p, lanes=lanes) as pl:
+            pl.set_culling(cull)
+            for _ in range(2):
+                pl.step(sc["x0"], sc["waypoints"], sc["circles"])
+            outs.append((pl.costs(), pl.noise(), pl.controls()))
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
