@@ -491,7 +491,7 @@ static hipError_t ws_reserve(BatchWs* b, size_t cap, hipStream_t stream)
 
 mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, const double* x0s,
                           const mppi_scene* scenes, const InstExtra* extra, int n, mppi_t* prof,
-                          double* gather_dev, int slot_doubles)
+                          double* gather_dev, int slot_doubles, bool use_graph)
 {
     mppi_t* h = prof;  // HIP_TRY marks it unusable on a device failure
     const size_t off_prefix = align_up(sizeof(BatchHdr), 16);
@@ -603,7 +603,7 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
     hipEvent_t a = nullptr;
     mppi_status s = record_launch(prof, 0, &a);
     if (s != MPPI_OK) return s;
-    if (graphs_enabled()) {
+    if (use_graph && graphs_enabled()) {
         GraphEntry* ge = nullptr;
         for (GraphEntry& g : ws->graphs)
             if (g.bytes == bucket && g.smem == smem_b && g.buf == b &&
@@ -611,7 +611,11 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
                 memcmp(g.grids, grids, sizeof grids) == 0)
                 ge = &g;
         if (!ge) {
-            if (ws->graphs.size() >= 64) ws_drop_graphs(ws);
+            if (ws->graphs.size() >= 64) {
+                // a cached graph may still be running on the stream
+                HIP_TRY(hipStreamSynchronize(stream));
+                ws_drop_graphs(ws);
+            }
             GraphEntry g;
             g.bytes = bucket;
             g.smem = smem_b;
@@ -759,7 +763,8 @@ mppi_status mppi_step_batch(mppi_t* const* hs, const double* x0s, const mppi_sce
         }
     }
     if (!lead->batch && (s = ws_create(&lead->batch)) != MPPI_OK) return s;
-    return batch_enqueue(lead->batch, lead->stream, hs, x0s, scenes, nullptr, n, lead, nullptr, 0);
+    return batch_enqueue(lead->batch, lead->stream, hs, x0s, scenes, nullptr, n, lead, nullptr, 0,
+                         true);
 }
 
 mppi_status mppi_sync(mppi_t* h)

@@ -137,9 +137,11 @@ void handle_release(mppi_t* h);
 // `stream`.  scenes == nullptr: resident scenes.  extra: optional per-instance
 // scratch/shift/result slot.  gather_dev: optional device buffer receiving,
 // per instance with out_slot >= 0, U [2T] doubles followed by the status and
-// the iteration counter at slot * slot_doubles.
+// the iteration counter at slot * slot_doubles.  use_graph: capture the
+// launch sequence per size class and replay it (repeated batches of one
+// shape); otherwise launch directly (batches whose composition changes).
 mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, const double* x0s,
                           const mppi_scene* scenes, const InstExtra* extra, int n, mppi_t* prof,
-                          double* gather_dev, int slot_doubles);
+                          double* gather_dev, int slot_doubles, bool use_graph);
 
 }  // namespace mppi_impl

@@ -286,8 +286,9 @@ void scheduler_loop(mppi_server* srv)
         ++srv->launches;
         srv->batched += n;
         lk.unlock();
+        // every batch has its own composition: direct launches, no graph
         mppi_status st = batch_enqueue(sc->ws, sc->s, hs.data(), x0s.data(), scs.data(), ex.data(),
-                                       n, nullptr, sc->gather_dev, kSlotDoubles);
+                                       n, nullptr, sc->gather_dev, kSlotDoubles, false);
         hipError_t e = hipSuccess;
         if (st == MPPI_OK)
             e = hipMemcpyAsync(sc->gather_host, sc->gather_dev,
