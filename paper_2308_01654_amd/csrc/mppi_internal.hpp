@@ -97,7 +97,7 @@ inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int sp
     size_t o = 0;
     L.c_pv = o;    o += (size_t)n_c * 16;
     L.wp_box = o;  o += (size_t)((n_wp + kChunk - 1) / kChunk) * 16;
-    L.wp_xy = o;   o += (size_t)n_wp * 8;
+    L.wp_xy = o;   o += (size_t)((n_wp + kChunk - 1) / kChunk) * kChunk * 8;  // padded
     L.U = o;       o += (size_t)T * 8;
     L.red = o;     o += 64 * 8;           // block reduction scratch (doubles)
     L.wp_vref = o; o += (size_t)n_wp * 4;

@@ -101,6 +101,29 @@ __device__ __forceinline__ Lds lds_bind(unsigned char* base, const LdsLayout& L)
     return s;
 }
 
+// Closest-waypoint update over chunk ch (kChunk consecutive waypoints, padded
+// with points at infinity): the chunk is read with four 16-byte LDS reads and
+// its distances are compared in index order, so ties keep the lowest index.
+__device__ __forceinline__ void scan_chunk(const Lds& s, int ch, float x, float y, float& best,
+                                           int& bj)
+{
+    static_assert(kChunk == 8, "chunk layout");
+    const float4* p = reinterpret_cast<const float4*>(s.wp_xy) + ch * (kChunk / 2);
+    const float4 q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
+    const float wx[8] = {q0.x, q0.z, q1.x, q1.z, q2.x, q2.z, q3.x, q3.z};
+    const float wy[8] = {q0.y, q0.w, q1.y, q1.w, q2.y, q2.w, q3.y, q3.w};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const float dx = x - wx[u];
+        const float dy = y - wy[u];
+        const float dd = fmaf(dy, dy, dx * dx);
+        if (dd < best) {
+            best = dd;
+            bj = ch * kChunk + u;
+        }
+    }
+}
+
 // Stage cost on the state reached at step t (Sec. III input cost, Sec. IV-C
 // tracking, speed and obstacle costs).  Every lane of the wave runs the same
 // waypoint and circle loops, so the LDS reads are broadcasts.
@@ -112,16 +135,7 @@ __device__ __forceinline__ float stage_cost(const InstDesc& d, const Lds& s, flo
     // c_dist = min_j ||P - W_j||^2; reference speed of the closest waypoint
     float best = INFINITY;
     int bj = 0;
-    for (int j = 0; j < d.n_wp; ++j) {
-        const float2 w = s.wp_xy[j];
-        const float dx = x - w.x;
-        const float dy = y - w.y;
-        const float dd = fmaf(dy, dy, dx * dx);
-        if (dd < best) {
-            best = dd;
-            bj = j;
-        }
-    }
+    for (int ch = 0; ch * kChunk < d.n_wp; ++ch) scan_chunk(s, ch, x, y, best, bj);
     const float dv = v - s.wp_vref[bj];
     // q_u = w_effort (alpha eps.eps + U.eps + U.U / 2)
     const float q = d.w_effort * (d.alpha * fmaf(ea, ea, ed * ed) + fmaf(Ua, ea, Ud * ed) +
@@ -239,17 +253,7 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
         while (m) {
             const int ch = base + __builtin_ctzll(m);
             m &= m - 1;
-            const int j1 = min((ch + 1) * kChunk, n_wp);
-            for (int j = ch * kChunk; j < j1; ++j) {
-                const float2 w = s.wp_xy[j];
-                const float dx = x - w.x;
-                const float dy = y - w.y;
-                const float dd = fmaf(dy, dy, dx * dx);
-                if (dd < best) {
-                    best = dd;
-                    bj = j;
-                }
-            }
+            scan_chunk(s, ch, x, y, best, bj);
         }
     }
     const float dv = v - s.wp_vref[bj];
@@ -284,17 +288,35 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
             }
             unsigned long long m = __ballot(need);
             while (m) {
-                const int i = base + __builtin_ctzll(m);
-                m &= m - 1;
-                const float4 p = s.c_pv[i];
-                const float rr = s.c_rr[i];
-                const float ox = fmaf(tau, p.z, p.x);
-                const float oy = fmaf(tau, p.w, p.y);
+                // up to four candidates per round: every load issued, one wait
+                int idx[4];
+                int cnt = 0;
 #pragma unroll
-                for (int e = 0; e < NE; ++e) {
-                    const float dx = ex[e] - ox;
-                    const float dy = ey[e] - oy;
-                    d_obj = fminf(d_obj, __builtin_amdgcn_sqrtf(fmaf(dy, dy, dx * dx)) - rr);
+                for (int u = 0; u < 4; ++u) {
+                    idx[u] = base + (m ? __builtin_ctzll(m) : 0);
+                    cnt += m ? 1 : 0;
+                    m &= m - 1;
+                }
+                float4 p[4];
+                float rr[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    p[u] = s.c_pv[idx[u]];
+                    rr[u] = s.c_rr[idx[u]];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (u < cnt) {
+                        const float ox = fmaf(tau, p[u].z, p[u].x);
+                        const float oy = fmaf(tau, p[u].w, p[u].y);
+#pragma unroll
+                        for (int e = 0; e < NE; ++e) {
+                            const float dx = ex[e] - ox;
+                            const float dy = ey[e] - oy;
+                            d_obj = fminf(d_obj,
+                                          __builtin_amdgcn_sqrtf(fmaf(dy, dy, dx * dx)) - rr[u]);
+                        }
+                    }
                 }
             }
         }
@@ -361,9 +383,11 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         s.c_pv[i] = d.c_pv[i];
         s.c_rr[i] = d.c_rr[i];
     }
-    for (int i = tid; i < d.n_wp; i += kBlock) {
-        s.wp_xy[i] = d.wp_xy[i];
-        s.wp_vref[i] = d.wp_vref[i];
+    const int n_wp_pad = (d.n_wp + kChunk - 1) / kChunk * kChunk;
+    for (int i = tid; i < n_wp_pad; i += kBlock) {
+        // padding points at infinity are never the closest
+        s.wp_xy[i] = i < d.n_wp ? d.wp_xy[i] : make_float2(INFINITY, INFINITY);
+        if (i < d.n_wp) s.wp_vref[i] = d.wp_vref[i];
     }
     for (int c = tid; c * kChunk < d.n_wp; c += kBlock) {
         float4 b = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
@@ -397,17 +421,25 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         const float2 em = draw_noise(d, kk, tm < T ? tm : T - 1, n_iter);
         float mx = 0.f, my = 0.f, mc = 1.f, ms = 0.f, mv = 0.f;
         float mUa = 0.f, mUd = 0.f, mea = 0.f, med = 0.f;
+        constexpr int PF = G < 4 ? G : 4;  // steps whose inputs are fetched together
+        float2 Upf[PF], epf[PF];
 #pragma unroll
         for (int i = 0; i < G; ++i) {
             const int t = t0 + i;
-            if (G > 1 && t >= T) continue;
-            float ea = em.x, ed = em.y;
-            if (G > 1) {
-                const int src = (tid & ~(G - 1)) + i;
-                ea = __shfl(em.x, src, 64);
-                ed = __shfl(em.y, src, 64);
+            if (i % PF == 0) {
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    Upf[u] = s.U[min(t + u, T - 1)];
+                    epf[u] = em;
+                    if (G > 1) {
+                        const int src = (tid & ~(G - 1)) + i + u;
+                        epf[u] = make_float2(__shfl(em.x, src, 64), __shfl(em.y, src, 64));
+                    }
+                }
             }
-            const float2 Ut = s.U[t];
+            if (G > 1 && t >= T) continue;
+            const float ea = epf[i % PF].x, ed = epf[i % PF].y;
+            const float2 Ut = Upf[i % PF];
             // noise check: bounds, speed cap, braking bound last
             float a = fminf(fmaxf(Ut.x + ea, d.a_min), d.a_max);
             a = fminf(a, (d.v_max - v) * d.inv_dt);
