@@ -284,7 +284,6 @@ void handle_release(mppi_t* h)
     (void)hipFree(h->S);
     (void)hipFree(h->eps);
     (void)hipFree(h->partials);
-    (void)hipFree(h->scales);
     (void)hipFree(h->wbuf);
     (void)hipFree(h->st);
     (void)hipFree(h->scene);
@@ -326,14 +325,13 @@ mppi_status handle_create(const mppi_config* cfg, void* hip_stream, bool with_sc
         h->own_stream = true;
     }
     if ((e = hipMalloc((void**)&h->U, sizeof(double) * 2 * T)) != hipSuccess ||
-        (e = hipMalloc((void**)&h->st, sizeof(DevState))) != hipSuccess)
+        (e = hipMalloc((void**)&h->st, state_bytes(h->max_tiles))) != hipSuccess)
         return bail(MPPI_E_NOMEM, "hipMalloc", e);
     if (with_scratch) {
         struct { void** p; size_t n; } allocs[] = {
             {(void**)&h->S, sizeof(float) * K},
             {(void**)&h->eps, sizeof(float2) * (size_t)T * K},
             {(void**)&h->partials, sizeof(double) * (size_t)h->max_tiles * (kPartialHead + 2 * T)},
-            {(void**)&h->scales, sizeof(double) * (size_t)h->max_tiles},
             {(void**)&h->wbuf, sizeof(double) * (size_t)K},
             {(void**)&h->scene, h->scene_cap},
         };
@@ -350,7 +348,7 @@ mppi_status handle_create(const mppi_config* cfg, void* hip_stream, bool with_sc
             return bail(MPPI_E_DEVICE, "initialise device state", e);
     }
     if ((e = hipMemsetAsync(h->U, 0, sizeof(double) * 2 * T, h->stream)) != hipSuccess ||
-        (e = hipMemsetAsync(h->st, 0, sizeof(DevState), h->stream)) != hipSuccess ||
+        (e = hipMemsetAsync(h->st, 0, state_bytes(h->max_tiles), h->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(h->stream)) != hipSuccess)
         return bail(MPPI_E_DEVICE, "initialise device state", e);
     if (const char* env = getenv("MPPI_LANES_PER_SAMPLE")) {
@@ -413,7 +411,6 @@ void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double or
     d.S = h->S;
     d.eps = h->eps;
     d.partials = h->partials;
-    d.scales = h->scales;
     d.st = h->st;
 }
 
@@ -556,7 +553,6 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
             descs[j].S = ex->S;
             descs[j].eps = ex->eps;
             descs[j].partials = ex->partials;
-            descs[j].scales = ex->scales;
             descs[j].out_slot = ex->out_slot;
             any_out |= ex->out_slot >= 0;
         }

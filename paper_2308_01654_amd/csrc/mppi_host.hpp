@@ -54,7 +54,6 @@ struct InstExtra {
     float* S;
     float2* eps;
     double* partials;
-    double* scales;
     int shift;
     int out_slot;
 };
@@ -75,7 +74,6 @@ struct mppi {
     float* S = nullptr;
     float2* eps = nullptr;
     double* partials = nullptr;
-    double* scales = nullptr;
     double* wbuf = nullptr;  // [K] weights export
     mppi_impl::DevState* st = nullptr;
     unsigned char* scene = nullptr;
@@ -115,6 +113,12 @@ namespace mppi_impl {
     } while (0)
 
 SceneLayout scene_layout(int n_wp, int n_c);
+// Bytes of a handle's device state: DevState and the combine-tree tickets
+// for up to max_tiles tiles.
+inline size_t state_bytes(int max_tiles)
+{
+    return sizeof(DevState) + sizeof(unsigned int) * (size_t)combine_tickets(max_tiles);
+}
 void write_scene(unsigned char* dst, const SceneLayout& L, const mppi_config& c,
                  const double origin[2], const mppi_scene* sc);
 mppi_status validate_scene(const mppi_config& c, const double x0[4], const mppi_scene* sc);

@@ -15,9 +15,11 @@ constexpr int kMaxCircles = 1024;
 constexpr int kMaxK = 1 << 24;
 
 // Per-instance state that stays resident on the device between iterations.
+// The allocation continues with the group tickets of the combine tree
+// (combine_tickets(max tiles) unsigned ints, zero between iterations).
 struct DevState {
     unsigned long long n_iter;  // Philox counter words 2-3: iteration number
-    unsigned int ticket;        // tiles finished in the running iteration
+    unsigned int ticket;        // root nodes of the combine tree finished
     int status;                 // 0 or MPPI_E_NONFINITE of the last iteration
     double s_min;               // min_k S_k
     double z;                   // sum_k exp(-(S_k - s_min)/lambda)
@@ -29,6 +31,20 @@ struct DevState {
 // sums and the shifted weighted perturbation sums for every (t, control).
 //   [0] m_b  [1] Z_b  [2] Q_b (sum of squares)  [3] unused  [4 + 2t + d] N_b
 constexpr int kPartialHead = 4;
+
+// Tile partials are merged by a tree of fixed shape: a node of level l + 1
+// merges up to kFanIn consecutive nodes of level l, and the root merges the
+// last level that has at most kFanIn nodes.  Each non-root group has a
+// ticket; the member that completes it merges the group into the row of its
+// first tile.  The shape depends on the tile count only.
+constexpr int kFanIn = 16;
+
+inline __host__ __device__ int combine_tickets(int n_tiles)
+{
+    int total = 0;
+    for (int n = n_tiles; n > kFanIn; n = (n + kFanIn - 1) / kFanIn) total += (n + kFanIn - 1) / kFanIn;
+    return total;
+}
 
 // Everything one launch needs to run one MPPI iteration of one instance.
 // Scene arrays are in the ego frame (x0's position subtracted) and float32.
@@ -60,8 +76,7 @@ struct InstDesc {
     float* S;             // [K]
     float2* eps;          // [T][K]
     double* partials;     // [n_tiles][kPartialHead + 2T]
-    double* scales;       // [n_tiles] scratch of the combining tile
-    DevState* st;
+    DevState* st;         // followed by the combine-tree tickets
 };
 
 // Header of a batch arena in device memory: followed by the tile prefix

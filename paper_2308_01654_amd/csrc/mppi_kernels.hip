@@ -522,68 +522,98 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     }
 
     // ---------------------------------------------------------------- phase 3
-    __threadfence();
-    __syncthreads();
-    unsigned int* flag = reinterpret_cast<unsigned int*>(s.red);
-    if (tid == 0) {
-        const unsigned int prev = __hip_atomic_fetch_add(&d.st->ticket, 1u, __ATOMIC_ACQ_REL,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-        flag[0] = (prev == (unsigned int)(d.n_tiles - 1)) ? 1u : 0u;
-    }
-    __syncthreads();
-    if (flag[0] == 0u) return;
-    __threadfence();
-
+    // Merge the tile partials up the combine tree.  A node's row is the row
+    // of its first tile; children are merged in index order with the
+    // log-sum-exp shift to their common minimum.
     const int stride = kPartialHead + 2 * T;
-    double m = INFINITY;
-    for (int b = tid; b < d.n_tiles; b += kBlock) m = fmin(m, d.partials[(size_t)b * stride]);
-    m = block_min(m, s.red);
-    if (!isfinite(m)) {
+    unsigned int* tickets = reinterpret_cast<unsigned int*>(d.st + 1);
+    unsigned int* flag = reinterpret_cast<unsigned int*>(s.red + 63);
+    double* sc_lds = s.red + 8;  // kFanIn child scales
+    int n_l = d.n_tiles;         // nodes at this level
+    int idx = tile;              // index of this node at this level
+    size_t span = 1;             // tiles per node at this level
+    int toff = 0;                // first ticket of this level
+    for (;;) {
+        const bool root = n_l <= kFanIn;
+        const int g = root ? 0 : idx / kFanIn;
+        const int first = g * kFanIn;
+        const int nc = root ? n_l : min(kFanIn, n_l - first);
+        __threadfence();
+        __syncthreads();
         if (tid == 0) {
-            d.st->status = -4;  // MPPI_E_NONFINITE: U and n stay unchanged
-            d.st->ticket = 0u;
+            unsigned int* tk = root ? &d.st->ticket : &tickets[toff + g];
+            const unsigned int prev =
+                __hip_atomic_fetch_add(tk, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            const bool last = prev == (unsigned int)(nc - 1);
+            // every member has arrived: the ticket is free for the next iteration
+            if (last) __hip_atomic_store(tk, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            flag[0] = last ? 1u : 0u;
         }
-        return;
-    }
-    for (int b = tid; b < d.n_tiles; b += kBlock) {
-        const double mb = d.partials[(size_t)b * stride];
-        d.scales[b] = isfinite(mb) ? exp(-(mb - m) / d.lambda) : 0.0;
-    }
-    __threadfence_block();
-    __syncthreads();
-    double zl = 0.0, ql = 0.0;
-    for (int b = tid; b < d.n_tiles; b += kBlock) {
-        const double sc = d.scales[b];
-        zl += d.partials[(size_t)b * stride + 1] * sc;
-        ql += d.partials[(size_t)b * stride + 2] * sc * sc;
-    }
-    const double Z = block_sum(zl, s.red);
-    const double Q = block_sum(ql, s.red);
-    for (int col = tid; col < 2 * T; col += kBlock) {
-        double acc = 0.0;
-        // eight tile rows in flight, merged in tile order
-        for (int b0 = 0; b0 < d.n_tiles; b0 += 8) {
-            double pv[8], sv[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int b = b0 + u;
-                pv[u] = b < d.n_tiles ? d.partials[(size_t)b * stride + kPartialHead + col] : 0.0;
-                sv[u] = b < d.n_tiles ? d.scales[b] : 0.0;
+        __syncthreads();
+        if (flag[0] == 0u) return;
+        __threadfence();
+
+        double* rows = d.partials + (size_t)first * span * stride;
+        const size_t cstride = span * stride;  // between consecutive children
+        if (tid < 64) {
+            const double* h = rows + (size_t)min(tid, nc - 1) * cstride;
+            const double mi = tid < nc ? h[0] : INFINITY;
+            const double zi = tid < nc ? h[1] : 0.0;
+            const double qi = tid < nc ? h[2] : 0.0;
+            const double mm = wave_min(mi);
+            // a child whose samples are all non-finite has m = +inf and weight 0
+            const double sc = (tid < nc && isfinite(mi)) ? exp(-(mi - mm) / d.lambda) : 0.0;
+            const double zz = wave_sum(zi * sc);
+            const double qq = wave_sum(qi * sc * sc);
+            if (tid < kFanIn) sc_lds[tid] = sc;
+            if (tid == 0) {
+                s.red[0] = mm;
+                s.red[1] = zz;
+                s.red[2] = qq;
             }
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (b0 + u < d.n_tiles) acc += pv[u] * sv[u];
         }
-        d.U[col] += acc / Z;
-    }
-    if (tid == 0) {
-        d.st->s_min = m;
-        d.st->z = Z;
-        d.st->log_z = log(Z);
-        d.st->ess = Z * Z / Q;
-        d.st->status = 0;
-        d.st->n_iter = n_iter + 1ull;
-        d.st->ticket = 0u;
+        __syncthreads();
+        const double mm = s.red[0], zz = s.red[1], qq = s.red[2];
+        if (root && !isfinite(mm)) {
+            if (tid == 0) d.st->status = -4;  // MPPI_E_NONFINITE: U and n stay unchanged
+            return;
+        }
+        for (int col = tid; col < 2 * T; col += kBlock) {
+            const double* src = rows + kPartialHead + col;
+            double acc = 0.0;
+            // eight children in flight, merged in child order
+            for (int i0 = 0; i0 < nc; i0 += 8) {
+                double pv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    pv[u] = i0 + u < nc ? src[(size_t)(i0 + u) * cstride] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (i0 + u < nc) acc += pv[u] * sc_lds[i0 + u];
+            }
+            if (root) d.U[col] += acc / zz;
+            else rows[kPartialHead + col] = acc;
+        }
+        if (root) {
+            if (tid == 0) {
+                d.st->s_min = mm;
+                d.st->z = zz;
+                d.st->log_z = log(zz);
+                d.st->ess = zz * zz / qq;
+                d.st->status = 0;
+                d.st->n_iter = n_iter + 1ull;
+            }
+            return;
+        }
+        if (tid == 0) {
+            rows[0] = mm;
+            rows[1] = zz;
+            rows[2] = qq;
+        }
+        toff += (n_l + kFanIn - 1) / kFanIn;
+        n_l = (n_l + kFanIn - 1) / kFanIn;
+        idx = g;
+        span *= kFanIn;
     }
 }
 

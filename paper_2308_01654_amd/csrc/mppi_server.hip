@@ -162,7 +162,7 @@ size_t request_bytes(const mppi_config& c, int lanes)
 {
     const size_t tiles = (size_t)(c.K + (kBlock / lanes) - 1) / (kBlock / lanes);
     return a256(sizeof(float) * c.K) + a256(sizeof(float2) * (size_t)c.T * c.K) +
-           a256(sizeof(double) * tiles * (kPartialHead + 2 * c.T)) + a256(sizeof(double) * tiles);
+           a256(sizeof(double) * tiles * (kPartialHead + 2 * c.T));
 }
 
 void finish_request(mppi_server* srv, Req* r)
@@ -277,8 +277,6 @@ void scheduler_loop(mppi_server* srv)
             ex[i].eps = reinterpret_cast<float2*>(base);
             base += a256(sizeof(float2) * (size_t)c.T * c.K);
             ex[i].partials = reinterpret_cast<double*>(base);
-            base += a256(sizeof(double) * tiles * (kPartialHead + 2 * c.T));
-            ex[i].scales = reinterpret_cast<double*>(base);
             ex[i].shift = v.admitted > 0 ? 1 : 0;
             ex[i].out_slot = i;
             ++v.admitted;
