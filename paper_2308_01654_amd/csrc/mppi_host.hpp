@@ -117,7 +117,8 @@ SceneLayout scene_layout(int n_wp, int n_c);
 // for up to max_tiles tiles.
 inline size_t state_bytes(int max_tiles)
 {
-    return sizeof(DevState) + sizeof(unsigned int) * (size_t)combine_tickets(max_tiles);
+    return sizeof(DevState) +
+           sizeof(unsigned int) * kTicketStride * ((size_t)combine_tickets(max_tiles) + 1);
 }
 void write_scene(unsigned char* dst, const SceneLayout& L, const mppi_config& c,
                  const double origin[2], const mppi_scene* sc);

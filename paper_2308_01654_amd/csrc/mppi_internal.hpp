@@ -16,7 +16,8 @@ constexpr int kMaxK = 1 << 24;
 
 // Per-instance state that stays resident on the device between iterations.
 // The allocation continues with the group tickets of the combine tree
-// (combine_tickets(max tiles) unsigned ints, zero between iterations).
+// (combine_tickets(max tiles) tickets of kTicketStride unsigned ints each,
+// zero between iterations).
 struct DevState {
     unsigned long long n_iter;  // Philox counter words 2-3: iteration number
     unsigned int ticket;        // root nodes of the combine tree finished
@@ -38,6 +39,9 @@ constexpr int kPartialHead = 4;
 // ticket; the member that completes it merges the group into the row of its
 // first tile.  The shape depends on the tile count only.
 constexpr int kFanIn = 16;
+// Tickets sit on separate 128-byte lines so that groups finishing at the same
+// time do not contend for one line.
+constexpr int kTicketStride = 32;
 
 inline __host__ __device__ int combine_tickets(int n_tiles)
 {

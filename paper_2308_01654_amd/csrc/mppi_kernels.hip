@@ -526,7 +526,9 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     // of its first tile; children are merged in index order with the
     // log-sum-exp shift to their common minimum.
     const int stride = kPartialHead + 2 * T;
-    unsigned int* tickets = reinterpret_cast<unsigned int*>(d.st + 1);
+    // first ticket on the 128-byte line after the state
+    unsigned int* tickets = reinterpret_cast<unsigned int*>(
+        (reinterpret_cast<uintptr_t>(d.st + 1) + 4 * kTicketStride - 1) & ~(uintptr_t)(4 * kTicketStride - 1));
     unsigned int* flag = reinterpret_cast<unsigned int*>(s.red + 63);
     double* sc_lds = s.red + 8;  // kFanIn child scales
     int n_l = d.n_tiles;         // nodes at this level
@@ -538,12 +540,14 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         const int g = root ? 0 : idx / kFanIn;
         const int first = g * kFanIn;
         const int nc = root ? n_l : min(kFanIn, n_l - first);
-        __threadfence();
+        // The barrier orders the workgroup's row stores before the ticket;
+        // the release increment publishes them device-wide.  Only the member
+        // that completes the group pays for the acquire (below).
         __syncthreads();
         if (tid == 0) {
-            unsigned int* tk = root ? &d.st->ticket : &tickets[toff + g];
+            unsigned int* tk = root ? &d.st->ticket : &tickets[(size_t)(toff + g) * kTicketStride];
             const unsigned int prev =
-                __hip_atomic_fetch_add(tk, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(tk, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             const bool last = prev == (unsigned int)(nc - 1);
             // every member has arrived: the ticket is free for the next iteration
             if (last) __hip_atomic_store(tk, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -551,7 +555,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         }
         __syncthreads();
         if (flag[0] == 0u) return;
-        __threadfence();
+        __threadfence();  // acquire the rows of every member
 
         double* rows = d.partials + (size_t)first * span * stride;
         const size_t cstride = span * stride;  // between consecutive children
