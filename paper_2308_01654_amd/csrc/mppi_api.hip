@@ -117,7 +117,8 @@ SceneLayout scene_layout(int n_wp, int n_c)
     SceneLayout L;
     L.o_pv = 0;
     L.o_xy = L.o_pv + align_up((size_t)n_c * 16, 16);
-    L.o_vr = L.o_xy + align_up((size_t)n_wp * 8, 16);
+    // waypoints padded to whole chunks (points at infinity)
+    L.o_vr = L.o_xy + align_up((size_t)(n_wp + kChunk - 1) / kChunk * kChunk * 8, 16);
     L.o_rr = L.o_vr + align_up((size_t)n_wp * 4, 16);
     L.bytes = L.o_rr + align_up((size_t)n_c * 4, 16);
     return L;
@@ -136,6 +137,7 @@ void write_scene(unsigned char* dst, const SceneLayout& L, const mppi_config& c,
         xy[i] = make_float2((float)(w[0] - origin[0]), (float)(w[1] - origin[1]));
         vr[i] = (float)w[3];
     }
+    for (int i = sc->n_waypoints; i % kChunk; ++i) xy[i] = make_float2(INFINITY, INFINITY);
     for (int i = 0; i < sc->n_circles; ++i) {
         const double* o = sc->circles + 5 * i;
         pv[i] = make_float4((float)(o[0] - origin[0]), (float)(o[1] - origin[1]), (float)o[3],

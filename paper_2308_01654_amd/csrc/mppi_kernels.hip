@@ -124,6 +124,26 @@ __device__ __forceinline__ void scan_chunk(const Lds& s, int ch, float x, float 
     }
 }
 
+// Clearance between the ego circles (centres ex, ey) and obstacle circle p
+// at time tau: min_e ||P_e - O|| - (r_c + r_ego), with the square root taken
+// once, of the smallest squared distance (the root is monotone).
+template <int NE>
+__device__ __forceinline__ float circle_gap(const float (&ex)[NE > 0 ? NE : 1],
+                                            const float (&ey)[NE > 0 ? NE : 1], const float4& p,
+                                            float rr, float tau)
+{
+    const float ox = fmaf(tau, p.z, p.x);
+    const float oy = fmaf(tau, p.w, p.y);
+    float m2 = INFINITY;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+        const float dx = ex[e] - ox;
+        const float dy = ey[e] - oy;
+        m2 = fminf(m2, fmaf(dy, dy, dx * dx));
+    }
+    return __builtin_amdgcn_sqrtf(m2) - rr;
+}
+
 // Stage cost on the state reached at step t (Sec. III input cost, Sec. IV-C
 // tracking, speed and obstacle costs).  Every lane of the wave runs the same
 // waypoint and circle loops, so the LDS reads are broadcasts.
@@ -153,14 +173,7 @@ __device__ __forceinline__ float stage_cost(const InstDesc& d, const Lds& s, flo
         for (int i = 0; i < d.n_c; ++i) {
             const float4 p = s.c_pv[i];
             const float rr = s.c_rr[i];
-            const float ox = fmaf(tau, p.z, p.x);
-            const float oy = fmaf(tau, p.w, p.y);
-#pragma unroll
-            for (int e = 0; e < NE; ++e) {
-                const float dx = ex[e] - ox;
-                const float dy = ey[e] - oy;
-                d_obj = fminf(d_obj, __builtin_amdgcn_sqrtf(fmaf(dy, dy, dx * dx)) - rr);
-            }
+            d_obj = fminf(d_obj, circle_gap<NE>(ex, ey, p, rr, tau));
         }
         const float g = fmaf(d.d_safe_c, v, d.d_safe_0) - d_obj;
         const float c_safe = g > 0.0f ? g * g : 0.0f;
@@ -169,39 +182,187 @@ __device__ __forceinline__ float stage_cost(const InstDesc& d, const Lds& s, flo
     return cost;
 }
 
-// Cross-lane move of a float by a DPP control (lanes outside row_mask keep x).
-template <int CTRL, int ROW_MASK = 0xf>
-__device__ __forceinline__ float dpp_f(float x)
-{
-    const int v = __builtin_bit_cast(int, x);
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(v, v, CTRL, ROW_MASK, 0xf, false));
-}
+// ----------------------------------------------------------------------------
+// Wave-level culling helpers.
+// ----------------------------------------------------------------------------
 
-// Wave-wide min / max with DPP: swap neighbours and quad halves, mirror inside
+// Order-preserving map of float32 onto int32 (its own inverse): for non-NaN
+// values the integer order of the keys is the float order, so wave minima and
+// maxima run on integer DPP operations without NaN canonicalisation.
+__device__ __forceinline__ int fkey(float f)
+{
+    const int b = __builtin_bit_cast(int, f);
+    return b ^ ((b >> 31) & 0x7fffffff);
+}
+__device__ __forceinline__ float fkey_inv(int k)
+{
+    return __builtin_bit_cast(float, k ^ ((k >> 31) & 0x7fffffff));
+}
+constexpr int kKeyPosInf = 0x7f800000;          // fkey(+inf)
+constexpr int kKeyNegInf = (int)0x807fffffu;    // fkey(-inf)
+
+// Cross-lane move by a DPP control; lanes outside row_mask receive `idv`,
+// the identity of the reduction that consumes the value.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ int dpp_i(int idv, int x)
+{
+    return __builtin_amdgcn_update_dpp(idv, x, CTRL, ROW_MASK, 0xf, false);
+}
+constexpr int kIntMax = 0x7fffffff;
+constexpr int kIntMin = (int)0x80000000u;
+
+// Wave-wide reduction stages: swap neighbours and quad halves, mirror inside
 // half rows and rows (every lane then holds its row's result), broadcast lane
 // 15 into rows 1 and 3 and lane 31 into rows 2 and 3; lane 63 ends with the
-// result of all 64 lanes, which is returned to every lane.
-__device__ __forceinline__ float wave_minf(float x)
+// result over all 64 lanes.  Five independent reductions (two minima, three
+// maxima) advance stage by stage so that their DPP latencies overlap.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ void red5_stage(int& a, int& b, int& c, int& e, int& f)
 {
-    x = fminf(x, dpp_f<0xB1>(x));       // quad_perm [1,0,3,2]
-    x = fminf(x, dpp_f<0x4E>(x));       // quad_perm [2,3,0,1]
-    x = fminf(x, dpp_f<0x141>(x));      // row_half_mirror
-    x = fminf(x, dpp_f<0x140>(x));      // row_mirror
-    x = fminf(x, dpp_f<0x142, 0xa>(x)); // row_bcast:15
-    x = fminf(x, dpp_f<0x143, 0xc>(x)); // row_bcast:31
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
+    a = min(a, dpp_i<CTRL, ROW_MASK>(kIntMax, a));
+    b = min(b, dpp_i<CTRL, ROW_MASK>(kIntMax, b));
+    c = max(c, dpp_i<CTRL, ROW_MASK>(kIntMin, c));
+    e = max(e, dpp_i<CTRL, ROW_MASK>(kIntMin, e));
+    f = max(f, dpp_i<CTRL, ROW_MASK>(kIntMin, f));
 }
 
-__device__ __forceinline__ float wave_maxf(float x)
+__device__ __forceinline__ int lane63(int x) { return __builtin_amdgcn_readlane(x, 63); }
+
+// Bounding box of the positions of the lanes with inc set, and the largest
+// safety distance among them (keys of +-inf for an empty set).
+struct WaveBox {
+    float xlo, xhi, ylo, yhi, dsmax;
+};
+
+__device__ __forceinline__ WaveBox wave_box(bool inc, float x, float y, float ds)
 {
-    x = fmaxf(x, dpp_f<0xB1>(x));
-    x = fmaxf(x, dpp_f<0x4E>(x));
-    x = fmaxf(x, dpp_f<0x141>(x));
-    x = fmaxf(x, dpp_f<0x140>(x));
-    x = fmaxf(x, dpp_f<0x142, 0xa>(x));
-    x = fmaxf(x, dpp_f<0x143, 0xc>(x));
-    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
+    int a = inc ? fkey(x) : kKeyPosInf;
+    int b = inc ? fkey(y) : kKeyPosInf;
+    int c = inc ? fkey(x) : kKeyNegInf;
+    int e = inc ? fkey(y) : kKeyNegInf;
+    int f = inc ? fkey(ds) : kKeyNegInf;
+    red5_stage<0xB1>(a, b, c, e, f);       // quad_perm [1,0,3,2]
+    red5_stage<0x4E>(a, b, c, e, f);       // quad_perm [2,3,0,1]
+    red5_stage<0x141>(a, b, c, e, f);      // row_half_mirror
+    red5_stage<0x140>(a, b, c, e, f);      // row_mirror
+    red5_stage<0x142, 0xa>(a, b, c, e, f); // row_bcast:15
+    red5_stage<0x143, 0xc>(a, b, c, e, f); // row_bcast:31
+    WaveBox w;
+    w.xlo = fkey_inv(lane63(a));
+    w.ylo = fkey_inv(lane63(b));
+    w.xhi = fkey_inv(lane63(c));
+    w.yhi = fkey_inv(lane63(e));
+    w.dsmax = fkey_inv(lane63(f));
+    return w;
 }
+
+// Wave minimum of non-negative floats (their bit patterns are ordered).
+__device__ __forceinline__ float wave_min_nonneg(float v)
+{
+    int a = __builtin_bit_cast(int, v);
+    a = min(a, dpp_i<0xB1>(kIntMax, a));
+    a = min(a, dpp_i<0x4E>(kIntMax, a));
+    a = min(a, dpp_i<0x141>(kIntMax, a));
+    a = min(a, dpp_i<0x140>(kIntMax, a));
+    a = min(a, dpp_i<0x142, 0xa>(kIntMax, a));
+    a = min(a, dpp_i<0x143, 0xc>(kIntMax, a));
+    return __builtin_bit_cast(float, lane63(a));
+}
+
+// Read-only scene data fetched with wave-uniform addresses: the constant
+// address space makes these scalar loads.
+template <typename T>
+using const_ptr = const __attribute__((address_space(4))) T*;
+
+template <typename T>
+__device__ __forceinline__ const_ptr<float> as_const(const T* p)
+{
+    return (const_ptr<float>)(reinterpret_cast<const float*>(p));
+}
+
+// Element i of a float4 array seen as floats.
+__device__ __forceinline__ float4 ld4(const_ptr<float> p, int i)
+{
+    return make_float4(p[4 * i], p[4 * i + 1], p[4 * i + 2], p[4 * i + 3]);
+}
+
+// Smallest squared distance from (x, y) to the 8 points of a waypoint chunk
+// (padded at the end with points at infinity).
+__device__ __forceinline__ float chunk_min(const float4 (&q)[4], float x, float y)
+{
+    const float wx[8] = {q[0].x, q[0].z, q[1].x, q[1].z, q[2].x, q[2].z, q[3].x, q[3].z};
+    const float wy[8] = {q[0].y, q[0].w, q[1].y, q[1].w, q[2].y, q[2].w, q[3].y, q[3].w};
+    float m = INFINITY;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const float dx = x - wx[u];
+        const float dy = y - wy[u];
+        m = fminf(m, fmaf(dy, dy, dx * dx));
+    }
+    return m;
+}
+
+// Scans the chunks whose bits are set in m (ascending, two per memory round
+// trip, read from global memory with scalar loads): best = smallest squared
+// distance, bch = first chunk that attains it.
+__device__ __forceinline__ void scan_chunks(const_ptr<float> wp4, int base, unsigned long long m,
+                                            float x, float y, float& best, int& bch)
+{
+    while (m) {
+        const int c0 = base + __builtin_ctzll(m);
+        m &= m - 1;
+        const bool two = m != 0;
+        const int c1 = two ? base + __builtin_ctzll(m) : c0;
+        if (two) m &= m - 1;
+        float4 q0[4], q1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            q0[u] = ld4(wp4, c0 * 4 + u);
+            q1[u] = ld4(wp4, c1 * 4 + u);
+        }
+        const float m0 = chunk_min(q0, x, y);
+        if (m0 < best) {
+            best = m0;
+            bch = c0;
+        }
+        if (two) {
+            const float m1 = chunk_min(q1, x, y);
+            if (m1 < best) {
+                best = m1;
+                bch = c1;
+            }
+        }
+    }
+}
+
+// Index of the first point of chunk bch at squared distance best from
+// (x, y): together with scan_chunks this is the lowest index attaining the
+// minimum, as in the sequential scan (index 0 when no distance is finite).
+__device__ __forceinline__ int chunk_argmin(const Lds& s, int bch, float best, float x, float y)
+{
+    if (!(best < INFINITY)) return 0;
+    const float4* p = reinterpret_cast<const float4*>(s.wp_xy) + bch * (kChunk / 2);
+    const float4 q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
+    const float wx[8] = {q0.x, q0.z, q1.x, q1.z, q2.x, q2.z, q3.x, q3.z};
+    const float wy[8] = {q0.y, q0.w, q1.y, q1.w, q2.y, q2.w, q3.y, q3.w};
+    int bj = bch * kChunk;
+#pragma unroll
+    for (int u = 7; u >= 0; --u) {
+        const float dx = x - wx[u];
+        const float dy = y - wy[u];
+        if (fmaf(dy, dy, dx * dx) == best) bj = bch * kChunk + u;
+    }
+    return bj;
+}
+
+// Per-lane culling data that stays in registers through the rollout: the
+// bounding box of chunk `lane` and obstacle circle `lane` (the first 64 of
+// each; larger scenes read the rest from LDS).
+struct LaneCull {
+    float4 box;   // (x_lo, x_hi, y_lo, y_hi) of chunk lane; empty past the end
+    float4 cpv;   // circle lane (x, y, vx, vy); at infinity past the end
+    float crr;    // its radius plus the ego radius
+};
 
 // The stage cost of stage_cost, with the two scans restricted to what can
 // matter for this wave (all 64 lanes call it; `act` lanes are evaluated).
@@ -215,51 +376,59 @@ __device__ __forceinline__ float wave_maxf(float x)
 //  * circles: a circle whose centre, swept over the wave's time range, stays
 //    farther than max(d_safe) + r_c + r_ego from the box of the wave's ego
 //    circles cannot make c_safe positive for any lane, so it is skipped.
+// Lanes whose position or safety distance is not finite are left out of the
+// wave box: their own cost is not finite under either scan.
 template <int NE>
-__device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds& s, bool act,
-                                                   float x, float y, float c, float sn, float v,
-                                                   float Ua, float Ud, float ea, float ed, int t,
-                                                   int t_lo, int t_hi)
+__device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds& s,
+                                                   const LaneCull& lc, bool vref_uniform, bool act,
+                                                   float x, float y,
+                                                   float c, float sn, float v, float Ua, float Ud,
+                                                   float ea, float ed, int t, int t_lo, int t_hi)
 {
     const int lane = threadIdx.x & 63;
-    const float bxlo = wave_minf(act ? x : INFINITY), bxhi = wave_maxf(act ? x : -INFINITY);
-    const float bylo = wave_minf(act ? y : INFINITY), byhi = wave_maxf(act ? y : -INFINITY);
+    const float ds = fmaf(d.d_safe_c, v, d.d_safe_0);
+    const bool inc = act && isfinite(x) && isfinite(y) && isfinite(ds);
+    const WaveBox wb = wave_box(inc, x, y, ds);
 
-    const int n_wp = d.n_wp;
-    const int n_ch = (n_wp + kChunk - 1) / kChunk;
-    float ub = INFINITY;
-    for (int base = 0; base < n_ch; base += 64) {
-        float m2 = INFINITY;
-        if (base + lane < n_ch) {
-            const float4 b = s.wp_box[base + lane];
-            const float dx = fmaxf(bxhi - b.x, b.y - bxlo);
-            const float dy = fmaxf(byhi - b.z, b.w - bylo);
-            m2 = fmaf(dy, dy, dx * dx);
-        }
-        ub = fminf(ub, wave_minf(m2));
-    }
-    const float thr = fmaf(ub, 1.0f + 1e-5f, 1e-6f);
+    // ---- waypoints
+    const int n_ch = (d.n_wp + kChunk - 1) / kChunk;
+    const const_ptr<float> wp4 = as_const(d.wp_xy);
     float best = INFINITY;
-    int bj = 0;
-    for (int base = 0; base < n_ch; base += 64) {
-        bool need = false;
-        if (base + lane < n_ch) {
-            const float4 b = s.wp_box[base + lane];
-            const float gx = fmaxf(fmaxf(b.x - bxhi, bxlo - b.y), 0.0f);
-            const float gy = fmaxf(fmaxf(b.z - byhi, bylo - b.w), 0.0f);
-            need = fmaf(gy, gy, gx * gx) <= thr;
-        }
-        unsigned long long m = __ballot(need);
-        while (m) {
-            const int ch = base + __builtin_ctzll(m);
-            m &= m - 1;
-            scan_chunk(s, ch, x, y, best, bj);
+    int bch = 0;
+    auto far2 = [&](const float4& b) {  // largest distance^2, wave box to chunk box
+        const float dx = fmaxf(wb.xhi - b.x, b.y - wb.xlo);
+        const float dy = fmaxf(wb.yhi - b.z, b.w - wb.ylo);
+        return fmaf(dy, dy, dx * dx);
+    };
+    auto near2 = [&](const float4& b) {  // smallest distance^2, wave box to chunk box
+        const float gx = fmaxf(fmaxf(b.x - wb.xhi, wb.xlo - b.y), 0.0f);
+        const float gy = fmaxf(fmaxf(b.z - wb.yhi, wb.ylo - b.w), 0.0f);
+        return fmaf(gy, gy, gx * gx);
+    };
+    if (n_ch <= 64) {
+        const float ub = wave_min_nonneg(far2(lc.box));
+        const float thr = fmaf(ub, 1.0f + 1e-5f, 1e-6f);
+        scan_chunks(wp4, 0, __ballot(near2(lc.box) <= thr), x, y, best, bch);
+    } else {
+        const float4 empty = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+        float ub = wave_min_nonneg(far2(lc.box));
+        for (int base = 64; base < n_ch; base += 64)
+            ub = fminf(ub, wave_min_nonneg(far2(base + lane < n_ch ? s.wp_box[base + lane] : empty)));
+        const float thr = fmaf(ub, 1.0f + 1e-5f, 1e-6f);
+        scan_chunks(wp4, 0, __ballot(near2(lc.box) <= thr), x, y, best, bch);
+        for (int base = 64; base < n_ch; base += 64) {
+            const float4 b = base + lane < n_ch ? s.wp_box[base + lane] : empty;
+            scan_chunks(wp4, base, __ballot(near2(b) <= thr), x, y, best, bch);
         }
     }
-    const float dv = v - s.wp_vref[bj];
+    // the reference speed of the closest waypoint (any one when all are equal)
+    const float vref = vref_uniform ? s.wp_vref[0] : s.wp_vref[chunk_argmin(s, bch, best, x, y)];
+    const float dv = v - vref;
     const float q = d.w_effort * (d.alpha * fmaf(ea, ea, ed * ed) + fmaf(Ua, ea, Ud * ed) +
                                   0.5f * fmaf(Ua, Ua, Ud * Ud));
     float cost = fmaf(d.w_track, best, fmaf(d.w_speed, dv * dv, q));
+
+    // ---- obstacle circles
     if (NE > 0) {
         float ex[NE > 0 ? NE : 1], ey[NE > 0 ? NE : 1];
 #pragma unroll
@@ -267,28 +436,32 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
             ex[e] = fmaf(d.ego_off[e], c, x);
             ey[e] = fmaf(d.ego_off[e], sn, y);
         }
-        const float ds = fmaf(d.d_safe_c, v, d.d_safe_0);
-        const float dsmax = wave_maxf(act ? ds : -INFINITY);
-        const float exlo = bxlo - d.ego_ext, exhi = bxhi + d.ego_ext;
-        const float eylo = bylo - d.ego_ext, eyhi = byhi + d.ego_ext;
+        const float exlo = wb.xlo - d.ego_ext, exhi = wb.xhi + d.ego_ext;
+        const float eylo = wb.ylo - d.ego_ext, eyhi = wb.yhi + d.ego_ext;
         const float tau_lo = (float)(t_lo + 1) * d.dt;
         const float tau_hi = (float)(t_hi + 1) * d.dt;
         const float tau = (float)(t + 1) * d.dt;
+        auto close = [&](const float4& p, float rr) {
+            const float xa = fmaf(tau_lo, p.z, p.x), xb = fmaf(tau_hi, p.z, p.x);
+            const float ya = fmaf(tau_lo, p.w, p.y), yb = fmaf(tau_hi, p.w, p.y);
+            const float gx = fmaxf(fmaxf(fminf(xa, xb) - exhi, exlo - fmaxf(xa, xb)), 0.0f);
+            const float gy = fmaxf(fmaxf(fminf(ya, yb) - eyhi, eylo - fmaxf(ya, yb)), 0.0f);
+            const float lim = wb.dsmax + rr + 0.01f;
+            return lim > 0.0f && fmaf(gy, gy, gx * gx) < lim * lim;
+        };
+        const const_ptr<float> cpv = as_const(d.c_pv);
+        const const_ptr<float> crr = as_const(d.c_rr);
         float d_obj = INFINITY;
         for (int base = 0; base < d.n_c; base += 64) {
-            bool need = false;
-            if (base + lane < d.n_c) {
-                const float4 p = s.c_pv[base + lane];
-                const float xa = fmaf(tau_lo, p.z, p.x), xb = fmaf(tau_hi, p.z, p.x);
-                const float ya = fmaf(tau_lo, p.w, p.y), yb = fmaf(tau_hi, p.w, p.y);
-                const float gx = fmaxf(fmaxf(fminf(xa, xb) - exhi, exlo - fmaxf(xa, xb)), 0.0f);
-                const float gy = fmaxf(fmaxf(fminf(ya, yb) - eyhi, eylo - fmaxf(ya, yb)), 0.0f);
-                const float lim = dsmax + s.c_rr[base + lane] + 0.01f;
-                need = lim > 0.0f && fmaf(gy, gy, gx * gx) < lim * lim;
+            bool need;
+            if (base == 0) {
+                need = close(lc.cpv, lc.crr);
+            } else {
+                need = base + lane < d.n_c && close(s.c_pv[base + lane], s.c_rr[base + lane]);
             }
             unsigned long long m = __ballot(need);
             while (m) {
-                // up to four candidates per round: every load issued, one wait
+                // up to four candidates per round trip, merged in index order
                 int idx[4];
                 int cnt = 0;
 #pragma unroll
@@ -301,23 +474,12 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
                 float rr[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    p[u] = s.c_pv[idx[u]];
-                    rr[u] = s.c_rr[idx[u]];
+                    p[u] = ld4(cpv, idx[u]);
+                    rr[u] = crr[idx[u]];
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (u < cnt) {
-                        const float ox = fmaf(tau, p[u].z, p[u].x);
-                        const float oy = fmaf(tau, p[u].w, p[u].y);
-#pragma unroll
-                        for (int e = 0; e < NE; ++e) {
-                            const float dx = ex[e] - ox;
-                            const float dy = ey[e] - oy;
-                            d_obj = fminf(d_obj,
-                                          __builtin_amdgcn_sqrtf(fmaf(dy, dy, dx * dx)) - rr[u]);
-                        }
-                    }
-                }
+                for (int u = 0; u < 4; ++u)
+                    if (u < cnt) d_obj = fminf(d_obj, circle_gap<NE>(ex, ey, p[u], rr[u], tau));
             }
         }
         const float g = ds - d_obj;
@@ -384,10 +546,16 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         s.c_rr[i] = d.c_rr[i];
     }
     const int n_wp_pad = (d.n_wp + kChunk - 1) / kChunk * kChunk;
+    const float vref0 = d.wp_vref[0];
+    bool same_vref = true;
     for (int i = tid; i < n_wp_pad; i += kBlock) {
         // padding points at infinity are never the closest
         s.wp_xy[i] = i < d.n_wp ? d.wp_xy[i] : make_float2(INFINITY, INFINITY);
-        if (i < d.n_wp) s.wp_vref[i] = d.wp_vref[i];
+        if (i < d.n_wp) {
+            const float vr = d.wp_vref[i];
+            s.wp_vref[i] = vr;
+            same_vref = same_vref && vr == vref0;
+        }
     }
     for (int c = tid; c * kChunk < d.n_wp; c += kBlock) {
         float4 b = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
@@ -403,7 +571,8 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     for (int i = tid; i < T; i += kBlock)
         s.U[i] = make_float2((float)d.U[2 * i], (float)d.U[2 * i + 1]);
     const unsigned long long n_iter = d.st->n_iter;
-    __syncthreads();
+    // one reference speed for every waypoint: the closest index is not needed
+    const bool vref_uniform = __syncthreads_and(same_vref) != 0;
 
     // ---------------------------------------------------------------- phase 1
     const int grp = tid / G;
@@ -413,57 +582,68 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     const bool valid = k < K;
     const int kk = valid ? k : K - 1;  // idle groups replay the last sample
 
+    LaneCull lc;
+    {
+        const int lane = tid & 63;
+        const int n_ch = (d.n_wp + kChunk - 1) / kChunk;
+        lc.box = lane < n_ch ? s.wp_box[lane] : make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+        lc.cpv = lane < d.n_c ? s.c_pv[lane] : make_float4(INFINITY, INFINITY, 0.0f, 0.0f);
+        lc.crr = lane < d.n_c ? s.c_rr[lane] : 0.0f;
+    }
     float x = d.px0, y = d.py0, th = d.th0, v = d.v0;
     float c = __cosf(th), sn = __sinf(th);
     float S = 0.0f, comp = 0.0f;  // Kahan pair of this lane's steps
     for (int t0 = 0; t0 < T; t0 += G) {
         const int tm = t0 + r;
-        const float2 em = draw_noise(d, kk, tm < T ? tm : T - 1, n_iter);
-        float mx = 0.f, my = 0.f, mc = 1.f, ms = 0.f, mv = 0.f;
-        float mUa = 0.f, mUd = 0.f, mea = 0.f, med = 0.f;
-        constexpr int PF = G < 4 ? G : 4;  // steps whose inputs are fetched together
-        float2 Upf[PF], epf[PF];
+        const int tc = tm < T ? tm : T - 1;
+        // This lane's step: perturbation, the state-independent part of the
+        // noise check (control bounds) and the steering tangent, computed
+        // once per step and handed to the G lanes that integrate it.
+        const float2 em = draw_noise(d, kk, tc, n_iter);
+        const float2 Um = s.U[tc];
+        const float a0m = fminf(fmaxf(Um.x + em.x, d.a_min), d.a_max);
+        const float dlm = fminf(fmaxf(Um.y + em.y, d.d_min), d.d_max);
+        const float tnm = __tanf(dlm);
+        float mx = 0.f, my = 0.f, mc = 1.f, ms = 0.f, mv = 0.f, ma = 0.f;
+        constexpr int PF = G < 4 ? G : 4;  // steps whose inputs are exchanged together
+        float apf[PF], tpf[PF];
 #pragma unroll
         for (int i = 0; i < G; ++i) {
             const int t = t0 + i;
             if (i % PF == 0) {
 #pragma unroll
                 for (int u = 0; u < PF; ++u) {
-                    Upf[u] = s.U[min(t + u, T - 1)];
-                    epf[u] = em;
+                    apf[u] = a0m;
+                    tpf[u] = tnm;
                     if (G > 1) {
                         const int src = (tid & ~(G - 1)) + i + u;
-                        epf[u] = make_float2(__shfl(em.x, src, 64), __shfl(em.y, src, 64));
+                        apf[u] = __shfl(a0m, src, 64);
+                        tpf[u] = __shfl(tnm, src, 64);
                     }
                 }
             }
             if (G > 1 && t >= T) continue;
-            const float ea = epf[i % PF].x, ed = epf[i % PF].y;
-            const float2 Ut = Upf[i % PF];
-            // noise check: bounds, speed cap, braking bound last
-            float a = fminf(fmaxf(Ut.x + ea, d.a_min), d.a_max);
-            a = fminf(a, (d.v_max - v) * d.inv_dt);
+            // noise check: speed cap, braking bound last
+            float a = fminf(apf[i % PF], (d.v_max - v) * d.inv_dt);
             a = fmaxf(a, d.a_min);
-            const float dl = fminf(fmaxf(Ut.y + ed, d.d_min), d.d_max);
             // eq. (5), explicit Euler from the old state
             const float vdt = v * d.dt;
-            const float tn = __tanf(dl);
             x = fmaf(vdt, c, x);
             y = fmaf(vdt, sn, y);
-            th = fmaf(vdt * d.inv_L, tn, th);
+            th = fmaf(vdt * d.inv_L, tpf[i % PF], th);
             v = fmaf(d.dt, a, v);
             c = __cosf(th);
             sn = __sinf(th);
             if (i == r) {
-                mx = x; my = y; mc = c; ms = sn; mv = v;
-                mUa = Ut.x; mUd = Ut.y;
-                mea = a - Ut.x; med = dl - Ut.y;
+                mx = x; my = y; mc = c; ms = sn; mv = v; ma = a;
             }
         }
+        const float mUa = Um.x, mUd = Um.y;
+        const float mea = ma - Um.x, med = dlm - Um.y;
         const bool act = tm < T;
         float q = 0.0f;
         if (d.cull)
-            q = stage_cost_culled<NE>(d, s, act, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm, t0,
+            q = stage_cost_culled<NE>(d, s, lc, vref_uniform, act, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm, t0,
                                       min(t0 + G, T) - 1);
         else if (act)
             q = stage_cost<NE>(d, s, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm);
