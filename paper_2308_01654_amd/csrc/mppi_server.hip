@@ -13,9 +13,10 @@
 //    ones wait behind it.
 //  * Continuous batching: whenever one of the server's streams is idle, the
 //    scheduler thread launches every admissible request as one batch (one
-//    launch per kernel variant, replayed as a HIP graph).  Batches on
-//    different streams overlap on the device; a completion thread per stream
-//    copies the results back and stamps completion times.
+//    direct launch per kernel variant present: batch compositions rarely
+//    repeat, so they are not captured as graphs).  Batches on different
+//    streams overlap on the device; a completion thread per stream copies the
+//    results back and stamps completion times.
 //  * Latency = completion - arrival stamp given at submit (the replay driver
 //    stamps the scheduled arrival, so queueing before submission counts).
 #include <hip/hip_runtime.h>
