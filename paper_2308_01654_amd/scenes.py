@@ -263,5 +263,28 @@ def tiny(K=8, T=4, n_c=3, seed=7):
                 iterations=1)
 
 
+def speed_profile(sc, seed=0, n_dup=12):
+    """A copy of scene sc whose waypoints carry a varying reference speed (a
+    smooth profile along x) and n_dup exactly repeated waypoints: the repeat
+    follows the original at the next index, with a reference speed 10 m/s
+    higher, so the closest index must be the lower of the two.  Repeats are
+    forced at indices that end a chunk of 8 consecutive waypoints."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    wp = np.array(sc["waypoints"], dtype=np.float64)
+    wp[:, 3] = 12.0 + np.sin(wp[:, 0] / 15.0)
+    pick = set(rng.choice(len(wp), size=min(n_dup, len(wp)), replace=False).tolist())
+    rows = []
+    for j in range(len(wp)):
+        rows.append(wp[j])
+        if j in pick or len(rows) % 8 == 0:
+            dup = wp[j].copy()
+            dup[3] += 10.0
+            rows.append(dup)
+    out = dict(sc)
+    out["waypoints"] = np.array(rows)
+    out["name"] = sc["name"] + "_speed"
+    return out
+
+
 def by_name(name):
     return {"c0": c0, "c1": c1, "c4": c4, "paper_table1": paper_table1, "tiny": tiny}[name]()

@@ -294,3 +294,28 @@ def test_culled_scans_bit_identical_to_full_scans(name, lanes):
             outs.append((pl.costs(), pl.noise(), pl.controls()))
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("lanes,n_c", [(1, 0), (8, 0), (16, 0), (8, 40)])
+def test_varying_reference_speed_and_repeated_waypoints(lanes, n_c):
+    """Per-waypoint reference speeds with exactly repeated waypoint positions
+    (the repeat has a reference speed 10 m/s higher, some repeats straddle
+    chunks of 8): the closest index, lowest on ties, picks the reference
+    speed.  The culled scan (minimum first, index resolved afterwards)
+    equals the full scan bit for bit, and both meet the staged gates."""
+    mppi = _mppi()
+    # without circles the costs are tracking and speed terms of order 1e3, so
+    # a wrong pick among repeated waypoints (10 m/s apart) fails gate D2
+    sc = scenes.speed_profile(scenes.tiny(K=3000, T=45, n_c=n_c, seed=5), seed=9)
+    p = sc["params"]
+    _say("speed profile lanes", lanes, "circles", n_c, "waypoints", len(sc["waypoints"]))
+    outs = []
+    for cull in (True, False):
+        with mppi.Planner(p, lanes=lanes) as pl:
+            pl.set_culling(cull)
+            g = P.gpu_step(pl, sc)
+            rep = P.staged(p, sc, g, n_iter=0)
+            P.assert_staged(rep)
+            outs.append((g["S"], g["eps"], g["U"]))
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
