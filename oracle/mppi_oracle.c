@@ -57,6 +57,16 @@
  *   - a non-finite S_k counts as +inf; if every S_k is non-finite the
  *     iteration fails and U is left unchanged.
  *
+ * The last steps of Algorithm 1 (optional, cfg.smoothing = 1):
+ *   u*    = SavitzkyGolay(U)                        eq. (sg): the 5-point
+ *           window (-3, 12, 17, 12, -3)/35; beyond either end of the
+ *           sequence the end value is repeated (the paper leaves the ends
+ *           open).  The smoothed sequence replaces U, so the warm start of
+ *           the next iteration shifts u* as Alg. 1 does.
+ *   x*_0 = x0, x*_{t+1} = F(x*_t, u*_t)             the optimal rollout; each
+ *           u*_t goes through the same noise check as the samples (with zero
+ *           noise), so the output trajectory {x*, u*} respects the bounds.
+ *
  * Build: gcc -O2 -fopenmp -shared -fPIC -o liboracle.so mppi_oracle.c -lm
  */
 #include <math.h>
@@ -77,6 +87,7 @@ typedef struct orc_cfg {
     double ego_r;
     double ego_off[4];
     uint64_t seed;
+    int32_t smoothing;  /* 1: Savitzky-Golay smoothing ends the iteration */
 } orc_cfg;
 
 enum { ORC_OK = 0, ORC_E_INVALID = -1, ORC_E_NONFINITE = -4 };
@@ -399,6 +410,39 @@ void orc_update(double* U, int T, int K, const double* w, const double* eps)
     }
 }
 
+/* Eq. (sg): out[t] = (-3 u[t-2] + 12 u[t-1] + 17 u[t] + 12 u[t+1] - 3 u[t+2]) / 35
+ * for each control, with u[i] = u[0] for i < 0 and u[i] = u[T-1] for i >= T. */
+void orc_sg_smooth(const double* U, int T, double* out)
+{
+    static const double z[5] = {-3.0, 12.0, 17.0, 12.0, -3.0};
+    for (int t = 0; t < T; ++t) {
+        for (int d = 0; d < 2; ++d) {
+            double acc = 0.0;
+            for (int j = -2; j <= 2; ++j) {
+                int i = t + j;
+                if (i < 0) i = 0;
+                if (i > T - 1) i = T - 1;
+                acc += z[j + 2] * U[2 * i + d];
+            }
+            out[2 * t + d] = acc / 35.0;
+        }
+    }
+}
+
+/* The optimal rollout of Alg. 1 from x0 under the controls Us [T][2]: each
+ * control passes the noise check with zero noise, states [T+1][4] and the
+ * applied controls [T][2] are returned. */
+void orc_optimal_trajectory(const orc_cfg* c, const double x0[4], const double* Us,
+                            double* states, double* applied)
+{
+    static const double zero[2] = {0.0, 0.0};
+    memcpy(states, x0, 4 * sizeof(double));
+    for (int t = 0; t < c->T; ++t) {
+        orc_apply_limits(c, Us + 2 * t, zero, states[4 * t + 3], applied + 2 * t);
+        orc_dynamics(c, states + 4 * t, applied + 2 * t, states + 4 * (t + 1));
+    }
+}
+
 /* One full iteration; U is updated in place only on success.
  * Optional outputs: S[K], w[K], eps[T][K][2]. */
 int orc_iteration(const orc_cfg* c, const double x0[4], const double* wp, int n_wp,
@@ -414,6 +458,16 @@ int orc_iteration(const orc_cfg* c, const double x0[4], const double* wp, int n_
     if (rc == ORC_OK) rc = orc_rollout(c, x0, wp, n_wp, circ, n_c, U, n_iter, NULL, S, e);
     if (rc == ORC_OK) rc = orc_weights(S, c->K, c->lambda, w, s_min, log_z);
     if (rc == ORC_OK) orc_update(U, c->T, c->K, w, e);
+    if (rc == ORC_OK && c->smoothing) {
+        double* sm = (double*)malloc(T * 2 * sizeof(double));
+        if (!sm) {
+            rc = ORC_E_INVALID;
+        } else {
+            orc_sg_smooth(U, c->T, sm);
+            memcpy(U, sm, T * 2 * sizeof(double));
+            free(sm);
+        }
+    }
     if (!S_out) free(S);
     if (!w_out) free(w);
     if (!eps_out) free(e);

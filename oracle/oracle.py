@@ -43,6 +43,7 @@ class OrcCfg(ctypes.Structure):
         ("n_ego", ctypes.c_int32), ("ego_r", ctypes.c_double),
         ("ego_off", ctypes.c_double * 4),
         ("seed", ctypes.c_uint64),
+        ("smoothing", ctypes.c_int32),
     ]
 
 
@@ -88,6 +89,8 @@ def lib():
             L.orc_update.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, dp]
             L.orc_iteration.argtypes = [cp, dp, dp, ctypes.c_int, dp, ctypes.c_int, dp,
                                         ctypes.c_uint64, dp, dp, dp, dp, dp]
+            L.orc_sg_smooth.argtypes = [dp, ctypes.c_int, dp]
+            L.orc_optimal_trajectory.argtypes = [cp, dp, dp, dp, dp]
             _lib = L
     return _lib
 
@@ -123,6 +126,7 @@ def make_cfg(p) -> OrcCfg:
     for i, o in enumerate(offs):
         c.ego_off[i] = float(o)
     c.seed = int(p["seed"])
+    c.smoothing = int(p.get("smoothing", 0))
     return c
 
 
@@ -302,3 +306,23 @@ def iteration(p, x0, waypoints, circles, U, n_iter=0):
     if rc != OK:
         raise ValueError("orc_iteration: status %d" % rc)
     return dict(U=Un, S=S, w=w, eps=eps, s_min=smin.value, log_z=logz.value)
+
+
+def sg_smooth(U):
+    """Savitzky-Golay smoothing of eq. (sg) with repeated end values: [T][2]."""
+    U = _f64(U).reshape(-1, 2)
+    out = np.zeros_like(U)
+    lib().orc_sg_smooth(_dp(U), U.shape[0], _dp(out))
+    return out
+
+
+def optimal_trajectory(p, x0, Us):
+    """Optimal rollout of Alg. 1 from x0 under controls Us (each through the
+    noise check with zero noise).  Returns (states [T+1][4], applied [T][2])."""
+    c = make_cfg(p)
+    Us = _f64(Us, (c.T, 2))
+    x0 = _f64(x0)
+    states = np.zeros((c.T + 1, 4))
+    applied = np.zeros((c.T, 2))
+    lib().orc_optimal_trajectory(ctypes.byref(c), _dp(x0), _dp(Us), _dp(states), _dp(applied))
+    return states, applied

@@ -512,3 +512,96 @@ def test_philox_batch_matches_single():
     out = O.philox_batch(ctrs, [0x1234, 0xABCD])
     for c, o in zip(ctrs, out):
         assert O.philox(list(c), [0x1234, 0xABCD]) == [int(v) for v in o]
+
+
+# ---- the last steps of Alg. 1: Savitzky-Golay smoothing and the optimal rollout
+
+def test_sg_window_is_scipys_quadratic_five_point_window():
+    """Eq. (sg)'s coefficients (-3, 12, 17, 12, -3)/35 are the 5-point
+    quadratic Savitzky-Golay smoothing window; scipy derives it independently
+    by least squares.  The oracle's filter applied to a unit impulse in the
+    interior returns the window itself."""
+    from scipy.signal import savgol_coeffs
+    assert np.allclose(savgol_coeffs(5, 2) * 35.0, [-3, 12, 17, 12, -3], atol=1e-12)
+    U = np.zeros((11, 2))
+    U[5, 0] = 1.0
+    U[5, 1] = -2.0
+    out = O.sg_smooth(U)
+    assert np.allclose(out[3:8, 0], np.array([-3, 12, 17, 12, -3])[::-1] / 35.0, atol=1e-15)
+    assert np.allclose(out[3:8, 1], -2.0 * np.array([-3, 12, 17, 12, -3])[::-1] / 35.0, atol=1e-15)
+    assert np.all(out[:3] == 0) and np.all(out[8:] == 0)
+
+
+@pytest.mark.parametrize("T", [1, 2, 3, 4, 5, 9, 100])
+def test_sg_matches_scipy_filter_with_repeated_ends(T):
+    """The whole filter, ends included, equals scipy's savgol_filter with the
+    'nearest' extension (the end values repeated) -- an independent
+    implementation of the same definition."""
+    from scipy.signal import savgol_filter
+    U = np.random.Generator(np.random.PCG64(T)).normal(size=(T, 2))
+    if T >= 5:
+        ref = savgol_filter(U, 5, 2, axis=0, mode="nearest")
+    else:
+        # scipy needs the window inside the data: extend by repetition by hand
+        ext = np.concatenate([np.repeat(U[:1], 2, 0), U, np.repeat(U[-1:], 2, 0)])
+        ref = np.stack([(-3 * ext[t] + 12 * ext[t + 1] + 17 * ext[t + 2] + 12 * ext[t + 3]
+                         - 3 * ext[t + 4]) / 35.0 for t in range(T)])
+    assert np.allclose(O.sg_smooth(U), ref, rtol=0, atol=1e-14)
+
+
+def test_sg_preserves_cubics_in_the_interior_and_constants_everywhere():
+    """A symmetric quadratic Savitzky-Golay window reproduces polynomials up
+    to degree three away from the ends; repeated end values keep a constant
+    sequence constant at the ends too."""
+    t = np.arange(40, dtype=np.float64)
+    U = np.stack([0.3 - 0.2 * t + 0.01 * t ** 2 - 1e-4 * t ** 3, 0.05 + 0.002 * t], axis=1)
+    out = O.sg_smooth(U)
+    assert np.allclose(out[2:-2], U[2:-2], rtol=0, atol=1e-12)
+    C = np.tile([0.7, -0.1], (9, 1))
+    assert np.allclose(O.sg_smooth(C), C, rtol=0, atol=1e-15)
+    # a linear ramp at the first end: (-3*0 + 12*0 + 17*0 + 12*1 - 3*2)/35
+    R = np.stack([np.arange(6.0), np.zeros(6)], axis=1)
+    assert abs(O.sg_smooth(R)[0, 0] - 6.0 / 35.0) < 1e-15
+
+
+def test_smoothing_iteration_ends_with_the_smoothed_update():
+    """With smoothing on, the iteration's controls are the eq. (sg) filter of
+    the plain update, computed on the same samples."""
+    sc = scenes.tiny(K=64, T=12, n_c=2, seed=3)
+    p = dict(sc["params"])
+    U0 = np.tile([0.2, 0.01], (p["T"], 1))
+    plain = O.iteration(p, sc["x0"], sc["waypoints"], sc["circles"], U0, n_iter=2)
+    p["smoothing"] = 1
+    sm = O.iteration(p, sc["x0"], sc["waypoints"], sc["circles"], U0, n_iter=2)
+    assert np.array_equal(sm["S"], plain["S"]) and np.array_equal(sm["w"], plain["w"])
+    from scipy.signal import savgol_filter
+    assert np.allclose(sm["U"], savgol_filter(plain["U"], 5, 2, axis=0, mode="nearest"),
+                       rtol=0, atol=1e-14)
+
+
+def test_optimal_trajectory_straight_line_closed_form():
+    """Constant controls inside every bound on a straight heading: x_T =
+    x0 + T v0 dt + a dt^2 T (T-1) / 2, y stays 0, v_T = v0 + T a dt."""
+    p = _p(T=20, dt=0.1, v_max=100.0)
+    a = 0.5
+    Us = np.tile([a, 0.0], (20, 1))
+    x0 = np.array([1.0, 0.0, 0.0, 8.0])
+    st_, ap = O.optimal_trajectory(p, x0, Us)
+    T, dt = 20, 0.1
+    assert abs(st_[-1, 0] - (1.0 + T * 8.0 * dt + a * dt * dt * T * (T - 1) / 2)) < 1e-12
+    assert np.all(st_[:, 1] == 0.0) and abs(st_[-1, 3] - (8.0 + T * a * dt)) < 1e-12
+    assert np.array_equal(ap, Us)
+
+
+def test_optimal_trajectory_respects_bounds_and_speed_cap():
+    """Controls outside the bounds are clamped, and the speed never exceeds
+    v_max (the noise check with zero noise)."""
+    p = _p(T=30, dt=0.1, v_max=10.0)
+    Us = np.tile([5.0, 2.0], (30, 1))       # both beyond u_max
+    st_, ap = O.optimal_trajectory(p, np.array([0.0, 0.0, 0.0, 9.5]), Us)
+    assert np.all(ap[:, 1] == p["u_max"][1])
+    assert np.all(ap[:, 0] <= p["u_max"][0]) and np.all(ap[:, 0] >= p["u_min"][0])
+    assert np.all(st_[:, 3] <= 10.0 + 1e-12)
+    Us = np.tile([-9.0, -2.0], (30, 1))     # below u_min
+    _, ap = O.optimal_trajectory(p, np.array([0.0, 0.0, 0.0, 9.5]), Us)
+    assert np.all(ap == np.array(p["u_min"]))
