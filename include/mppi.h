@@ -85,6 +85,10 @@ typedef struct mppi_config {
     uint64_t seed;         /* Philox key                                                */
     int32_t max_waypoints; /* capacity for mppi_scene.n_waypoints, 1..2048              */
     int32_t max_circles;   /* capacity for mppi_scene.n_circles, 0..1024                */
+    int32_t smoothing;     /* 1: end every iteration with the Savitzky-Golay filter of
+                              eq. (sg) (window (-3,12,17,12,-3)/35, end values repeated
+                              beyond the horizon), which replaces U -- the last steps of
+                              Alg. 1, so a warm-start shift then shifts u*; 0: off      */
 } mppi_config;
 
 /* Scene and road model of one request, world coordinates. */
@@ -188,6 +192,19 @@ mppi_status mppi_set_state(mppi_t* h, const double* U, size_t n, uint64_t n_iter
 mppi_status mppi_get_costs(mppi_t* h, float* out, size_t n);
 mppi_status mppi_get_weights(mppi_t* h, double* out, size_t n);
 mppi_status mppi_get_noise(mppi_t* h, float* out, size_t n);
+
+/* The optimal trajectory of Alg. 1 (the rollout after the update): from the
+ * x0 of the last completed step, x*_{t+1} = F(x*_t, u*_t) (eq. (5), explicit
+ * Euler) under the handle's current nominal controls u* (the smoothed
+ * sequence when cfg.smoothing = 1), each control put through the noise check
+ * with zero noise so that the trajectory respects the bounds and the speed
+ * cap.  Computed in float64 on the device; synchronises the handle's stream.
+ * states: [T+1][4] world-frame (x, y, yaw, v), n_states >= 4 (T+1);
+ * controls: [T][2] applied (a, delta), n_controls >= 2T (either may be NULL).
+ * MPPI_E_INVALID before the first step or for short buffers (nothing
+ * written). */
+mppi_status mppi_get_trajectory(mppi_t* h, double* states, size_t n_states, double* controls,
+                                size_t n_controls);
 mppi_status mppi_get_iter_stats(mppi_t* h, mppi_iter_stats* out);
 
 /* Launch shape: lanes cooperating on one sample (1, 2, 4, 8 or 16), or 0 to

@@ -99,6 +99,8 @@ mppi_status validate_config(const mppi_config* c)
     if (c->max_circles < 0 || c->max_circles > kMaxCircles)
         return fail(MPPI_E_INVALID, "max_circles=%d outside [0, %d]", c->max_circles,
                     kMaxCircles);
+    if (c->smoothing != 0 && c->smoothing != 1)
+        return fail(MPPI_E_INVALID, "smoothing must be 0 or 1");
     return MPPI_OK;
 }
 
@@ -287,6 +289,7 @@ void handle_release(mppi_t* h)
     (void)hipFree(h->eps);
     (void)hipFree(h->partials);
     (void)hipFree(h->wbuf);
+    (void)hipFree(h->traj);
     (void)hipFree(h->st);
     (void)hipFree(h->scene);
     if (h->batch) {
@@ -327,6 +330,8 @@ mppi_status handle_create(const mppi_config* cfg, void* hip_stream, bool with_sc
         h->own_stream = true;
     }
     if ((e = hipMalloc((void**)&h->U, sizeof(double) * 2 * T)) != hipSuccess ||
+        (e = hipMalloc((void**)&h->traj, sizeof(double) * (4 * (size_t)(T + 1) + 2 * T))) !=
+            hipSuccess ||
         (e = hipMalloc((void**)&h->st, state_bytes(h->max_tiles))) != hipSuccess)
         return bail(MPPI_E_NOMEM, "hipMalloc", e);
     if (with_scratch) {
@@ -402,6 +407,7 @@ void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double or
     d.key1 = (uint32_t)(c.seed >> 32);
     d.shift = shift;
     d.cull = h->no_cull ? 0 : 1;
+    d.smooth = c.smoothing;
     d.ego_ext = 0.f;
     for (int e = 0; e < c.n_ego; ++e) d.ego_ext = fmaxf(d.ego_ext, (float)fabs(c.ego_off[e]));
     d.out_slot = -1;
@@ -642,6 +648,7 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
     for (int j = 0; j < n; ++j) {
         hs[order[j]]->stepped = true;
         hs[order[j]]->last_lanes = descs[j].lanes;
+        memcpy(hs[order[j]]->last_x0, x0s + 4 * order[j], sizeof(double) * 4);
     }
     return MPPI_OK;
 }
@@ -729,6 +736,7 @@ mppi_status mppi_step_resident(mppi_t* h, const double x0[4])
     if ((s = record_end(h, 0, a)) != MPPI_OK) return s;
     h->last_lanes = d.lanes;
     h->stepped = true;
+    memcpy(h->last_x0, x0, sizeof(double) * 4);
     return MPPI_OK;
 }
 
@@ -872,6 +880,38 @@ mppi_status mppi_get_noise(mppi_t* h, float* out, size_t n)
     if (!out || n < need) return fail(MPPI_E_INVALID, "buffer needs 2*T*K floats");
     HIP_TRY(hipStreamSynchronize(h->stream));
     HIP_TRY(hipMemcpy(out, h->eps, sizeof(float) * need, hipMemcpyDeviceToHost));
+    return MPPI_OK;
+}
+
+mppi_status mppi_get_trajectory(mppi_t* h, double* states, size_t n_states, double* controls,
+                                size_t n_controls)
+{
+    mppi_status s = usable(h);
+    if (s != MPPI_OK) return s;
+    const int T = h->cfg.T;
+    if (!h->stepped) return fail(MPPI_E_INVALID, "no step has been taken");
+    if (states && n_states < (size_t)4 * (T + 1))
+        return fail(MPPI_E_INVALID, "states needs 4*(T+1) doubles");
+    if (controls && n_controls < (size_t)2 * T)
+        return fail(MPPI_E_INVALID, "controls needs 2*T doubles");
+    TrajArgs a;
+    const mppi_config& c = h->cfg;
+    for (int i = 0; i < 4; ++i) a.x0[i] = h->last_x0[i];
+    a.T = T;
+    a.dt = c.dt;
+    a.wheelbase = c.wheelbase;
+    a.a_min = c.u_min[0];
+    a.a_max = c.u_max[0];
+    a.d_min = c.u_min[1];
+    a.d_max = c.u_max[1];
+    a.v_max = c.v_max;
+    HIP_TRY(launch_trajectory(a, h->U, h->traj, h->traj + 4 * (size_t)(T + 1), h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    if (states)
+        HIP_TRY(hipMemcpy(states, h->traj, sizeof(double) * 4 * (T + 1), hipMemcpyDeviceToHost));
+    if (controls)
+        HIP_TRY(hipMemcpy(controls, h->traj + 4 * (size_t)(T + 1), sizeof(double) * 2 * T,
+                          hipMemcpyDeviceToHost));
     return MPPI_OK;
 }
 

@@ -75,6 +75,7 @@ struct mppi {
     float2* eps = nullptr;
     double* partials = nullptr;
     double* wbuf = nullptr;  // [K] weights export
+    double* traj = nullptr;  // optimal trajectory: states [T+1][4], controls [T][2]
     mppi_impl::DevState* st = nullptr;
     unsigned char* scene = nullptr;
     size_t scene_cap = 0;
@@ -92,6 +93,7 @@ struct mppi {
     mppi_impl::SceneLayout lay = {0, 0, 0, 0, 0};
     // last step
     bool stepped = false;
+    double last_x0[4] = {0.0, 0.0, 0.0, 0.0};
     // profiling
     bool prof = false;
     std::vector<mppi_impl::ProfEvent> events;

@@ -69,6 +69,7 @@ struct InstDesc {
     uint32_t key0, key1;  // Philox key = seed
     int shift;            // shift U by one step before the iteration (warm start)
     int cull;             // wave-level culling of waypoint chunks and circles
+    int smooth;           // end with the Savitzky-Golay filter of eq. (sg)
     float ego_ext;        // max |ego_off|
     int out_slot;         // slot in the gathered results of a batch (-1: none)
     // device pointers
@@ -142,6 +143,16 @@ hipError_t launch_shift_batch(const BatchHdr* hdr_dev, int n_inst, hipStream_t s
 hipError_t launch_gather(const BatchHdr* hdr_dev, int n_inst, double* out, int slot_doubles,
                          hipStream_t stream);
 hipError_t launch_weights(const InstDesc& d, double* w_out, hipStream_t stream);
+
+// Optimal rollout of Alg. 1 (float64, world frame) from x0 under the nominal
+// controls U [T][2]: states [T+1][4] and applied controls [T][2].
+struct TrajArgs {
+    double x0[4];
+    int T;
+    double dt, wheelbase, a_min, a_max, d_min, d_max, v_max;
+};
+hipError_t launch_trajectory(const TrajArgs& a, const double* U, double* states, double* applied,
+                             hipStream_t stream);
 hipError_t launch_shift(double* U, int T, int steps, hipStream_t stream);
 hipError_t launch_copy(const float4* src, float4* dst, size_t n16, hipStream_t stream);
 hipError_t launch_debug_philox(uint32_t key0, uint32_t key1, unsigned long long n_iter,

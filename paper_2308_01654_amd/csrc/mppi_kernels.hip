@@ -775,10 +775,29 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
                 for (int u = 0; u < 8; ++u)
                     if (i0 + u < nc) acc += pv[u] * sc_lds[i0 + u];
             }
-            if (root) d.U[col] += acc / zz;
-            else rows[kPartialHead + col] = acc;
+            if (root) {
+                const double un = d.U[col] + acc / zz;
+                // with smoothing the updated sequence is staged in the root row
+                if (d.smooth) rows[kPartialHead + col] = un;
+                else d.U[col] = un;
+            } else {
+                rows[kPartialHead + col] = acc;
+            }
         }
         if (root) {
+            if (d.smooth) {
+                // eq. (sg): u*_t = (-3 u_{t-2} + 12 u_{t-1} + 17 u_t + 12 u_{t+1}
+                // - 3 u_{t+2}) / 35, the end values repeated beyond the horizon
+                __syncthreads();
+                const double* un = rows + kPartialHead;
+                for (int col = tid; col < 2 * T; col += kBlock) {
+                    const int t = col >> 1, c2 = col & 1;
+                    auto at = [&](int i) { return un[2 * min(max(i, 0), T - 1) + c2]; };
+                    const double sm = -3.0 * at(t - 2) + 12.0 * at(t - 1) + 17.0 * at(t) +
+                                      12.0 * at(t + 1) - 3.0 * at(t + 2);
+                    d.U[col] = sm / 35.0;
+                }
+            }
             if (tid == 0) {
                 d.st->s_min = mm;
                 d.st->z = zz;
@@ -798,6 +817,40 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         n_l = (n_l + kFanIn - 1) / kFanIn;
         idx = g;
         span *= kFanIn;
+    }
+}
+
+// Optimal rollout of Alg. 1 in float64 and world coordinates: from x0,
+// x*_{t+1} = F(x*_t, u*_t) (eq. (5), explicit Euler from the old state), each
+// nominal control put through the noise check with zero noise (bounds, speed
+// cap, braking bound last).  One thread walks the horizon.
+__global__ void k_trajectory(TrajArgs a, const double* __restrict__ U, double* __restrict__ xs,
+                             double* __restrict__ us)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double x = a.x0[0], y = a.x0[1], th = a.x0[2], v = a.x0[3];
+    xs[0] = x;
+    xs[1] = y;
+    xs[2] = th;
+    xs[3] = v;
+    for (int t = 0; t < a.T; ++t) {
+        double acc = fmin(fmax(U[2 * t], a.a_min), a.a_max);
+        acc = fmax(fmin(acc, (a.v_max - v) / a.dt), a.a_min);
+        const double dl = fmin(fmax(U[2 * t + 1], a.d_min), a.d_max);
+        const double vdt = a.dt * v;
+        const double xn = x + vdt * cos(th);
+        const double yn = y + vdt * sin(th);
+        const double thn = th + vdt * tan(dl) / a.wheelbase;
+        v += a.dt * acc;
+        x = xn;
+        y = yn;
+        th = thn;
+        us[2 * t] = acc;
+        us[2 * t + 1] = dl;
+        xs[4 * (t + 1)] = x;
+        xs[4 * (t + 1) + 1] = y;
+        xs[4 * (t + 1) + 2] = th;
+        xs[4 * (t + 1) + 3] = v;
     }
 }
 
@@ -924,6 +977,13 @@ __global__ void k_weights(const float* __restrict__ S, int K, double lambda,
     if (k >= K) return;
     const float sk = S[k];
     w[k] = isfinite(sk) ? exp(-((double)sk - st->s_min) / lambda) / st->z : 0.0;
+}
+
+hipError_t launch_trajectory(const TrajArgs& a, const double* U, double* states, double* applied,
+                             hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_trajectory, dim3(1), dim3(64), 0, stream, a, U, states, applied);
+    return hipGetLastError();
 }
 
 hipError_t launch_weights(const InstDesc& d, double* w_out, hipStream_t stream)

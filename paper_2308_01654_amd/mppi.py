@@ -47,6 +47,7 @@ class Config(ctypes.Structure):
         ("ego_off", ctypes.c_double * 4),
         ("seed", ctypes.c_uint64),
         ("max_waypoints", ctypes.c_int32), ("max_circles", ctypes.c_int32),
+        ("smoothing", ctypes.c_int32),
     ]
 
 
@@ -123,6 +124,7 @@ SIGNATURES = [
     ("mppi_get_costs", _i32, [_vp, _fp, _sz]),
     ("mppi_get_weights", _i32, [_vp, _dp, _sz]),
     ("mppi_get_noise", _i32, [_vp, _fp, _sz]),
+    ("mppi_get_trajectory", _i32, [_vp, _dp, _sz, _dp, _sz]),
     ("mppi_get_iter_stats", _i32, [_vp, ctypes.POINTER(IterStats)]),
     ("mppi_set_lanes_per_sample", _i32, [_vp, _i32]),
     ("mppi_set_culling", _i32, [_vp, _i32]),
@@ -197,6 +199,7 @@ def config_from_params(p, max_waypoints=2048, max_circles=1024) -> Config:
     c.seed = int(p["seed"])
     c.max_waypoints = int(max_waypoints)
     c.max_circles = int(max_circles)
+    c.smoothing = int(p.get("smoothing", 0))
     return c
 
 
@@ -362,6 +365,15 @@ class Planner:
         out = np.zeros(self.K)
         check(load().mppi_get_weights(self.h, out.ctypes.data_as(_dp), out.size))
         return out
+
+    def trajectory(self):
+        """Optimal trajectory after the last step: (states [T+1][4], applied
+        controls [T][2])."""
+        xs = np.zeros((self.T + 1, 4))
+        us = np.zeros((self.T, 2))
+        check(load().mppi_get_trajectory(self.h, xs.ctypes.data_as(_dp), xs.size,
+                                         us.ctypes.data_as(_dp), us.size))
+        return xs, us
 
     def noise(self):
         out = np.zeros((self.T, self.K, 2), dtype=np.float32)

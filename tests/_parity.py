@@ -63,6 +63,8 @@ def staged(p, scene, g, n_iter, ks=None):
     w_ref, smin, logz = O.weights(g["S"], p["lam"])
     rep["G2_max_abs"] = float(np.max(np.abs(g["w"] - w_ref)))
     U_ref = O.update(g["U_prev"], g["w"], g["eps"])
+    if p.get("smoothing", 0):
+        U_ref = O.sg_smooth(U_ref)  # the last steps of Alg. 1, eq. (sg)
     rep["G3_max_over_tol"] = float(np.max(np.abs(g["U"] - U_ref) / u_tol(U_ref, sig)))
     rep["s_min"] = (g["stats"]["s_min"], smin)
     rep["log_z"] = (g["stats"]["log_z"], logz)

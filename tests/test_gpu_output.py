@@ -1,0 +1,159 @@
+"""The last steps of Alg. 1 on MI355X: Savitzky-Golay smoothing of the
+updated controls (eq. (sg)) and the optimal trajectory {x*, u*}.
+
+Smoothing is checked by the staged gates (G3 against the oracle update
+followed by the oracle's filter), end to end, and for bit-identity between
+alone, batched and served runs of a vehicle's request sequence (the warm
+start then shifts the smoothed sequence).  The trajectory is checked against
+the oracle's float64 optimal rollout fed the GPU's controls."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2308_01654_amd import scenes
+from tests import _parity as P
+
+pytestmark = pytest.mark.gpu
+
+# float64 on both sides; the device and host math libraries differ in the
+# last bits of cos/sin/tan, accumulated over at most a few hundred steps
+TRAJ_ABS = 1e-9
+
+
+def _mppi():
+    from paper_2308_01654_amd import mppi
+    mppi.load()
+    return mppi
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _smoothed(sc):
+    p = dict(sc["params"])
+    p["smoothing"] = 1
+    return p
+
+
+@pytest.mark.parametrize("name,lanes", [("c0", 16), ("c0", 4), ("c0", 1), ("c1", 8)])
+def test_smoothing_staged_parity(name, lanes):
+    mppi = _mppi()
+    sc = scenes.by_name(name)
+    p = _smoothed(sc)
+    _say("smoothing staged", name, lanes)
+    with mppi.Planner(p, lanes=lanes) as pl:
+        pl.set_controls(np.tile([0.3, 0.02], (p["T"], 1)))
+        for it in range(2):
+            g = P.gpu_step(pl, sc)
+            rep = P.staged(p, sc, g, n_iter=it)
+            P.assert_staged(rep)
+
+
+def test_smoothing_end_to_end_and_ragged_horizons():
+    """Independent oracle iteration with smoothing; short horizons exercise
+    the repeated end values (T < 5)."""
+    mppi = _mppi()
+    for K, T in ((1024, 50), (300, 4), (77, 1), (500, 2)):
+        sc = scenes.tiny(K=K, T=T, n_c=5, seed=K + T)
+        p = _smoothed(sc)
+        _say("smoothing e2e", K, T)
+        with mppi.Planner(p) as pl:
+            g = P.gpu_step(pl, sc)
+            rep = P.staged(p, sc, g, n_iter=0)
+            P.assert_staged(rep)
+            rep, ok = P.end_to_end(p, sc, g, 0)
+            if not ok:
+                assert rep["w_max_abs"] <= max(P.W_TOL, 1.5 * rep["predicted_w_bound"]) or \
+                    rep["top2_gap"] <= 2 * rep["beta"], rep
+
+
+@pytest.mark.parametrize("smoothing", [0, 1])
+def test_trajectory_matches_oracle_rollout(smoothing):
+    """x*_{t+1} = F(x*_t, u*_t) from the last step's x0 under the handle's
+    controls, each through the noise check: equal to the oracle's float64
+    optimal rollout within TRAJ_ABS; the applied controls within bounds."""
+    mppi = _mppi()
+    sc = scenes.c1()
+    p = dict(sc["params"])
+    p["smoothing"] = smoothing
+    with mppi.Planner(p) as pl:
+        for it in range(3):
+            pl.step(sc["x0"], sc["waypoints"], sc["circles"])
+            xs, us = pl.trajectory()
+            U = pl.controls()
+            ref_x, ref_u = O.optimal_trajectory(p, sc["x0"], U)
+            _say("trajectory", smoothing, it, float(np.max(np.abs(xs - ref_x))))
+            assert np.max(np.abs(us - ref_u)) <= 1e-12
+            assert np.max(np.abs(xs - ref_x)) <= TRAJ_ABS
+            assert np.all(us >= np.array(p["u_min"]) - 1e-15)
+            assert np.all(us <= np.array(p["u_max"]) + 1e-15)
+            assert np.all(xs[:, 3] <= p["v_max"] + 1e-12)
+            assert np.array_equal(xs[0], np.asarray(sc["x0"], dtype=np.float64))
+
+
+def test_trajectory_before_any_step_is_rejected():
+    mppi = _mppi()
+    with mppi.Planner(scenes.c0()["params"]) as pl:
+        with pytest.raises(mppi.MppiError):
+            pl.trajectory()
+
+
+def test_smoothing_alone_batched_served_bitwise():
+    """A vehicle's request sequence (shift by one step between requests) with
+    smoothing gives the same bits alone, in a batch and served."""
+    mppi = _mppi()
+    rng = np.random.Generator(np.random.PCG64(21))
+    vehs = []
+    for v in range(6):
+        K = int(rng.choice([256, 1000, 2048]))
+        T = int(rng.choice([3, 20, 50]))
+        p = scenes.params(K=K, T=T, dt=0.05, v_max=15.0, seed=7000 + v, smoothing=int(v % 2 == 0))
+        reqs = []
+        x = float(rng.uniform(-5, 20))
+        for i in range(3):
+            circ = scenes.sine_circles(rng, int(rng.integers(0, 20)), x + 5, x + 80)
+            wp = scenes.sine_lane(np.floor(x) - 20, np.floor(x) + 120, 15.0)
+            reqs.append((scenes._sine_x0(x, 12.0), wp, circ))
+            x += 0.75
+        vehs.append((p, reqs))
+    ref = []
+    for p, reqs in vehs:
+        out = []
+        with mppi.Planner(p) as pl:
+            for i, (x0, wp, ci) in enumerate(reqs):
+                if i:
+                    pl.shift(1)
+                pl.step(x0, wp, ci)
+                out.append(pl.controls())
+        ref.append(out)
+    _say("batched")
+    pls = [mppi.Planner(vehs[0][0])]
+    try:
+        s0 = pls[0].stream()  # a batch runs on one stream: the first planner's
+        pls += [mppi.Planner(p, hip_stream=s0) for p, _ in vehs[1:]]
+        for i in range(3):
+            if i:
+                for pl in pls:
+                    pl.shift(1)
+            mppi.step_batch(pls, [reqs[i][0] for _, reqs in vehs],
+                            [(reqs[i][1], reqs[i][2]) for _, reqs in vehs])
+            for v, pl in enumerate(pls):
+                assert np.array_equal(pl.controls(), ref[v][i]), ("batched", v, i)
+    finally:
+        for pl in reversed(pls):  # the stream's owner last
+            pl.close()
+    _say("served")
+    with mppi.Server(n_streams=2, max_batch=16) as srv:
+        vids = [srv.add_vehicle(p) for p, _ in vehs]
+        tickets = []
+        for i in range(3):
+            for vid, (p, reqs) in zip(vids, vehs):
+                x0, wp, ci = reqs[i]
+                tickets.append((vid, i, srv.submit(vid, x0, wp, ci)))
+        for vid, i, t in tickets:
+            got = srv.wait(t, vid)[0]
+            assert np.array_equal(got, ref[vids.index(vid)][i]), ("served", vid, i)
