@@ -160,6 +160,35 @@ def sweep():
             pl.close()
 
 
+def alg1_output(p, x0, wp, circ, warmup, steps):
+    """The last steps of Alg. 1 on the same workload: iteration kernel time
+    with Savitzky-Golay smoothing in the root merge, and the latency of one
+    optimal-trajectory call (device rollout + copies, host clock)."""
+    from paper_2308_01654_amd import mppi
+    ps = dict(p)
+    ps["smoothing"] = 1
+    pl = mppi.Planner(ps)
+    pl.set_scene(x0, wp, circ)
+    for _ in range(warmup):
+        pl.step_resident(x0)
+    pl.sync()
+    pl.set_profiling(True)
+    for _ in range(steps):
+        pl.step_resident(x0)
+    pl.sync()
+    prof = pl.profile()
+    pl.set_profiling(False)
+    lat = []
+    for _ in range(50):
+        a = time.perf_counter()
+        pl.trajectory()
+        lat.append((time.perf_counter() - a) * 1e3)
+    pl.close()
+    return {"smoothing_kernel_ms": round(prof["iter_ms"] / max(prof["iter_launches"], 1), 5),
+            "trajectory_call_ms_p50": round(float(np.percentile(lat, 50)), 4),
+            "trajectory_call_ms_p99": round(float(np.percentile(lat, 99)), 4)}
+
+
 def c3_load(n_vehicles, duration_s, pool_size=512, seed=33):
     """Served load: vehicles with their own (K, T) and seeds replanning at
     20 Hz with exponential inter-arrival times (mean 50 ms) and a random
@@ -313,6 +342,7 @@ def main(argv=None):
     pl.sync()
     pcie_value = K * T * 50 / (time.perf_counter() - a)
     pl.close()
+    smooth = alg1_output(p, x0, wp, circ, args.warmup, args.steps)
 
     out = {
         "metric": METRIC,
@@ -336,6 +366,7 @@ def main(argv=None):
                        "one_at_a_time_unloaded_p999": round(float(np.percentile(lat, 99.9)), 4)},
         "wall_s_timed": round(t1 - t0, 4),
         "host_staged_value": round(pcie_value, 1),
+        "alg1_output": smooth,
     }
     if args.served_seconds > 0:
         sv = served(duration_s=args.served_seconds, plain_duration_s=args.plain_seconds)
