@@ -595,6 +595,11 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     float S = 0.0f, comp = 0.0f;  // Kahan pair of this lane's steps
     for (int t0 = 0; t0 < T; t0 += G) {
         const int tm = t0 + r;
+        // The lane's step within the block, opaque to the compiler so that the
+        // per-step "own step" tests stay in the loop as vector compares
+        // instead of G hoisted scalar masks (which exhaust the SGPRs).
+        int rb = r;
+        asm volatile("" : "+v"(rb));
         const int tc = tm < T ? tm : T - 1;
         // This lane's step: perturbation, the state-independent part of the
         // noise check (control bounds) and the steering tangent, computed
@@ -634,7 +639,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             v = fmaf(d.dt, a, v);
             c = __cosf(th);
             sn = __sinf(th);
-            if (i == r) {
+            if (i == rb) {
                 mx = x; my = y; mc = c; ms = sn; mv = v; ma = a;
             }
         }
