@@ -56,6 +56,13 @@
  *     z_d = rho sin(2 pi u2).
  *   - a non-finite S_k counts as +inf; if every S_k is non-finite the
  *     iteration fails and U is left unchanged.
+ *   - the other Sec. IV-C terms (zero weight unless configured):
+ *     c_target = 1 when the step ends farther from the target point T_P
+ *     than it started (squared distances compared), T_P being the last
+ *     waypoint of the path; c_yaw = wrap(theta - theta_r)^2 with the
+ *     difference wrapped into [-pi, pi) and theta_r the yaw of the closest
+ *     waypoint; in the collision-only mode (object avoidance) c_safe_dist
+ *     counts only when d_obj <= 0.
  *
  * The last steps of Algorithm 1 (optional, cfg.smoothing = 1):
  *   u*    = SavitzkyGolay(U)                        eq. (sg): the 5-point
@@ -88,6 +95,9 @@ typedef struct orc_cfg {
     double ego_off[4];
     uint64_t seed;
     int32_t smoothing;  /* 1: Savitzky-Golay smoothing ends the iteration */
+    double w_target;    /* weight of c_target (Sec. IV-C) */
+    double w_yaw;       /* weight of c_yaw (Sec. IV-C) */
+    int32_t collision_only; /* 1: c_safe_dist only when an object is hit */
 } orc_cfg;
 
 enum { ORC_OK = 0, ORC_E_INVALID = -1, ORC_E_NONFINITE = -4 };
@@ -193,8 +203,9 @@ void orc_dynamics(const orc_cfg* c, const double x[4], const double u[2], double
     xn[3] = x[3] + dt * u[0];
 }
 
-/* c_dist and the reference speed of the closest waypoint (Sec. IV-C). */
-static void tracking(const double* wp, int n_wp, const double P[2], double* c_dist, double* v_ref)
+/* c_dist and the reference yaw and speed of the closest waypoint (Sec. IV-C). */
+static void tracking(const double* wp, int n_wp, const double P[2], double* c_dist,
+                     double* yaw_ref, double* v_ref)
 {
     double best = INFINITY;
     int bj = 0;
@@ -205,7 +216,15 @@ static void tracking(const double* wp, int n_wp, const double P[2], double* c_di
         if (d < best) { best = d; bj = j; }
     }
     *c_dist = best;
+    *yaw_ref = wp[4 * bj + 2];
     *v_ref = wp[4 * bj + 3];
+}
+
+/* An angle difference brought into [-pi, pi). */
+static double wrap_angle(double d)
+{
+    const double pi = 3.14159265358979323846;
+    return d - 2.0 * pi * floor((d + pi) / (2.0 * pi));
 }
 
 /* d_obj of Sec. IV-C over ego circles and (moving) obstacle circles. */
@@ -229,15 +248,23 @@ static double object_distance(const orc_cfg* c, const double* circ, int n_c,
 }
 
 /* Stage cost of Sec. III (input part) and Sec. IV-C (state part) evaluated on
- * the new state x' reached with nominal U_t and applied perturbation e. */
+ * the new state x' reached from x (previous state) with nominal U_t and
+ * applied perturbation e.  parts: c_dist, c_speed, q_u, c_safe, c_target,
+ * c_yaw. */
 double orc_stage_cost(const orc_cfg* c, const double* wp, int n_wp, const double* circ, int n_c,
                       const double xn[4], const double U[2], const double e[2], int t,
-                      double parts[4])
+                      const double xp[4], double parts[6])
 {
     double P[2] = { xn[0], xn[1] };
-    double c_dist, v_ref;
-    tracking(wp, n_wp, P, &c_dist, &v_ref);
+    double c_dist, yaw_ref, v_ref;
+    tracking(wp, n_wp, P, &c_dist, &yaw_ref, &v_ref);
     double c_speed = (xn[3] - v_ref) * (xn[3] - v_ref);
+    const double tpx = wp[4 * (n_wp - 1) + 0], tpy = wp[4 * (n_wp - 1) + 1];
+    double dn = (xn[0] - tpx) * (xn[0] - tpx) + (xn[1] - tpy) * (xn[1] - tpy);
+    double dp = (xp[0] - tpx) * (xp[0] - tpx) + (xp[1] - tpy) * (xp[1] - tpy);
+    double c_target = dn > dp ? 1.0 : 0.0;
+    double dyaw = wrap_angle(xn[2] - yaw_ref);
+    double c_yaw = dyaw * dyaw;
     double alpha = (c->gamma - 1.0) / (2.0 * c->gamma);
     double q_u = c->w_effort * (alpha * (e[0] * e[0] + e[1] * e[1])
                                 + (U[0] * e[0] + U[1] * e[1])
@@ -247,8 +274,13 @@ double orc_stage_cost(const orc_cfg* c, const double* wp, int n_wp, const double
     double d_safe = c->d_safe_c * xn[3] + c->d_safe_0;
     double g = d_safe - d_obj;
     double c_safe = g > 0.0 ? g * g : 0.0;
-    if (parts) { parts[0] = c_dist; parts[1] = c_speed; parts[2] = q_u; parts[3] = c_safe; }
-    return c->w_track * c_dist + c->w_speed * c_speed + q_u + c->w_coll * c_safe;
+    if (c->collision_only && !(d_obj <= 0.0)) c_safe = 0.0;
+    if (parts) {
+        parts[0] = c_dist; parts[1] = c_speed; parts[2] = q_u; parts[3] = c_safe;
+        parts[4] = c_target; parts[5] = c_yaw;
+    }
+    return c->w_track * c_dist + c->w_target * c_target + c->w_yaw * c_yaw +
+           c->w_speed * c_speed + q_u + c->w_coll * c_safe;
 }
 
 static int cfg_ok(const orc_cfg* c, int n_wp, int n_c)
@@ -298,7 +330,7 @@ int orc_rollout(const orc_cfg* c, const double x0[4], const double* wp, int n_wp
             }
             double xn[4];
             orc_dynamics(c, x, u, xn);
-            S += orc_stage_cost(c, wp, n_wp, circ, n_c, xn, Ut, e, t, NULL);
+            S += orc_stage_cost(c, wp, n_wp, circ, n_c, xn, Ut, e, t, x, NULL);
             memcpy(x, xn, sizeof x);
         }
         S_out[k] = S;
@@ -344,7 +376,7 @@ int orc_rollout_samples(const orc_cfg* c, const double x0[4], const double* wp, 
             }
             double xn[4];
             orc_dynamics(c, x, u, xn);
-            S += orc_stage_cost(c, wp, n_wp, circ, n_c, xn, Ut, e, t, NULL);
+            S += orc_stage_cost(c, wp, n_wp, circ, n_c, xn, Ut, e, t, x, NULL);
             memcpy(x, xn, sizeof x);
         }
         S_out[i] = S;
@@ -353,7 +385,8 @@ int orc_rollout_samples(const orc_cfg* c, const double x0[4], const double* wp, 
 }
 
 /* Deterministic rollout of one control sequence (no noise); states [T+1][4],
- * stage costs [T] and their parts [T][4] (c_dist, c_speed, q_u, c_safe). */
+ * stage costs [T] and their parts [T][6] (c_dist, c_speed, q_u, c_safe,
+ * c_target, c_yaw). */
 int orc_simulate(const orc_cfg* c, const double x0[4], const double* wp, int n_wp,
                  const double* circ, int n_c, const double* U, const double* eps,
                  double* states, double* costs, double* parts)
@@ -366,8 +399,8 @@ int orc_simulate(const orc_cfg* c, const double x0[4], const double* wp, int n_w
         double u[2] = { U[2 * t] + e[0], U[2 * t + 1] + e[1] };
         double xn[4];
         orc_dynamics(c, x, u, xn);
-        costs[t] = orc_stage_cost(c, wp, n_wp, circ, n_c, xn, U + 2 * t, e, t,
-                                  parts ? parts + 4 * t : NULL);
+        costs[t] = orc_stage_cost(c, wp, n_wp, circ, n_c, xn, U + 2 * t, e, t, x,
+                                  parts ? parts + 6 * t : NULL);
         memcpy(states + 4 * (t + 1), xn, sizeof xn);
         memcpy(x, xn, sizeof x);
     }

@@ -44,6 +44,8 @@ class OrcCfg(ctypes.Structure):
         ("ego_off", ctypes.c_double * 4),
         ("seed", ctypes.c_uint64),
         ("smoothing", ctypes.c_int32),
+        ("w_target", ctypes.c_double), ("w_yaw", ctypes.c_double),
+        ("collision_only", ctypes.c_int32),
     ]
 
 
@@ -76,7 +78,7 @@ def lib():
             L.orc_apply_limits.argtypes = [cp, dp, dp, ctypes.c_double, dp]
             L.orc_dynamics.argtypes = [cp, dp, dp, dp]
             L.orc_stage_cost.argtypes = [cp, dp, ctypes.c_int, dp, ctypes.c_int, dp, dp, dp,
-                                         ctypes.c_int, dp]
+                                         ctypes.c_int, dp, dp]
             L.orc_stage_cost.restype = ctypes.c_double
             L.orc_rollout.argtypes = [cp, dp, dp, ctypes.c_int, dp, ctypes.c_int, dp,
                                       ctypes.c_uint64, dp, dp, dp]
@@ -127,6 +129,9 @@ def make_cfg(p) -> OrcCfg:
         c.ego_off[i] = float(o)
     c.seed = int(p["seed"])
     c.smoothing = int(p.get("smoothing", 0))
+    c.w_target = float(p.get("w_target", 0.0))
+    c.w_yaw = float(p.get("w_yaw", 0.0))
+    c.collision_only = int(p.get("collision_only", 0))
     return c
 
 
@@ -187,21 +192,24 @@ def dynamics(p, x, u):
     return out
 
 
-def stage_cost(p, waypoints, circles, x_new, U_t, eps, t):
-    """Stage cost on the new state; returns (cost, (c_dist, c_speed, q_u, c_safe))."""
+def stage_cost(p, waypoints, circles, x_new, U_t, eps, t, x_prev=None):
+    """Stage cost on the new state reached from x_prev (default: x_new, so
+    c_target = 0); returns (cost, (c_dist, c_speed, q_u, c_safe, c_target,
+    c_yaw))."""
     c = make_cfg(p)
     wp = _f64(waypoints, (-1, 4))
     ci = _f64(circles, (-1, 5)) if len(circles) else np.zeros((0, 5))
     xn, U_t, eps = _f64(x_new), _f64(U_t), _f64(eps)
-    parts = np.zeros(4)
+    xp = xn if x_prev is None else _f64(x_prev)
+    parts = np.zeros(6)
     v = lib().orc_stage_cost(ctypes.byref(c), _dp(wp), wp.shape[0], _dp(ci), ci.shape[0],
-                             _dp(xn), _dp(U_t), _dp(eps), int(t), _dp(parts))
+                             _dp(xn), _dp(U_t), _dp(eps), int(t), _dp(xp), _dp(parts))
     return v, parts
 
 
 def simulate(p, x0, waypoints, circles, U, eps=None):
     """Deterministic rollout of one control sequence U (+ optional eps).
-    Returns (states [T+1][4], stage costs [T], parts [T][4])."""
+    Returns (states [T+1][4], stage costs [T], parts [T][6])."""
     c = make_cfg(p)
     T = c.T
     wp = _f64(waypoints, (-1, 4))
@@ -211,7 +219,7 @@ def simulate(p, x0, waypoints, circles, U, eps=None):
     x0 = _f64(x0)
     states = np.zeros((T + 1, 4))
     costs = np.zeros(T)
-    parts = np.zeros((T, 4))
+    parts = np.zeros((T, 6))
     rc = lib().orc_simulate(ctypes.byref(c), _dp(x0), _dp(wp), wp.shape[0], _dp(ci),
                             ci.shape[0], _dp(U), _dp(e), _dp(states), _dp(costs), _dp(parts))
     if rc != OK:

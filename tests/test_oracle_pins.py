@@ -605,3 +605,65 @@ def test_optimal_trajectory_respects_bounds_and_speed_cap():
     Us = np.tile([-9.0, -2.0], (30, 1))     # below u_min
     _, ap = O.optimal_trajectory(p, np.array([0.0, 0.0, 0.0, 9.5]), Us)
     assert np.all(ap == np.array(p["u_min"]))
+
+
+# ---- the paper's full Sec. IV-C cost: c_target, c_yaw, collision-only mode
+
+def test_target_cost_counts_steps_away_from_the_last_waypoint():
+    """c_target = 1 exactly when the new position is farther from the target
+    point (the last waypoint, here (100, 0)) than the previous one; a step
+    along a circle around the target costs nothing."""
+    p = _p(w_track=0, w_speed=0, w_effort=0, w_coll=0, w_target=7.0)
+    wp = scenes.straight_lane(0, 100, 0.0)
+    none = np.zeros((0, 5))
+    cases = [((50, 0), (51, 0), 0.0), ((50, 0), (49, 0), 1.0), ((70, 0), (100, 30), 0.0),
+             ((70, 0), (100, 30.001), 1.0), ((120, 5), (119, 5), 0.0), ((120, 5), (121, 5), 1.0)]
+    for (px, py), (nx, ny), expect in cases:
+        c, parts = O.stage_cost(p, wp, none, [nx, ny, 0, 0], [0, 0], [0, 0], 0,
+                                x_prev=[px, py, 0, 0])
+        assert parts[4] == expect and c == 7.0 * expect
+
+
+def test_yaw_cost_wraps_the_heading_difference():
+    """c_yaw = wrap(theta - theta_r)^2 with the difference in [-pi, pi) and
+    theta_r the yaw of the closest waypoint: headings pi - 0.1 and
+    -pi + 0.1 differ by 0.2, not 2 pi - 0.2; whole turns of the unwrapped
+    state change nothing."""
+    p = _p(w_track=0, w_speed=0, w_effort=0, w_coll=0, w_yaw=120.0)
+    none = np.zeros((0, 5))
+    wp = np.array([[0.0, 0.0, -math.pi + 0.1, 0.0], [10.0, 0.0, 0.1, 0.0]])
+    for th, ref_x, expect in [(math.pi - 0.1, 1.0, 0.04), (0.3, 9.0, 0.04),
+                              (0.3 + 4 * math.pi, 9.0, 0.04), (-0.3 - 6 * math.pi, 9.0, 0.16),
+                              (0.1, 9.0, 0.0)]:
+        c, parts = O.stage_cost(p, wp, none, [ref_x, 0.5, th, 0], [0, 0], [0, 0], 0)
+        assert math.isclose(parts[5], expect, rel_tol=1e-9, abs_tol=1e-12), (th, parts[5])
+        assert math.isclose(c, 120.0 * expect, rel_tol=1e-9, abs_tol=1e-10)
+
+
+def test_collision_only_mode_counts_only_overlaps():
+    """Object avoidance: with the margin d_safe = 0.5 an obstacle at d_obj =
+    0.3 costs (0.5 - 0.3)^2 normally and nothing in the collision-only mode;
+    an overlap d_obj = -0.2 costs (0.5 + 0.2)^2 in both."""
+    base = dict(ego_off=(0.0,), ego_r=1.0, d_safe_c=0.0, d_safe_0=0.5, w_track=0, w_speed=0,
+                w_effort=0, w_coll=25.0)
+    wp = scenes.straight_lane(-3, 3, 0.0)
+    x = [0.0, 0.0, 0.0, 5.0]
+    for d_obj, normal in [(0.3, 0.2 ** 2), (-0.2, 0.7 ** 2), (0.0, 0.5 ** 2), (0.6, 0.0)]:
+        circ = [[2.0 + d_obj, 0.0, 1.0, 0, 0]]   # centre 2 + d_obj, radii 1 + 1
+        _, pn = O.stage_cost(_p(**base), wp, circ, x, [0, 0], [0, 0], 0)
+        _, pc = O.stage_cost(_p(collision_only=1, **base), wp, circ, x, [0, 0], [0, 0], 0)
+        assert math.isclose(pn[3], normal, rel_tol=1e-9, abs_tol=1e-15)
+        assert math.isclose(pc[3], normal if d_obj <= 0 else 0.0, rel_tol=1e-9, abs_tol=1e-15)
+
+
+def test_paper_weights_worked_total():
+    """The Sec. IV-C total 15 c_dist + 7 c_target + 120 c_yaw + 5 c_speed +
+    25 c_safe_dist on a hand-made state: 1 m off an integer lane (c_dist =
+    1), stepping away from the target (1), heading 0.1 rad off (0.01),
+    2 m/s above the reference speed (4), no obstacle: 15 + 7 + 1.2 + 20."""
+    p = _p(w_track=15.0, w_target=7.0, w_yaw=120.0, w_speed=5.0, w_coll=25.0, w_effort=0.0)
+    wp = scenes.straight_lane(0, 50, 10.0)
+    c, parts = O.stage_cost(p, wp, np.zeros((0, 5)), [20.0, 1.0, 0.1, 12.0], [0, 0], [0, 0], 0,
+                            x_prev=[20.5, 1.0, 0.1, 12.0])
+    assert np.allclose(parts, [1.0, 4.0, 0.0, 0.0, 1.0, 0.01], rtol=1e-12, atol=1e-15)
+    assert math.isclose(c, 43.2, rel_tol=1e-12)
