@@ -89,6 +89,12 @@ typedef struct mppi_config {
                               eq. (sg) (window (-3,12,17,12,-3)/35, end values repeated
                               beyond the horizon), which replaces U -- the last steps of
                               Alg. 1, so a warm-start shift then shifts u*; 0: off      */
+    double w_target;       /* weight of c_target (Sec. IV-C): 1 when a step ends farther
+                              from the target point (the last waypoint) than it began   */
+    double w_yaw;          /* weight of c_yaw (Sec. IV-C): heading minus the closest
+                              waypoint's yaw, wrapped into [-pi, pi), squared            */
+    int32_t collision_only;/* 1: c_safe_dist only when an object is hit, d_obj <= 0
+                              (the paper's object-avoidance mode); 0: always            */
 } mppi_config;
 
 /* Scene and road model of one request, world coordinates. */

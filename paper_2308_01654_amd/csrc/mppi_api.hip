@@ -101,6 +101,10 @@ mppi_status validate_config(const mppi_config* c)
                     kMaxCircles);
     if (c->smoothing != 0 && c->smoothing != 1)
         return fail(MPPI_E_INVALID, "smoothing must be 0 or 1");
+    if (!isfinite(c->w_target) || !isfinite(c->w_yaw))
+        return fail(MPPI_E_INVALID, "w_target and w_yaw must be finite");
+    if (c->collision_only != 0 && c->collision_only != 1)
+        return fail(MPPI_E_INVALID, "collision_only must be 0 or 1");
     return MPPI_OK;
 }
 
@@ -121,7 +125,8 @@ SceneLayout scene_layout(int n_wp, int n_c)
     L.o_xy = L.o_pv + align_up((size_t)n_c * 16, 16);
     // waypoints padded to whole chunks (points at infinity)
     L.o_vr = L.o_xy + align_up((size_t)(n_wp + kChunk - 1) / kChunk * kChunk * 8, 16);
-    L.o_rr = L.o_vr + align_up((size_t)n_wp * 4, 16);
+    L.o_yw = L.o_vr + align_up((size_t)n_wp * 4, 16);
+    L.o_rr = L.o_yw + align_up((size_t)n_wp * 4, 16);
     L.bytes = L.o_rr + align_up((size_t)n_c * 4, 16);
     return L;
 }
@@ -133,11 +138,13 @@ void write_scene(unsigned char* dst, const SceneLayout& L, const mppi_config& c,
     float4* pv = reinterpret_cast<float4*>(dst + L.o_pv);
     float2* xy = reinterpret_cast<float2*>(dst + L.o_xy);
     float* vr = reinterpret_cast<float*>(dst + L.o_vr);
+    float* yw = reinterpret_cast<float*>(dst + L.o_yw);
     float* rr = reinterpret_cast<float*>(dst + L.o_rr);
     for (int i = 0; i < sc->n_waypoints; ++i) {
         const double* w = sc->waypoints + 4 * i;
         xy[i] = make_float2((float)(w[0] - origin[0]), (float)(w[1] - origin[1]));
         vr[i] = (float)w[3];
+        yw[i] = (float)w[2];
     }
     for (int i = sc->n_waypoints; i % kChunk; ++i) xy[i] = make_float2(INFINITY, INFINITY);
     for (int i = 0; i < sc->n_circles; ++i) {
@@ -408,12 +415,16 @@ void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double or
     d.shift = shift;
     d.cull = h->no_cull ? 0 : 1;
     d.smooth = c.smoothing;
+    d.w_target = (float)c.w_target;
+    d.w_yaw = (float)c.w_yaw;
+    d.coll_only = c.collision_only;
     d.ego_ext = 0.f;
     for (int e = 0; e < c.n_ego; ++e) d.ego_ext = fmaxf(d.ego_ext, (float)fabs(c.ego_off[e]));
     d.out_slot = -1;
     d.c_pv = reinterpret_cast<const float4*>(scene + L.o_pv);
     d.wp_xy = reinterpret_cast<const float2*>(scene + L.o_xy);
     d.wp_vref = reinterpret_cast<const float*>(scene + L.o_vr);
+    d.wp_yaw = reinterpret_cast<const float*>(scene + L.o_yw);
     d.c_rr = reinterpret_cast<const float*>(scene + L.o_rr);
     d.U = h->U;
     d.S = h->S;

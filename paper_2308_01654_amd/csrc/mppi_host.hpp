@@ -44,7 +44,7 @@ struct ProfEvent {
 
 // Offsets of the four scene arrays inside a staged scene block.
 struct SceneLayout {
-    size_t o_pv, o_xy, o_vr, o_rr, bytes;
+    size_t o_pv, o_xy, o_vr, o_yw, o_rr, bytes;
 };
 
 // Per-instance extras of a batched launch: scratch buffers that replace the
@@ -90,7 +90,7 @@ struct mppi {
     bool has_scene = false;
     double origin[2] = {0.0, 0.0};
     int n_wp = 0, n_c = 0;
-    mppi_impl::SceneLayout lay = {0, 0, 0, 0, 0};
+    mppi_impl::SceneLayout lay = {0, 0, 0, 0, 0, 0};
     // last step
     bool stepped = false;
     double last_x0[4] = {0.0, 0.0, 0.0, 0.0};

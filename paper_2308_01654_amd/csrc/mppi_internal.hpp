@@ -70,11 +70,14 @@ struct InstDesc {
     int shift;            // shift U by one step before the iteration (warm start)
     int cull;             // wave-level culling of waypoint chunks and circles
     int smooth;           // end with the Savitzky-Golay filter of eq. (sg)
+    float w_target, w_yaw;// weights of c_target and c_yaw (0: term skipped)
+    int coll_only;        // c_safe_dist only when d_obj <= 0
     float ego_ext;        // max |ego_off|
     int out_slot;         // slot in the gathered results of a batch (-1: none)
     // device pointers
     const float2* wp_xy;  // [n_wp]
     const float* wp_vref; // [n_wp]
+    const float* wp_yaw;  // [n_wp]
     const float4* c_pv;   // [n_c] (x, y, vx, vy)
     const float* c_rr;    // [n_c] r_c + r_ego
     double* U;            // [T][2]
@@ -102,7 +105,7 @@ struct BatchHdr {
 
 // Dynamic LDS layout of the iteration kernel for a given scene size.
 struct LdsLayout {
-    size_t c_pv, wp_box, wp_xy, U, red, wp_vref, c_rr, omega, total;
+    size_t c_pv, wp_box, wp_xy, U, red, wp_vref, wp_yaw, c_rr, omega, blk, total;
 };
 
 // Waypoints are grouped in chunks of this many consecutive points; each chunk
@@ -121,8 +124,11 @@ inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int sp
     L.U = o;       o += (size_t)T * 8;
     L.red = o;     o += 64 * 8;           // block reduction scratch (doubles)
     L.wp_vref = o; o += (size_t)n_wp * 4;
+    L.wp_yaw = o;  o += (size_t)n_wp * 4;
     L.c_rr = o;    o += (size_t)n_c * 4;
     L.omega = o;   o += (size_t)spb * 4;
+    o = align_up(o, 8);
+    L.blk = o;     o += (size_t)spb * 8;   // block-start position per sample
     L.total = align_up(o, 16);
     return L;
 }

@@ -83,8 +83,10 @@ struct Lds {
     float2* U;
     double* red;
     float* wp_vref;
+    float* wp_yaw;
     float* c_rr;
     float* omega;
+    float2* blk;
 };
 
 __device__ __forceinline__ Lds lds_bind(unsigned char* base, const LdsLayout& L)
@@ -96,8 +98,10 @@ __device__ __forceinline__ Lds lds_bind(unsigned char* base, const LdsLayout& L)
     s.U = reinterpret_cast<float2*>(base + L.U);
     s.red = reinterpret_cast<double*>(base + L.red);
     s.wp_vref = reinterpret_cast<float*>(base + L.wp_vref);
+    s.wp_yaw = reinterpret_cast<float*>(base + L.wp_yaw);
     s.c_rr = reinterpret_cast<float*>(base + L.c_rr);
     s.omega = reinterpret_cast<float*>(base + L.omega);
+    s.blk = reinterpret_cast<float2*>(base + L.blk);
     return s;
 }
 
@@ -144,18 +148,53 @@ __device__ __forceinline__ float circle_gap(const float (&ex)[NE > 0 ? NE : 1],
     return __builtin_amdgcn_sqrtf(m2) - rr;
 }
 
+// The Sec. IV-C terms beyond tracking, speed and obstacles, each skipped at
+// zero weight: c_target = 1 when the step from (xp, yp) to (x, y) ends
+// farther from the target point (the last waypoint) -- the sign of
+// |P - T|^2 - |P_prev - T|^2 = (P - P_prev).(P + P_prev - 2 T) -- and c_yaw,
+// the heading th minus the yaw of closest waypoint bj, wrapped into
+// [-pi, pi), squared.
+__device__ __forceinline__ float extra_terms(const InstDesc& d, const Lds& s, int bj, float x,
+                                             float y, float th, float xp, float yp)
+{
+    float e = 0.0f;
+    if (d.w_target != 0.0f) {
+        const float2 tp = s.wp_xy[d.n_wp - 1];
+        const float dx = x - xp, dy = y - yp;
+        const float sx = (x - tp.x) + (xp - tp.x), sy = (y - tp.y) + (yp - tp.y);
+        e = fmaf(d.w_target, fmaf(dx, sx, dy * sy) > 0.0f ? 1.0f : 0.0f, e);
+    }
+    if (d.w_yaw != 0.0f) {
+        float dyaw = th - s.wp_yaw[bj];
+        dyaw -= 6.28318530717958647692f *
+                floorf((dyaw + 3.14159265358979323846f) * 0.15915494309189533577f);
+        e = fmaf(d.w_yaw, dyaw * dyaw, e);
+    }
+    return e;
+}
+
+// Obstacle cost from the clearance d_obj and the safety distance ds; in the
+// collision-only mode it counts only when an object is hit (d_obj <= 0).
+__device__ __forceinline__ float safe_cost(const InstDesc& d, float ds, float d_obj)
+{
+    const float g = ds - d_obj;
+    return (g > 0.0f && (!d.coll_only || d_obj <= 0.0f)) ? g * g : 0.0f;
+}
+
 // Stage cost on the state reached at step t (Sec. III input cost, Sec. IV-C
 // tracking, speed and obstacle costs).  Every lane of the wave runs the same
 // waypoint and circle loops, so the LDS reads are broadcasts.
 template <int NE>
 __device__ __forceinline__ float stage_cost(const InstDesc& d, const Lds& s, float x, float y,
                                             float c, float sn, float v, float Ua, float Ud,
-                                            float ea, float ed, int t)
+                                            float ea, float ed, int t, float th, float xp,
+                                            float yp)
 {
     // c_dist = min_j ||P - W_j||^2; reference speed of the closest waypoint
     float best = INFINITY;
     int bj = 0;
     for (int ch = 0; ch * kChunk < d.n_wp; ++ch) scan_chunk(s, ch, x, y, best, bj);
+    const float ext = extra_terms(d, s, bj, x, y, th, xp, yp);
     const float dv = v - s.wp_vref[bj];
     // q_u = w_effort (alpha eps.eps + U.eps + U.U / 2)
     const float q = d.w_effort * (d.alpha * fmaf(ea, ea, ed * ed) + fmaf(Ua, ea, Ud * ed) +
@@ -175,11 +214,9 @@ __device__ __forceinline__ float stage_cost(const InstDesc& d, const Lds& s, flo
             const float rr = s.c_rr[i];
             d_obj = fminf(d_obj, circle_gap<NE>(ex, ey, p, rr, tau));
         }
-        const float g = fmaf(d.d_safe_c, v, d.d_safe_0) - d_obj;
-        const float c_safe = g > 0.0f ? g * g : 0.0f;
-        cost = fmaf(d.w_coll, c_safe, cost);
+        cost = fmaf(d.w_coll, safe_cost(d, fmaf(d.d_safe_c, v, d.d_safe_0), d_obj), cost);
     }
-    return cost;
+    return cost + ext;
 }
 
 // ----------------------------------------------------------------------------
@@ -383,7 +420,8 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
                                                    const LaneCull& lc, bool vref_uniform, bool act,
                                                    float x, float y,
                                                    float c, float sn, float v, float Ua, float Ud,
-                                                   float ea, float ed, int t, int t_lo, int t_hi)
+                                                   float ea, float ed, int t, int t_lo, int t_hi,
+                                                   float th, float xp, float yp)
 {
     const int lane = threadIdx.x & 63;
     const float ds = fmaf(d.d_safe_c, v, d.d_safe_0);
@@ -421,8 +459,12 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
             scan_chunks(wp4, base, __ballot(near2(b) <= thr), x, y, best, bch);
         }
     }
-    // the reference speed of the closest waypoint (any one when all are equal)
-    const float vref = vref_uniform ? s.wp_vref[0] : s.wp_vref[chunk_argmin(s, bch, best, x, y)];
+    // the closest index, needed for its reference speed (unless every
+    // waypoint has the same one) and for its yaw
+    const bool need_idx = !vref_uniform || d.w_yaw != 0.0f;
+    const int bj = need_idx ? chunk_argmin(s, bch, best, x, y) : 0;
+    const float vref = s.wp_vref[vref_uniform ? 0 : bj];
+    const float ext = extra_terms(d, s, bj, x, y, th, xp, yp);
     const float dv = v - vref;
     const float q = d.w_effort * (d.alpha * fmaf(ea, ea, ed * ed) + fmaf(Ua, ea, Ud * ed) +
                                   0.5f * fmaf(Ua, Ua, Ud * Ud));
@@ -446,7 +488,8 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
             const float ya = fmaf(tau_lo, p.w, p.y), yb = fmaf(tau_hi, p.w, p.y);
             const float gx = fmaxf(fmaxf(fminf(xa, xb) - exhi, exlo - fmaxf(xa, xb)), 0.0f);
             const float gy = fmaxf(fmaxf(fminf(ya, yb) - eyhi, eylo - fmaxf(ya, yb)), 0.0f);
-            const float lim = wb.dsmax + rr + 0.01f;
+            // collision-only: only circles that can reach an ego circle matter
+            const float lim = (d.coll_only ? 0.0f : wb.dsmax) + rr + 0.01f;
             return lim > 0.0f && fmaf(gy, gy, gx * gx) < lim * lim;
         };
         const const_ptr<float> cpv = as_const(d.c_pv);
@@ -482,11 +525,9 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
                     if (u < cnt) d_obj = fminf(d_obj, circle_gap<NE>(ex, ey, p[u], rr[u], tau));
             }
         }
-        const float g = ds - d_obj;
-        const float c_safe = g > 0.0f ? g * g : 0.0f;
-        cost = fmaf(d.w_coll, c_safe, cost);
+        cost = fmaf(d.w_coll, safe_cost(d, ds, d_obj), cost);
     }
-    return cost;
+    return cost + ext;
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -554,6 +595,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         if (i < d.n_wp) {
             const float vr = d.wp_vref[i];
             s.wp_vref[i] = vr;
+            s.wp_yaw[i] = d.wp_yaw[i];
             same_vref = same_vref && vr == vref0;
         }
     }
@@ -609,7 +651,9 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         const float a0m = fminf(fmaxf(Um.x + em.x, d.a_min), d.a_max);
         const float dlm = fminf(fmaxf(Um.y + em.y, d.d_min), d.d_max);
         const float tnm = __tanf(dlm);
-        float mx = 0.f, my = 0.f, mc = 1.f, ms = 0.f, mv = 0.f, ma = 0.f;
+        // position at the start of the block, for c_target of its first step
+        if (d.w_target != 0.0f && r == 0) s.blk[grp] = make_float2(x, y);
+        float mx = 0.f, my = 0.f, mc = 1.f, ms = 0.f, mv = 0.f, ma = 0.f, mth = 0.f;
         constexpr int PF = G < 4 ? G : 4;  // steps whose inputs are exchanged together
         float apf[PF], tpf[PF];
 #pragma unroll
@@ -640,18 +684,34 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             c = __cosf(th);
             sn = __sinf(th);
             if (i == rb) {
-                mx = x; my = y; mc = c; ms = sn; mv = v; ma = a;
+                mx = x; my = y; mc = c; ms = sn; mv = v; ma = a; mth = th;
             }
         }
         const float mUa = Um.x, mUd = Um.y;
         const float mea = ma - Um.x, med = dlm - Um.y;
         const bool act = tm < T;
+        // position before this lane's step (for c_target): the block start for
+        // the first step of the block, else the state the previous lane kept
+        float pxp = 0.0f, pyp = 0.0f;
+        if (d.w_target != 0.0f) {
+            const float2 b0 = s.blk[grp];  // written by this wave's lane r = 0
+            pxp = b0.x;
+            pyp = b0.y;
+            if (G > 1) {
+                const int src = (tid & ~(G - 1)) + (r > 0 ? r - 1 : 0);
+                const float sx = __shfl(mx, src, 64), sy = __shfl(my, src, 64);
+                if (r > 0) {
+                    pxp = sx;
+                    pyp = sy;
+                }
+            }
+        }
         float q = 0.0f;
         if (d.cull)
             q = stage_cost_culled<NE>(d, s, lc, vref_uniform, act, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm, t0,
-                                      min(t0 + G, T) - 1);
+                                      min(t0 + G, T) - 1, mth, pxp, pyp);
         else if (act)
-            q = stage_cost<NE>(d, s, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm);
+            q = stage_cost<NE>(d, s, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm, mth, pxp, pyp);
         if (act) {
             const float yk = q - comp;
             const float tk = S + yk;

@@ -48,6 +48,8 @@ class Config(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("max_waypoints", ctypes.c_int32), ("max_circles", ctypes.c_int32),
         ("smoothing", ctypes.c_int32),
+        ("w_target", ctypes.c_double), ("w_yaw", ctypes.c_double),
+        ("collision_only", ctypes.c_int32),
     ]
 
 
@@ -200,6 +202,9 @@ def config_from_params(p, max_waypoints=2048, max_circles=1024) -> Config:
     c.max_waypoints = int(max_waypoints)
     c.max_circles = int(max_circles)
     c.smoothing = int(p.get("smoothing", 0))
+    c.w_target = float(p.get("w_target", 0.0))
+    c.w_yaw = float(p.get("w_yaw", 0.0))
+    c.collision_only = int(p.get("collision_only", 0))
     return c
 
 

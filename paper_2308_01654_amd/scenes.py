@@ -253,6 +253,58 @@ def paper_table1():
                 iterations=1)
 
 
+# ---- the paper's three scenarios (Sec. IV-A) with its full Sec. IV-C cost
+# and Table I parameters, on synthetic straight roads: lane merge, object
+# avoidance (collision-only obstacle cost, a 0.7 m margin around the object)
+# and vehicle following (velocity-dependent safe distance).
+
+V_G = 30.0 / 3.6                       # target speed of Table I
+
+
+def paper_params(**over):
+    """Table I and the Sec. IV-C weights 15 / 7 / 120 / 5 / 25 (the paper's
+    total has no input cost term), Savitzky-Golay smoothing on."""
+    p = params(K=2560, T=16, dt=0.25, lam=150.0, sigma=(0.85, 0.05), v_max=V_G,
+               u_min=(-2.5, -0.5), u_max=(1.1, 0.5),
+               w_track=15.0, w_target=7.0, w_yaw=120.0, w_speed=5.0, w_coll=25.0,
+               w_effort=0.0, d_safe_c=1.36, d_safe_0=11.0, smoothing=1, seed=11)
+    p.update(over)
+    return p
+
+
+def car_circles(x, y, r=1.0, vx=0.0, vy=0.0, margin=0.0):
+    """A car-sized object (4.5 m x 1.8 m) as three circles along x."""
+    return np.array([[x + dx, y, r + margin, vx, vy] for dx in (-1.5, 0.0, 1.5)])
+
+
+def paper_merge():
+    """Lane merge: the path is the lane y = 0; the vehicle starts on the
+    parallel lane 3.5 m to the left at 5 m/s."""
+    p = paper_params(seed=21)
+    wp = straight_lane(-10.0, 200.0, V_G)
+    return dict(name="paper_merge", params=p, x0=np.array([0.0, 3.5, 0.0, 5.0]), waypoints=wp,
+                circles=np.zeros((0, 5)), iterations=1)
+
+
+def paper_avoid():
+    """Object avoidance: a stopped car on the path 40 m ahead; obstacle
+    cost only on contact (collision-only mode), the object inflated by the
+    prescribed 0.7 m margin."""
+    p = paper_params(seed=22, collision_only=1)
+    wp = straight_lane(-10.0, 200.0, V_G)
+    return dict(name="paper_avoid", params=p, x0=np.array([0.0, 0.0, 0.0, V_G]), waypoints=wp,
+                circles=car_circles(40.0, 0.0, margin=0.7), iterations=1)
+
+
+def paper_follow(lead_speed=4.0):
+    """Vehicle following: a car 30 m ahead on the path at lead_speed; the
+    safe distance 1.36 v + 11 m of Table I keeps the follower behind it."""
+    p = paper_params(seed=23)
+    wp = straight_lane(-10.0, 400.0, V_G)
+    return dict(name="paper_follow", params=p, x0=np.array([0.0, 0.0, 0.0, V_G]), waypoints=wp,
+                circles=car_circles(30.0, 0.0, vx=lead_speed), iterations=1)
+
+
 def tiny(K=8, T=4, n_c=3, seed=7):
     """A small random scene for exhaustive checks."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -287,4 +339,6 @@ def speed_profile(sc, seed=0, n_dup=12):
 
 
 def by_name(name):
-    return {"c0": c0, "c1": c1, "c4": c4, "paper_table1": paper_table1, "tiny": tiny}[name]()
+    return {"c0": c0, "c1": c1, "c4": c4, "paper_table1": paper_table1, "tiny": tiny,
+            "paper_merge": paper_merge, "paper_avoid": paper_avoid,
+            "paper_follow": paper_follow}[name]()

@@ -667,3 +667,23 @@ def test_paper_weights_worked_total():
                             x_prev=[20.5, 1.0, 0.1, 12.0])
     assert np.allclose(parts, [1.0, 4.0, 0.0, 0.0, 1.0, 0.01], rtol=1e-12, atol=1e-15)
     assert math.isclose(c, 43.2, rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("name", ["paper_merge", "paper_avoid", "paper_follow"])
+def test_paper_scenarios_closed_loop_oracle(name):
+    """The oracle planner with the paper's cost and Table I parameters
+    reproduces the qualitative outcomes the paper reports (speed never above
+    30 km/h, steering within 10 degrees, no collision, merge onto the lane,
+    pass the object, settle behind the lead vehicle)."""
+    from tests import _closed_loop as CL
+    sc = scenes.by_name(name)
+    p = sc["params"]
+    state = {"U": np.zeros((p["T"], 2))}
+
+    def plan(k, x, circ):
+        U = state["U"] if k == 0 else np.vstack([state["U"][1:], state["U"][-1:]])
+        state["U"] = O.iteration(p, x, sc["waypoints"], circ, U, n_iter=k)["U"]
+        return O.optimal_trajectory(p, x, state["U"])
+
+    xs, us, ds = CL.drive(sc, plan, 60)
+    CL.check_outcomes(name, p, xs, us, ds)
