@@ -137,7 +137,8 @@ def sweep():
     """Kernel time of one iteration for every lanes-per-sample shape on the
     plain, sine-lane, stress and paper-shaped workloads (HIP events)."""
     from paper_2308_01654_amd import mppi, scenes
-    for sc in (scenes.c0(), scenes.c1(), scenes.c4(), scenes.paper_table1()):
+    for sc in (scenes.c0(), scenes.c1(), scenes.c4(), scenes.paper_table1(),
+               scenes.paper_merge(), scenes.paper_avoid(), scenes.paper_follow()):
         p = sc["params"]
         K, T = p["K"], p["T"]
         F = flops_per_rollout_step(len(sc["waypoints"]), len(sc["circles"]), len(p["ego_off"]))
@@ -187,6 +188,28 @@ def alg1_output(p, x0, wp, circ, warmup, steps):
     return {"smoothing_kernel_ms": round(prof["iter_ms"] / max(prof["iter_launches"], 1), 5),
             "trajectory_call_ms_p50": round(float(np.percentile(lat, 50)), 4),
             "trajectory_call_ms_p99": round(float(np.percentile(lat, 99)), 4)}
+
+
+def paper_cost_kernels(steps=50):
+    """Iteration kernel time (HIP events, tuned launch shape) of the paper's
+    full-cost scenarios at the Table I shape (K=2560, T=16, dt=0.25)."""
+    from paper_2308_01654_amd import mppi, scenes
+    out = {}
+    for f in (scenes.paper_merge, scenes.paper_avoid, scenes.paper_follow):
+        sc = f()
+        pl = mppi.Planner(sc["params"])
+        pl.set_scene(sc["x0"], sc["waypoints"], sc["circles"])
+        for _ in range(5):
+            pl.step_resident(sc["x0"])
+        pl.sync()
+        pl.set_profiling(True)
+        for _ in range(steps):
+            pl.step_resident(sc["x0"])
+        pl.sync()
+        prof = pl.profile()
+        pl.close()
+        out[sc["name"] + "_kernel_ms"] = round(prof["iter_ms"] / max(prof["iter_launches"], 1), 5)
+    return out
 
 
 def c3_load(n_vehicles, duration_s, pool_size=512, seed=33):
@@ -343,6 +366,7 @@ def main(argv=None):
     pcie_value = K * T * 50 / (time.perf_counter() - a)
     pl.close()
     smooth = alg1_output(p, x0, wp, circ, args.warmup, args.steps)
+    smooth.update(paper_cost_kernels())
 
     out = {
         "metric": METRIC,

@@ -684,9 +684,13 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             c = __cosf(th);
             sn = __sinf(th);
             if (i == rb) {
-                mx = x; my = y; mc = c; ms = sn; mv = v; ma = a; mth = th;
+                mx = x; my = y; mv = v; ma = a; mth = th;
             }
         }
+        // the heading's cosine and sine at this lane's step, recomputed from the
+        // kept heading with the instructions of the walk (same bits)
+        mc = __cosf(mth);
+        ms = __sinf(mth);
         const float mUa = Um.x, mUd = Um.y;
         const float mea = ma - Um.x, med = dlm - Um.y;
         const bool act = tm < T;
