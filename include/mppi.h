@@ -95,6 +95,12 @@ typedef struct mppi_config {
                               waypoint's yaw, wrapped into [-pi, pi), squared            */
     int32_t collision_only;/* 1: c_safe_dist only when an object is hit, d_obj <= 0
                               (the paper's object-avoidance mode); 0: always            */
+    int32_t model;         /* 0: 4-state bicycle, controls (a, steering angle delta);
+                              1: the 5-state model of eq. (5), the steering angle is
+                              state and the second control is the steering rate omega
+                              (sigma[1], u_min[1], u_max[1] then bound omega, e.g.
+                              +-omega_max); the initial angle comes from
+                              mppi_set_steering.  Served vehicles must use 0.          */
 } mppi_config;
 
 /* Scene and road model of one request, world coordinates. */
@@ -199,13 +205,19 @@ mppi_status mppi_get_costs(mppi_t* h, float* out, size_t n);
 mppi_status mppi_get_weights(mppi_t* h, double* out, size_t n);
 mppi_status mppi_get_noise(mppi_t* h, float* out, size_t n);
 
+/* Steering angle delta0 [rad] of the next steps' initial state for the
+ * 5-state model (cfg.model = 1; ignored otherwise).  Default 0; kept until
+ * changed.  MPPI_E_INVALID if not finite. */
+mppi_status mppi_set_steering(mppi_t* h, double delta0);
+
 /* The optimal trajectory of Alg. 1 (the rollout after the update): from the
  * x0 of the last completed step, x*_{t+1} = F(x*_t, u*_t) (eq. (5), explicit
  * Euler) under the handle's current nominal controls u* (the smoothed
  * sequence when cfg.smoothing = 1), each control put through the noise check
  * with zero noise so that the trajectory respects the bounds and the speed
  * cap.  Computed in float64 on the device; synchronises the handle's stream.
- * states: [T+1][4] world-frame (x, y, yaw, v), n_states >= 4 (T+1);
+ * states: [T+1][4] world-frame (x, y, yaw, v) -- [T+1][5] with the steering
+ * angle for the 5-state model --, n_states >= columns (T+1);
  * controls: [T][2] applied (a, delta), n_controls >= 2T (either may be NULL).
  * MPPI_E_INVALID before the first step or for short buffers (nothing
  * written). */

@@ -56,6 +56,11 @@
  *     z_d = rho sin(2 pi u2).
  *   - a non-finite S_k counts as +inf; if every S_k is non-finite the
  *     iteration fails and U is left unchanged.
+ *   - the 5-state model of eq. (5) (cfg.model = 1): the state carries the
+ *     steering angle delta (initial value cfg.steer0) and the second
+ *     control is the steering rate omega, clamped to [u_min, u_max] of that
+ *     control (+-omega_max) by the noise check; explicit Euler from the old
+ *     state: theta' = theta + dt v tan(delta) / l, delta' = delta + dt omega.
  *   - the other Sec. IV-C terms (zero weight unless configured):
  *     c_target = 1 when the step ends farther from the target point T_P
  *     than it started (squared distances compared), T_P being the last
@@ -98,6 +103,8 @@ typedef struct orc_cfg {
     double w_target;    /* weight of c_target (Sec. IV-C) */
     double w_yaw;       /* weight of c_yaw (Sec. IV-C) */
     int32_t collision_only; /* 1: c_safe_dist only when an object is hit */
+    int32_t model;      /* 0: 4-state, steering-angle control; 1: eq. (5) 5-state */
+    double steer0;      /* initial steering angle of the 5-state model */
 } orc_cfg;
 
 enum { ORC_OK = 0, ORC_E_INVALID = -1, ORC_E_NONFINITE = -4 };
@@ -193,14 +200,18 @@ void orc_apply_limits(const orc_cfg* c, const double U[2], const double eps[2], 
     applied[1] = clampd(U[1] + eps[1], c->d_min, c->d_max);
 }
 
-/* Eq. (5), explicit Euler with every right-hand side from the old state. */
-void orc_dynamics(const orc_cfg* c, const double x[4], const double u[2], double xn[4])
+/* Eq. (5), explicit Euler with every right-hand side from the old state.
+ * States have 5 entries (x, y, theta, v, delta); with the 4-state model the
+ * steering angle is the control u[1] and x[4] is carried unchanged. */
+void orc_dynamics(const orc_cfg* c, const double x[5], const double u[2], double xn[5])
 {
     double dt = c->dt;
+    double delta = c->model ? x[4] : u[1];
     xn[0] = x[0] + dt * x[3] * cos(x[2]);
     xn[1] = x[1] + dt * x[3] * sin(x[2]);
-    xn[2] = x[2] + dt * x[3] * tan(u[1]) / c->wheelbase;
+    xn[2] = x[2] + dt * x[3] * tan(delta) / c->wheelbase;
     xn[3] = x[3] + dt * u[0];
+    xn[4] = c->model ? x[4] + dt * u[1] : x[4];
 }
 
 /* c_dist and the reference yaw and speed of the closest waypoint (Sec. IV-C). */
@@ -307,7 +318,7 @@ int orc_rollout(const orc_cfg* c, const double x0[4], const double* wp, int n_wp
     const int K = c->K, T = c->T;
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < K; ++k) {
-        double x[4] = { x0[0], x0[1], x0[2], x0[3] };
+        double x[5] = { x0[0], x0[1], x0[2], x0[3], c->steer0 };
         double S = 0.0;
         for (int t = 0; t < T; ++t) {
             const double* Ut = U + 2 * t;
@@ -328,7 +339,7 @@ int orc_rollout(const orc_cfg* c, const double x0[4], const double* wp, int n_wp
                 eps_out[((size_t)t * K + k) * 2 + 0] = e[0];
                 eps_out[((size_t)t * K + k) * 2 + 1] = e[1];
             }
-            double xn[4];
+            double xn[5];
             orc_dynamics(c, x, u, xn);
             S += orc_stage_cost(c, wp, n_wp, circ, n_c, xn, Ut, e, t, x, NULL);
             memcpy(x, xn, sizeof x);
@@ -353,7 +364,7 @@ int orc_rollout_samples(const orc_cfg* c, const double x0[4], const double* wp, 
 #pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < nk; ++i) {
         const int k = ks[i];
-        double x[4] = { x0[0], x0[1], x0[2], x0[3] };
+        double x[5] = { x0[0], x0[1], x0[2], x0[3], c->steer0 };
         double S = 0.0;
         for (int t = 0; t < T; ++t) {
             const double* Ut = U + 2 * t;
@@ -374,7 +385,7 @@ int orc_rollout_samples(const orc_cfg* c, const double x0[4], const double* wp, 
                 eps_out[((size_t)t * nk + i) * 2 + 0] = e[0];
                 eps_out[((size_t)t * nk + i) * 2 + 1] = e[1];
             }
-            double xn[4];
+            double xn[5];
             orc_dynamics(c, x, u, xn);
             S += orc_stage_cost(c, wp, n_wp, circ, n_c, xn, Ut, e, t, x, NULL);
             memcpy(x, xn, sizeof x);
@@ -392,16 +403,17 @@ int orc_simulate(const orc_cfg* c, const double x0[4], const double* wp, int n_w
                  double* states, double* costs, double* parts)
 {
     if (!cfg_ok(c, n_wp, n_c)) return ORC_E_INVALID;
-    double x[4] = { x0[0], x0[1], x0[2], x0[3] };
-    memcpy(states, x, sizeof x);
+    const int ns = 4 + (c->model ? 1 : 0);  /* state columns written */
+    double x[5] = { x0[0], x0[1], x0[2], x0[3], c->steer0 };
+    memcpy(states, x, ns * sizeof(double));
     for (int t = 0; t < c->T; ++t) {
         double e[2] = { eps ? eps[2 * t] : 0.0, eps ? eps[2 * t + 1] : 0.0 };
         double u[2] = { U[2 * t] + e[0], U[2 * t + 1] + e[1] };
-        double xn[4];
+        double xn[5];
         orc_dynamics(c, x, u, xn);
         costs[t] = orc_stage_cost(c, wp, n_wp, circ, n_c, xn, U + 2 * t, e, t, x,
                                   parts ? parts + 6 * t : NULL);
-        memcpy(states + 4 * (t + 1), xn, sizeof xn);
+        memcpy(states + ns * (t + 1), xn, ns * sizeof(double));
         memcpy(x, xn, sizeof x);
     }
     return ORC_OK;
@@ -463,16 +475,21 @@ void orc_sg_smooth(const double* U, int T, double* out)
 }
 
 /* The optimal rollout of Alg. 1 from x0 under the controls Us [T][2]: each
- * control passes the noise check with zero noise, states [T+1][4] and the
- * applied controls [T][2] are returned. */
+ * control passes the noise check with zero noise; states [T+1][4] ([T+1][5]
+ * with the steering angle for the 5-state model) and the applied controls
+ * [T][2] are returned. */
 void orc_optimal_trajectory(const orc_cfg* c, const double x0[4], const double* Us,
                             double* states, double* applied)
 {
     static const double zero[2] = {0.0, 0.0};
-    memcpy(states, x0, 4 * sizeof(double));
+    const int ns = 4 + (c->model ? 1 : 0);
+    double x[5] = { x0[0], x0[1], x0[2], x0[3], c->steer0 }, xn[5];
+    memcpy(states, x, ns * sizeof(double));
     for (int t = 0; t < c->T; ++t) {
-        orc_apply_limits(c, Us + 2 * t, zero, states[4 * t + 3], applied + 2 * t);
-        orc_dynamics(c, states + 4 * t, applied + 2 * t, states + 4 * (t + 1));
+        orc_apply_limits(c, Us + 2 * t, zero, x[3], applied + 2 * t);
+        orc_dynamics(c, x, applied + 2 * t, xn);
+        memcpy(states + ns * (t + 1), xn, ns * sizeof(double));
+        memcpy(x, xn, sizeof x);
     }
 }
 

@@ -46,6 +46,7 @@ class OrcCfg(ctypes.Structure):
         ("smoothing", ctypes.c_int32),
         ("w_target", ctypes.c_double), ("w_yaw", ctypes.c_double),
         ("collision_only", ctypes.c_int32),
+        ("model", ctypes.c_int32), ("steer0", ctypes.c_double),
     ]
 
 
@@ -132,6 +133,8 @@ def make_cfg(p) -> OrcCfg:
     c.w_target = float(p.get("w_target", 0.0))
     c.w_yaw = float(p.get("w_yaw", 0.0))
     c.collision_only = int(p.get("collision_only", 0))
+    c.model = int(p.get("model", 0))
+    c.steer0 = float(p.get("steer0", 0.0))
     return c
 
 
@@ -185,11 +188,15 @@ def apply_limits(p, U_t, eps, v):
 
 
 def dynamics(p, x, u):
+    """One Euler step: x is (x, y, theta, v) or, for the 5-state model,
+    (x, y, theta, v, delta); returns the same length."""
     c = make_cfg(p)
     x, u = _f64(x), _f64(u)
-    out = np.zeros(4)
-    lib().orc_dynamics(ctypes.byref(c), _dp(x), _dp(u), _dp(out))
-    return out
+    x5 = np.zeros(5)
+    x5[:x.shape[0]] = x
+    out = np.zeros(5)
+    lib().orc_dynamics(ctypes.byref(c), _dp(x5), _dp(u), _dp(out))
+    return out[:x.shape[0]]
 
 
 def stage_cost(p, waypoints, circles, x_new, U_t, eps, t, x_prev=None):
@@ -217,7 +224,7 @@ def simulate(p, x0, waypoints, circles, U, eps=None):
     U = _f64(U, (T, 2))
     e = None if eps is None else _f64(eps, (T, 2))
     x0 = _f64(x0)
-    states = np.zeros((T + 1, 4))
+    states = np.zeros((T + 1, 4 + (1 if c.model else 0)))
     costs = np.zeros(T)
     parts = np.zeros((T, 6))
     rc = lib().orc_simulate(ctypes.byref(c), _dp(x0), _dp(wp), wp.shape[0], _dp(ci),
@@ -330,7 +337,7 @@ def optimal_trajectory(p, x0, Us):
     c = make_cfg(p)
     Us = _f64(Us, (c.T, 2))
     x0 = _f64(x0)
-    states = np.zeros((c.T + 1, 4))
+    states = np.zeros((c.T + 1, 4 + (1 if c.model else 0)))
     applied = np.zeros((c.T, 2))
     lib().orc_optimal_trajectory(ctypes.byref(c), _dp(x0), _dp(Us), _dp(states), _dp(applied))
     return states, applied

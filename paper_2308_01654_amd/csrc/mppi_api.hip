@@ -105,6 +105,7 @@ mppi_status validate_config(const mppi_config* c)
         return fail(MPPI_E_INVALID, "w_target and w_yaw must be finite");
     if (c->collision_only != 0 && c->collision_only != 1)
         return fail(MPPI_E_INVALID, "collision_only must be 0 or 1");
+    if (c->model != 0 && c->model != 1) return fail(MPPI_E_INVALID, "model must be 0 or 1");
     return MPPI_OK;
 }
 
@@ -337,7 +338,7 @@ mppi_status handle_create(const mppi_config* cfg, void* hip_stream, bool with_sc
         h->own_stream = true;
     }
     if ((e = hipMalloc((void**)&h->U, sizeof(double) * 2 * T)) != hipSuccess ||
-        (e = hipMalloc((void**)&h->traj, sizeof(double) * (4 * (size_t)(T + 1) + 2 * T))) !=
+        (e = hipMalloc((void**)&h->traj, sizeof(double) * (5 * (size_t)(T + 1) + 2 * T))) !=
             hipSuccess ||
         (e = hipMalloc((void**)&h->st, state_bytes(h->max_tiles))) != hipSuccess)
         return bail(MPPI_E_NOMEM, "hipMalloc", e);
@@ -418,6 +419,8 @@ void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double or
     d.w_target = (float)c.w_target;
     d.w_yaw = (float)c.w_yaw;
     d.coll_only = c.collision_only;
+    d.model = c.model;
+    d.steer0 = (float)h->steer0;
     d.ego_ext = 0.f;
     for (int e = 0; e < c.n_ego; ++e) d.ego_ext = fmaxf(d.ego_ext, (float)fabs(c.ego_off[e]));
     d.out_slot = -1;
@@ -542,7 +545,7 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
         const int g = hs[i]->lanes_req ? hs[i]->lanes_req : auto_lanes(c, nc);
         const int gi = g == 1 ? 0 : g == 2 ? 1 : g == 4 ? 2 : g == 8 ? 3 : 4;
         order[i] = i;
-        cls[i] = 5 * gi + active_ego(c.n_ego, nc);
+        cls[i] = 25 * (c.model ? 1 : 0) + 5 * gi + active_ego(c.n_ego, nc);
         work[i] = (double)c.T * (73.0 + 6.0 * nw + 7.0 * c.n_ego * nc);
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
@@ -608,8 +611,8 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
         if (e == hipSuccess && shift_blocks) e = launch_shift_batch(hdr_dev, shift_blocks, stream);
         for (int c = 0; c < kLaneClasses && e == hipSuccess; ++c)
             if (grids[c] > 0)
-                e = launch_batch(kClassLanes[c / 5], c % 5, nullptr, hdr_dev, c, grids[c], smem_b,
-                                 stream);
+                e = launch_batch(kClassLanes[(c % 25) / 5], c % 5, c / 25, nullptr, hdr_dev, c,
+                                 grids[c], smem_b, stream);
         if (e == hipSuccess && gather_blocks)
             e = launch_gather(hdr_dev, gather_blocks, gather_dev, slot_doubles, stream);
         return e;
@@ -660,6 +663,7 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
         hs[order[j]]->stepped = true;
         hs[order[j]]->last_lanes = descs[j].lanes;
         memcpy(hs[order[j]]->last_x0, x0s + 4 * order[j], sizeof(double) * 4);
+        hs[order[j]]->last_steer0 = hs[order[j]]->steer0;
     }
     return MPPI_OK;
 }
@@ -742,12 +746,13 @@ mppi_status mppi_step_resident(mppi_t* h, const double x0[4])
     const size_t smem = lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes).total;
     hipEvent_t a = nullptr;
     if ((s = record_launch(h, 0, &a)) != MPPI_OK) return s;
-    HIP_TRY(launch_batch(d.lanes, active_ego(d.n_ego, d.n_c), &d, nullptr, 0, d.n_tiles, smem,
-                         h->stream));
+    HIP_TRY(launch_batch(d.lanes, active_ego(d.n_ego, d.n_c), d.model, &d, nullptr, 0, d.n_tiles,
+                         smem, h->stream));
     if ((s = record_end(h, 0, a)) != MPPI_OK) return s;
     h->last_lanes = d.lanes;
     h->stepped = true;
     memcpy(h->last_x0, x0, sizeof(double) * 4);
+    h->last_steer0 = h->steer0;
     return MPPI_OK;
 }
 
@@ -900,15 +905,18 @@ mppi_status mppi_get_trajectory(mppi_t* h, double* states, size_t n_states, doub
     mppi_status s = usable(h);
     if (s != MPPI_OK) return s;
     const int T = h->cfg.T;
+    const size_t cols = h->cfg.model ? 5 : 4;
     if (!h->stepped) return fail(MPPI_E_INVALID, "no step has been taken");
-    if (states && n_states < (size_t)4 * (T + 1))
-        return fail(MPPI_E_INVALID, "states needs 4*(T+1) doubles");
+    if (states && n_states < cols * (T + 1))
+        return fail(MPPI_E_INVALID, "states needs %zu*(T+1) doubles", cols);
     if (controls && n_controls < (size_t)2 * T)
         return fail(MPPI_E_INVALID, "controls needs 2*T doubles");
     TrajArgs a;
     const mppi_config& c = h->cfg;
     for (int i = 0; i < 4; ++i) a.x0[i] = h->last_x0[i];
+    a.steer0 = h->last_steer0;
     a.T = T;
+    a.model = c.model;
     a.dt = c.dt;
     a.wheelbase = c.wheelbase;
     a.a_min = c.u_min[0];
@@ -916,13 +924,23 @@ mppi_status mppi_get_trajectory(mppi_t* h, double* states, size_t n_states, doub
     a.d_min = c.u_min[1];
     a.d_max = c.u_max[1];
     a.v_max = c.v_max;
-    HIP_TRY(launch_trajectory(a, h->U, h->traj, h->traj + 4 * (size_t)(T + 1), h->stream));
+    double* xs = h->traj;
+    double* us = h->traj + 5 * (size_t)(T + 1);
+    HIP_TRY(launch_trajectory(a, h->U, xs, us, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     if (states)
-        HIP_TRY(hipMemcpy(states, h->traj, sizeof(double) * 4 * (T + 1), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(states, xs, sizeof(double) * cols * (T + 1), hipMemcpyDeviceToHost));
     if (controls)
-        HIP_TRY(hipMemcpy(controls, h->traj + 4 * (size_t)(T + 1), sizeof(double) * 2 * T,
-                          hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(controls, us, sizeof(double) * 2 * T, hipMemcpyDeviceToHost));
+    return MPPI_OK;
+}
+
+mppi_status mppi_set_steering(mppi_t* h, double delta0)
+{
+    mppi_status s = usable(h);
+    if (s != MPPI_OK) return s;
+    if (!isfinite(delta0)) return fail(MPPI_E_INVALID, "steering angle must be finite");
+    h->steer0 = delta0;
     return MPPI_OK;
 }
 

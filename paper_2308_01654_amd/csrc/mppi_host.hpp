@@ -94,6 +94,8 @@ struct mppi {
     // last step
     bool stepped = false;
     double last_x0[4] = {0.0, 0.0, 0.0, 0.0};
+    double steer0 = 0.0;      // initial steering angle (5-state model)
+    double last_steer0 = 0.0; // the one the last step used
     // profiling
     bool prof = false;
     std::vector<mppi_impl::ProfEvent> events;

@@ -72,6 +72,8 @@ struct InstDesc {
     int smooth;           // end with the Savitzky-Golay filter of eq. (sg)
     float w_target, w_yaw;// weights of c_target and c_yaw (0: term skipped)
     int coll_only;        // c_safe_dist only when d_obj <= 0
+    int model;            // 1: 5-state model of eq. (5), steering-rate control
+    float steer0;         // its initial steering angle
     float ego_ext;        // max |ego_off|
     int out_slot;         // slot in the gathered results of a batch (-1: none)
     // device pointers
@@ -89,11 +91,11 @@ struct InstDesc {
 
 // Header of a batch arena in device memory: followed by the tile prefix
 // (n_inst + 1 ints) at off_prefix and the descriptors at off_descs.
-// Instances are grouped by kernel variant: class c = 5 * lane_index + ne
-// (lane_index 0..4 for 1, 2, 4, 8, 16 lanes per sample; ne = ego circles
-// that meet obstacle circles, 0..4) owns instances [cls_begin[c],
-// cls_begin[c+1]).
-constexpr int kLaneClasses = 25;
+// Instances are grouped by kernel variant: class c = 25 * model +
+// 5 * lane_index + ne (model 0 or 1 (5-state); lane_index 0..4 for 1, 2, 4,
+// 8, 16 lanes per sample; ne = ego circles that meet obstacle circles, 0..4)
+// owns instances [cls_begin[c], cls_begin[c+1]).
+constexpr int kLaneClasses = 50;
 struct BatchHdr {
     int n_inst;
     int total_tiles;
@@ -138,8 +140,9 @@ inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int sp
 // Iteration kernel, one workgroup per tile: one instance (d0, hdr_dev ==
 // nullptr) or lanes class `cls` of the batch described by the arena at
 // hdr_dev (lanes is the launch shape of every instance it processes).
-hipError_t launch_batch(int lanes, int ne, const InstDesc* d0, const BatchHdr* hdr_dev, int cls,
-                        int grid, size_t smem, hipStream_t stream);
+hipError_t launch_batch(int lanes, int ne, int model, const InstDesc* d0,
+                        const BatchHdr* hdr_dev, int cls, int grid, size_t smem,
+                        hipStream_t stream);
 
 // Ego circles that take part in the obstacle term of an instance.
 inline int active_ego(int n_ego, int n_c) { return n_c > 0 ? n_ego : 0; }
@@ -154,7 +157,9 @@ hipError_t launch_weights(const InstDesc& d, double* w_out, hipStream_t stream);
 // controls U [T][2]: states [T+1][4] and applied controls [T][2].
 struct TrajArgs {
     double x0[4];
+    double steer0;  // initial steering angle (model 1)
     int T;
+    int model;      // 1: 5-state model, states written with 5 columns
     double dt, wheelbase, a_min, a_max, d_min, d_max, v_max;
 };
 hipError_t launch_trajectory(const TrajArgs& a, const double* U, double* states, double* applied,

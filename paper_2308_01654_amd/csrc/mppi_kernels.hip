@@ -572,7 +572,9 @@ __device__ __forceinline__ double block_min(double v, double* red)
     return r;
 }
 
-template <int G, int NE>
+// M5: the 5-state model of eq. (5) -- the steering angle is part of the state
+// and the second control is the steering rate.
+template <int G, int NE, bool M5>
 __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
 {
     const int tid = threadIdx.x;
@@ -633,6 +635,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         lc.crr = lane < d.n_c ? s.c_rr[lane] : 0.0f;
     }
     float x = d.px0, y = d.py0, th = d.th0, v = d.v0;
+    float delta = d.steer0;  // steering angle (5-state model only)
     float c = __cosf(th), sn = __sinf(th);
     float S = 0.0f, comp = 0.0f;  // Kahan pair of this lane's steps
     for (int t0 = 0; t0 < T; t0 += G) {
@@ -644,13 +647,15 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         asm volatile("" : "+v"(rb));
         const int tc = tm < T ? tm : T - 1;
         // This lane's step: perturbation, the state-independent part of the
-        // noise check (control bounds) and the steering tangent, computed
-        // once per step and handed to the G lanes that integrate it.
+        // noise check (control bounds) and -- for the steering-angle control --
+        // its tangent, computed once per step and handed to the G lanes that
+        // integrate it.  With the 5-state model the second control is the
+        // steering rate, handed over as it is.
         const float2 em = draw_noise(d, kk, tc, n_iter);
         const float2 Um = s.U[tc];
         const float a0m = fminf(fmaxf(Um.x + em.x, d.a_min), d.a_max);
         const float dlm = fminf(fmaxf(Um.y + em.y, d.d_min), d.d_max);
-        const float tnm = __tanf(dlm);
+        const float tnm = M5 ? dlm : __tanf(dlm);
         // position at the start of the block, for c_target of its first step
         if (d.w_target != 0.0f && r == 0) s.blk[grp] = make_float2(x, y);
         float mx = 0.f, my = 0.f, mc = 1.f, ms = 0.f, mv = 0.f, ma = 0.f, mth = 0.f;
@@ -679,7 +684,14 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             const float vdt = v * d.dt;
             x = fmaf(vdt, c, x);
             y = fmaf(vdt, sn, y);
-            th = fmaf(vdt * d.inv_L, tpf[i % PF], th);
+            if (M5) {
+                // eq. (5): the heading turns with the steering angle before
+                // the step, which then moves at the applied rate
+                th = fmaf(vdt * d.inv_L, __tanf(delta), th);
+                delta = fmaf(d.dt, tpf[i % PF], delta);
+            } else {
+                th = fmaf(vdt * d.inv_L, tpf[i % PF], th);
+            }
             v = fmaf(d.dt, a, v);
             c = __cosf(th);
             sn = __sinf(th);
@@ -897,29 +909,34 @@ __global__ void k_trajectory(TrajArgs a, const double* __restrict__ U, double* _
                              double* __restrict__ us)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double x = a.x0[0], y = a.x0[1], th = a.x0[2], v = a.x0[3];
-    xs[0] = x;
-    xs[1] = y;
-    xs[2] = th;
-    xs[3] = v;
+    const int cols = a.model ? 5 : 4;  // the 5-state model also writes delta
+    double x = a.x0[0], y = a.x0[1], th = a.x0[2], v = a.x0[3], delta = a.steer0;
+    auto put = [&](int t) {
+        double* o = xs + (size_t)cols * t;
+        o[0] = x;
+        o[1] = y;
+        o[2] = th;
+        o[3] = v;
+        if (a.model) o[4] = delta;
+    };
+    put(0);
     for (int t = 0; t < a.T; ++t) {
         double acc = fmin(fmax(U[2 * t], a.a_min), a.a_max);
         acc = fmax(fmin(acc, (a.v_max - v) / a.dt), a.a_min);
-        const double dl = fmin(fmax(U[2 * t + 1], a.d_min), a.d_max);
+        const double u2 = fmin(fmax(U[2 * t + 1], a.d_min), a.d_max);
         const double vdt = a.dt * v;
         const double xn = x + vdt * cos(th);
         const double yn = y + vdt * sin(th);
-        const double thn = th + vdt * tan(dl) / a.wheelbase;
+        // the steering angle is the control, or (5-state model) the state
+        const double thn = th + vdt * tan(a.model ? delta : u2) / a.wheelbase;
+        if (a.model) delta += a.dt * u2;
         v += a.dt * acc;
         x = xn;
         y = yn;
         th = thn;
         us[2 * t] = acc;
-        us[2 * t + 1] = dl;
-        xs[4 * (t + 1)] = x;
-        xs[4 * (t + 1) + 1] = y;
-        xs[4 * (t + 1) + 2] = th;
-        xs[4 * (t + 1) + 3] = v;
+        us[2 * t + 1] = u2;
+        put(t + 1);
     }
 }
 
@@ -931,14 +948,14 @@ __global__ void k_trajectory(TrajArgs a, const double* __restrict__ U, double* _
 // the instance, so an instance computes the same bits alone or in any batch.
 // Workgroups past the last tile of the class (the grid is rounded up so that
 // captured graphs can be replayed for other batches) return at once.
-template <int G, int NE>
+template <int G, int NE, bool M5>
 __global__ __launch_bounds__(kBlock) void k_batch(InstDesc d0, const BatchHdr* __restrict__ hdr,
                                                   int cls)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int w = blockIdx.x;
     if (!hdr) {
-        if (w < d0.n_tiles) iteration_tile<G, NE>(d0, w, smem);
+        if (w < d0.n_tiles) iteration_tile<G, NE, M5>(d0, w, smem);
         return;
     }
     const unsigned char* base = reinterpret_cast<const unsigned char*>(hdr);
@@ -953,37 +970,46 @@ __global__ __launch_bounds__(kBlock) void k_batch(InstDesc d0, const BatchHdr* _
         const int mid = (lo + hi + 1) >> 1;
         if (prefix[mid] <= gw) lo = mid; else hi = mid - 1;
     }
-    iteration_tile<G, NE>(descs[lo], gw - prefix[lo], smem);
+    iteration_tile<G, NE, M5>(descs[lo], gw - prefix[lo], smem);
 }
 
-template <int G>
-static hipError_t launch_g(int ne, const InstDesc& a, const BatchHdr* hdr_dev, int cls, int grid,
-                           size_t smem, hipStream_t stream)
+template <int G, bool M5>
+static hipError_t launch_gm(int ne, const InstDesc& a, const BatchHdr* hdr_dev, int cls, int grid,
+                            size_t smem, hipStream_t stream)
 {
     const dim3 g(grid), b(kBlock);
     switch (ne) {
-    case 0: hipLaunchKernelGGL((k_batch<G, 0>), g, b, smem, stream, a, hdr_dev, cls); break;
-    case 1: hipLaunchKernelGGL((k_batch<G, 1>), g, b, smem, stream, a, hdr_dev, cls); break;
-    case 2: hipLaunchKernelGGL((k_batch<G, 2>), g, b, smem, stream, a, hdr_dev, cls); break;
-    case 3: hipLaunchKernelGGL((k_batch<G, 3>), g, b, smem, stream, a, hdr_dev, cls); break;
-    case 4: hipLaunchKernelGGL((k_batch<G, 4>), g, b, smem, stream, a, hdr_dev, cls); break;
+    case 0: hipLaunchKernelGGL((k_batch<G, 0, M5>), g, b, smem, stream, a, hdr_dev, cls); break;
+    case 1: hipLaunchKernelGGL((k_batch<G, 1, M5>), g, b, smem, stream, a, hdr_dev, cls); break;
+    case 2: hipLaunchKernelGGL((k_batch<G, 2, M5>), g, b, smem, stream, a, hdr_dev, cls); break;
+    case 3: hipLaunchKernelGGL((k_batch<G, 3, M5>), g, b, smem, stream, a, hdr_dev, cls); break;
+    case 4: hipLaunchKernelGGL((k_batch<G, 4, M5>), g, b, smem, stream, a, hdr_dev, cls); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_batch(int lanes, int ne, const InstDesc* d0, const BatchHdr* hdr_dev, int cls,
-                        int grid, size_t smem, hipStream_t stream)
+template <int G>
+static hipError_t launch_g(int ne, int model, const InstDesc& a, const BatchHdr* hdr_dev, int cls,
+                           int grid, size_t smem, hipStream_t stream)
+{
+    return model ? launch_gm<G, true>(ne, a, hdr_dev, cls, grid, smem, stream)
+                 : launch_gm<G, false>(ne, a, hdr_dev, cls, grid, smem, stream);
+}
+
+hipError_t launch_batch(int lanes, int ne, int model, const InstDesc* d0,
+                        const BatchHdr* hdr_dev, int cls, int grid, size_t smem,
+                        hipStream_t stream)
 {
     InstDesc zero;
     memset(&zero, 0, sizeof zero);
     const InstDesc& a = d0 ? *d0 : zero;
     switch (lanes) {
-    case 1: return launch_g<1>(ne, a, hdr_dev, cls, grid, smem, stream);
-    case 2: return launch_g<2>(ne, a, hdr_dev, cls, grid, smem, stream);
-    case 4: return launch_g<4>(ne, a, hdr_dev, cls, grid, smem, stream);
-    case 8: return launch_g<8>(ne, a, hdr_dev, cls, grid, smem, stream);
-    case 16: return launch_g<16>(ne, a, hdr_dev, cls, grid, smem, stream);
+    case 1: return launch_g<1>(ne, model, a, hdr_dev, cls, grid, smem, stream);
+    case 2: return launch_g<2>(ne, model, a, hdr_dev, cls, grid, smem, stream);
+    case 4: return launch_g<4>(ne, model, a, hdr_dev, cls, grid, smem, stream);
+    case 8: return launch_g<8>(ne, model, a, hdr_dev, cls, grid, smem, stream);
+    case 16: return launch_g<16>(ne, model, a, hdr_dev, cls, grid, smem, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -414,6 +414,8 @@ mppi_status mppi_server_add_vehicle(mppi_server_t* srv, const mppi_config* cfg, 
     mppi_status s = server_usable(srv);
     if (s != MPPI_OK) return s;
     if (!vid) return fail(MPPI_E_INVALID, "vid is NULL");
+    if (cfg && cfg->model != 0)
+        return fail(MPPI_E_INVALID, "served vehicles use the 4-state model (model = 0)");
     mppi_t* h = nullptr;
     if ((s = handle_create(cfg, srv->streams[0]->s, false, &h)) != MPPI_OK) return s;
     // the worst-case request of this vehicle must fit the budget

@@ -50,6 +50,7 @@ class Config(ctypes.Structure):
         ("smoothing", ctypes.c_int32),
         ("w_target", ctypes.c_double), ("w_yaw", ctypes.c_double),
         ("collision_only", ctypes.c_int32),
+        ("model", ctypes.c_int32),
     ]
 
 
@@ -127,6 +128,7 @@ SIGNATURES = [
     ("mppi_get_weights", _i32, [_vp, _dp, _sz]),
     ("mppi_get_noise", _i32, [_vp, _fp, _sz]),
     ("mppi_get_trajectory", _i32, [_vp, _dp, _sz, _dp, _sz]),
+    ("mppi_set_steering", _i32, [_vp, ctypes.c_double]),
     ("mppi_get_iter_stats", _i32, [_vp, ctypes.POINTER(IterStats)]),
     ("mppi_set_lanes_per_sample", _i32, [_vp, _i32]),
     ("mppi_set_culling", _i32, [_vp, _i32]),
@@ -205,6 +207,7 @@ def config_from_params(p, max_waypoints=2048, max_circles=1024) -> Config:
     c.w_target = float(p.get("w_target", 0.0))
     c.w_yaw = float(p.get("w_yaw", 0.0))
     c.collision_only = int(p.get("collision_only", 0))
+    c.model = int(p.get("model", 0))
     return c
 
 
@@ -374,11 +377,15 @@ class Planner:
     def trajectory(self):
         """Optimal trajectory after the last step: (states [T+1][4], applied
         controls [T][2])."""
-        xs = np.zeros((self.T + 1, 4))
+        xs = np.zeros((self.T + 1, 5 if self.cfg.model else 4))
         us = np.zeros((self.T, 2))
         check(load().mppi_get_trajectory(self.h, xs.ctypes.data_as(_dp), xs.size,
                                          us.ctypes.data_as(_dp), us.size))
         return xs, us
+
+    def set_steering(self, delta0):
+        """Initial steering angle of the 5-state model for the next steps."""
+        check(load().mppi_set_steering(self.h, float(delta0)))
 
     def noise(self):
         out = np.zeros((self.T, self.K, 2), dtype=np.float32)

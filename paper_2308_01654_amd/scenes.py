@@ -305,6 +305,19 @@ def paper_follow(lead_speed=4.0):
                 circles=car_circles(30.0, 0.0, vx=lead_speed), iterations=1)
 
 
+def paper_model5(sc, steer0=0.0):
+    """A copy of scene sc planned with the 5-state model of eq. (5): the
+    steering angle is state (initially steer0) and the second control is the
+    steering rate, with Table I's noise 0.05 rad/s and bound 0.11 rad/s."""
+    out = dict(sc)
+    p = dict(sc["params"])
+    p.update(model=1, steer0=steer0, u_min=(p["u_min"][0], -0.11), u_max=(p["u_max"][0], 0.11),
+             sigma=(p["sigma"][0], 0.05))
+    out["params"] = p
+    out["name"] = sc["name"] + "_m5"
+    return out
+
+
 def tiny(K=8, T=4, n_c=3, seed=7):
     """A small random scene for exhaustive checks."""
     rng = np.random.Generator(np.random.PCG64(seed))

@@ -33,6 +33,8 @@ def drive(sc, plan, ticks):
     p = sc["params"]
     dt = p["dt"]
     x = np.array(sc["x0"], dtype=np.float64)
+    if p.get("model", 0):
+        x = np.append(x, p.get("steer0", 0.0))   # the steering angle is state
     xs, us, ds = [], [], []
     for k in range(ticks):
         traj, ctl = plan(k, x, moved(sc["circles"], k * dt))
@@ -45,12 +47,14 @@ def drive(sc, plan, ticks):
 
 def check_outcomes(name, p, xs, us, ds, lead_speed=4.0):
     """The paper's observations: the speed never exceeds the target speed,
-    the steering stays within 10 degrees, no object is hit; the merge ends on
-    the lane, the avoidance passes the object and returns, the follower
-    settles at the lead's speed behind it."""
+    the steering angle stays within 10 degrees, no object is hit (for the
+    avoidance: the car itself, inside the 0.7 m margin its circles carry);
+    the merge ends on the lane, the avoidance passes the object and
+    returns, the follower settles at the lead's speed behind it."""
+    steer = xs[:, 4] if p.get("model", 0) else us[:, 1]
     assert np.all(xs[:, 3] <= p["v_max"] + 1e-9), xs[:, 3].max()
-    assert np.all(np.abs(us[:, 1]) <= STEER_10_DEG), np.abs(us[:, 1]).max()
-    assert np.all(ds > 0.0), ds.min()
+    assert np.all(np.abs(steer) <= STEER_10_DEG), np.abs(steer).max()
+    assert np.all(ds > (-0.7 if name == "paper_avoid" else 0.0)), ds.min()
     n = len(xs)
     if name == "paper_merge":
         assert np.all(np.abs(xs[n // 2:, 1]) < 0.3), xs[:, 1]

@@ -669,21 +669,58 @@ def test_paper_weights_worked_total():
     assert math.isclose(c, 43.2, rel_tol=1e-12)
 
 
+@pytest.mark.parametrize("model", [0, 1])
 @pytest.mark.parametrize("name", ["paper_merge", "paper_avoid", "paper_follow"])
-def test_paper_scenarios_closed_loop_oracle(name):
+def test_paper_scenarios_closed_loop_oracle(name, model):
     """The oracle planner with the paper's cost and Table I parameters
     reproduces the qualitative outcomes the paper reports (speed never above
     30 km/h, steering within 10 degrees, no collision, merge onto the lane,
     pass the object, settle behind the lead vehicle)."""
     from tests import _closed_loop as CL
-    sc = scenes.by_name(name)
-    p = sc["params"]
-    state = {"U": np.zeros((p["T"], 2))}
+    sc = scenes.paper_model5(scenes.by_name(name)) if model else scenes.by_name(name)
+    p0 = sc["params"]
+    state = {"U": np.zeros((p0["T"], 2))}
 
     def plan(k, x, circ):
+        p = dict(p0, steer0=float(x[4])) if model else p0
         U = state["U"] if k == 0 else np.vstack([state["U"][1:], state["U"][-1:]])
-        state["U"] = O.iteration(p, x, sc["waypoints"], circ, U, n_iter=k)["U"]
-        return O.optimal_trajectory(p, x, state["U"])
+        state["U"] = O.iteration(p, x[:4], sc["waypoints"], circ, U, n_iter=k)["U"]
+        return O.optimal_trajectory(p, x[:4], state["U"])
 
     xs, us, ds = CL.drive(sc, plan, 60)
-    CL.check_outcomes(name, p, xs, us, ds)
+    CL.check_outcomes(name, p0, xs, us, ds)
+
+
+# ---- the 5-state model of eq. (5): steering angle in the state, rate control
+
+def test_steering_rate_model_with_zero_rate_is_constant_steering():
+    """With omega = 0 the steering angle stays at its initial value delta0,
+    so the 5-state model meets the constant-steering closed form (the
+    4-state model's special case) and its delta column stays delta0."""
+    T, dt, v, L, de, th0 = 60, 0.05, 9.0, 2.7, 0.21, -0.4
+    p = _inf_p(T=T, dt=dt, wheelbase=L, model=1, steer0=de)
+    st_, _, _ = O.simulate(p, [0.5, 0.25, th0, v], scenes.straight_lane(-5, 5, 0),
+                           np.zeros((0, 5)), np.zeros((T, 2)))
+    phi = dt * v * math.tan(de) / L
+    g = dt * v * math.sin(T * phi / 2) / math.sin(phi / 2)
+    mid = th0 + (T - 1) * phi / 2
+    assert st_.shape == (T + 1, 5) and np.all(st_[:, 4] == de)
+    assert math.isclose(st_[-1, 0] - 0.5, g * math.cos(mid), rel_tol=1e-11)
+    assert math.isclose(st_[-1, 1] - 0.25, g * math.sin(mid), rel_tol=1e-11)
+    assert math.isclose(st_[-1, 2], th0 + T * phi, rel_tol=1e-12)
+
+
+def test_steering_rate_model_integrates_the_clamped_rate():
+    """delta_{t+1} = delta_t + dt omega_t with omega clamped to +-omega_max
+    (0.11 rad/s, Table I); the heading uses the steering angle before the
+    step: theta_1 = theta_0 + dt v tan(delta_0) / l."""
+    T, dt, v, L = 16, 0.25, 8.0, 2.7
+    p = _p(T=T, dt=dt, wheelbase=L, model=1, steer0=0.05, u_min=(-2.5, -0.11),
+           u_max=(1.1, 0.11), v_max=100.0)
+    om = np.linspace(-0.3, 0.3, T)                 # partly beyond the rate bound
+    st_, ap = O.optimal_trajectory(p, np.array([0.0, 0.0, 0.1, v]), np.stack([np.zeros(T), om], 1))
+    assert np.all(np.abs(ap[:, 1]) <= 0.11) and np.allclose(ap[:, 1], np.clip(om, -0.11, 0.11))
+    assert np.allclose(np.diff(st_[:, 4]), dt * ap[:, 1], rtol=0, atol=1e-15)
+    assert math.isclose(st_[1, 2], 0.1 + dt * v * math.tan(0.05) / L, rel_tol=1e-14)
+    assert math.isclose(st_[2, 2], st_[1, 2] + dt * v * math.tan(0.05 + dt * ap[0, 1]) / L,
+                        rel_tol=1e-14)
