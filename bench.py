@@ -192,11 +192,13 @@ def alg1_output(p, x0, wp, circ, warmup, steps):
 
 def paper_cost_kernels(steps=50):
     """Iteration kernel time (HIP events, tuned launch shape) of the paper's
-    full-cost scenarios at the Table I shape (K=2560, T=16, dt=0.25)."""
+    full-cost scenarios at the Table I shape (K=2560, T=16, dt=0.25), with
+    the 4-state model and with the 5-state model of eq. (5)."""
     from paper_2308_01654_amd import mppi, scenes
     out = {}
-    for f in (scenes.paper_merge, scenes.paper_avoid, scenes.paper_follow):
-        sc = f()
+    cases = [f() for f in (scenes.paper_merge, scenes.paper_avoid, scenes.paper_follow)]
+    cases += [scenes.paper_model5(sc) for sc in list(cases)]
+    for sc in cases:
         pl = mppi.Planner(sc["params"])
         pl.set_scene(sc["x0"], sc["waypoints"], sc["circles"])
         for _ in range(5):
