@@ -61,6 +61,10 @@
  *     control is the steering rate omega, clamped to [u_min, u_max] of that
  *     control (+-omega_max) by the noise check; explicit Euler from the old
  *     state: theta' = theta + dt v tan(delta) / l, delta' = delta + dt omega.
+ *   - per-step weights (cfg.per_step = 1): the update of U_t weights the
+ *     samples by their cost-to-go S_{t,k} = sum_{s >= t} q_{s,k} (the
+ *     eq. (update-input) form with S indexed by t), with its own minimum
+ *     per t; the default uses one total per sample (S_{0,k}) for every t.
  *   - the other Sec. IV-C terms (zero weight unless configured):
  *     c_target = 1 when the step ends farther from the target point T_P
  *     than it started (squared distances compared), T_P being the last
@@ -105,6 +109,7 @@ typedef struct orc_cfg {
     int32_t collision_only; /* 1: c_safe_dist only when an object is hit */
     int32_t model;      /* 0: 4-state, steering-angle control; 1: eq. (5) 5-state */
     double steer0;      /* initial steering angle of the 5-state model */
+    int32_t per_step;   /* 1: weights per step from the cost-to-go S_t,k */
 } orc_cfg;
 
 enum { ORC_OK = 0, ORC_E_INVALID = -1, ORC_E_NONFINITE = -4 };
@@ -312,7 +317,7 @@ static int cfg_ok(const orc_cfg* c, int n_wp, int n_c)
  */
 int orc_rollout(const orc_cfg* c, const double x0[4], const double* wp, int n_wp,
                 const double* circ, int n_c, const double* U, uint64_t n_iter,
-                const double* eps_in, double* S_out, double* eps_out)
+                const double* eps_in, double* S_out, double* eps_out, double* q_out)
 {
     if (!cfg_ok(c, n_wp, n_c)) return ORC_E_INVALID;
     const int K = c->K, T = c->T;
@@ -341,7 +346,9 @@ int orc_rollout(const orc_cfg* c, const double x0[4], const double* wp, int n_wp
             }
             double xn[5];
             orc_dynamics(c, x, u, xn);
-            S += orc_stage_cost(c, wp, n_wp, circ, n_c, xn, Ut, e, t, x, NULL);
+            const double q = orc_stage_cost(c, wp, n_wp, circ, n_c, xn, Ut, e, t, x, NULL);
+            if (q_out) q_out[(size_t)t * K + k] = q;
+            S += q;
             memcpy(x, xn, sizeof x);
         }
         S_out[k] = S;
@@ -493,6 +500,49 @@ void orc_optimal_trajectory(const orc_cfg* c, const double x0[4], const double* 
     }
 }
 
+/* Per-step update: from stage costs q [T][K], the cost-to-go
+ * S_{t,k} = q_{t,k} + S_{t+1,k} (summed from the last step back), then for
+ * every t the weights of S_{t,.} with their own minimum and
+ * U_t += sum_k w_{t,k} eps[t][k].  Optional outputs: S_tk [T][K], w0 [K]
+ * (the weights of t = 0), the minimum and log Z of t = 0.  Fails without
+ * touching U if some t has no finite cost-to-go. */
+int orc_update_per_step(double* U, int T, int K, const double* q, const double* eps,
+                        double lambda, double* S_tk, double* w0, double* s_min, double* log_z)
+{
+    double* S = S_tk ? S_tk : (double*)malloc((size_t)T * K * sizeof(double));
+    double* w = (double*)malloc((size_t)T * K * sizeof(double));
+    double* mins = (double*)malloc((size_t)T * 2 * sizeof(double));
+    int rc = (S && w && mins) ? ORC_OK : ORC_E_INVALID;
+    for (int k = 0; rc == ORC_OK && k < K; ++k) {
+        double acc = 0.0;
+        for (int t = T - 1; t >= 0; --t) {
+            acc += q[(size_t)t * K + k];
+            S[(size_t)t * K + k] = acc;
+        }
+    }
+    for (int t = 0; rc == ORC_OK && t < T; ++t)
+        rc = orc_weights(S + (size_t)t * K, K, lambda, w + (size_t)t * K, mins + 2 * t,
+                         mins + 2 * t + 1);
+    if (rc == ORC_OK) {
+        for (int t = 0; t < T; ++t) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int k = 0; k < K; ++k) {
+                s0 += w[(size_t)t * K + k] * eps[((size_t)t * K + k) * 2 + 0];
+                s1 += w[(size_t)t * K + k] * eps[((size_t)t * K + k) * 2 + 1];
+            }
+            U[2 * t + 0] += s0;
+            U[2 * t + 1] += s1;
+        }
+        if (w0) memcpy(w0, w, (size_t)K * sizeof(double));
+        if (s_min) *s_min = mins[0];
+        if (log_z) *log_z = mins[1];
+    }
+    if (!S_tk) free(S);
+    free(w);
+    free(mins);
+    return rc;
+}
+
 /* One full iteration; U is updated in place only on success.
  * Optional outputs: S[K], w[K], eps[T][K][2]. */
 int orc_iteration(const orc_cfg* c, const double x0[4], const double* wp, int n_wp,
@@ -504,10 +554,16 @@ int orc_iteration(const orc_cfg* c, const double x0[4], const double* wp, int n_
     double* S = S_out ? S_out : (double*)malloc(K * sizeof(double));
     double* w = w_out ? w_out : (double*)malloc(K * sizeof(double));
     double* e = eps_out ? eps_out : (double*)malloc(T * K * 2 * sizeof(double));
-    int rc = (S && w && e) ? ORC_OK : ORC_E_INVALID;
-    if (rc == ORC_OK) rc = orc_rollout(c, x0, wp, n_wp, circ, n_c, U, n_iter, NULL, S, e);
-    if (rc == ORC_OK) rc = orc_weights(S, c->K, c->lambda, w, s_min, log_z);
-    if (rc == ORC_OK) orc_update(U, c->T, c->K, w, e);
+    double* q = c->per_step ? (double*)malloc(T * K * sizeof(double)) : NULL;
+    int rc = (S && w && e && (q || !c->per_step)) ? ORC_OK : ORC_E_INVALID;
+    if (rc == ORC_OK) rc = orc_rollout(c, x0, wp, n_wp, circ, n_c, U, n_iter, NULL, S, e, q);
+    if (rc == ORC_OK && c->per_step) {
+        rc = orc_update_per_step(U, c->T, c->K, q, e, c->lambda, NULL, w, s_min, log_z);
+    } else {
+        if (rc == ORC_OK) rc = orc_weights(S, c->K, c->lambda, w, s_min, log_z);
+        if (rc == ORC_OK) orc_update(U, c->T, c->K, w, e);
+    }
+    free(q);
     if (rc == ORC_OK && c->smoothing) {
         double* sm = (double*)malloc(T * 2 * sizeof(double));
         if (!sm) {

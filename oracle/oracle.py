@@ -47,6 +47,7 @@ class OrcCfg(ctypes.Structure):
         ("w_target", ctypes.c_double), ("w_yaw", ctypes.c_double),
         ("collision_only", ctypes.c_int32),
         ("model", ctypes.c_int32), ("steer0", ctypes.c_double),
+        ("per_step", ctypes.c_int32),
     ]
 
 
@@ -82,7 +83,9 @@ def lib():
                                          ctypes.c_int, dp, dp]
             L.orc_stage_cost.restype = ctypes.c_double
             L.orc_rollout.argtypes = [cp, dp, dp, ctypes.c_int, dp, ctypes.c_int, dp,
-                                      ctypes.c_uint64, dp, dp, dp]
+                                      ctypes.c_uint64, dp, dp, dp, dp]
+            L.orc_update_per_step.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, dp,
+                                              ctypes.c_double, dp, dp, dp, dp]
             L.orc_rollout_samples.argtypes = [cp, dp, dp, ctypes.c_int, dp, ctypes.c_int, dp,
                                               ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32),
                                               ctypes.c_int, dp, dp, dp]
@@ -135,6 +138,7 @@ def make_cfg(p) -> OrcCfg:
     c.collision_only = int(p.get("collision_only", 0))
     c.model = int(p.get("model", 0))
     c.steer0 = float(p.get("steer0", 0.0))
+    c.per_step = int(p.get("per_step", 0))
     return c
 
 
@@ -234,8 +238,9 @@ def simulate(p, x0, waypoints, circles, U, eps=None):
     return states, costs, parts
 
 
-def rollout(p, x0, waypoints, circles, U, n_iter=0, eps_in=None):
-    """All K rollouts.  Returns (S [K], eps_eff [T][K][2])."""
+def rollout(p, x0, waypoints, circles, U, n_iter=0, eps_in=None, stage_costs=False):
+    """All K rollouts.  Returns (S [K], eps_eff [T][K][2]) and, with
+    stage_costs, the per-step costs q [T][K] as a third element."""
     c = make_cfg(p)
     K, T = c.K, c.T
     wp = _f64(waypoints, (-1, 4))
@@ -245,11 +250,12 @@ def rollout(p, x0, waypoints, circles, U, n_iter=0, eps_in=None):
     ein = None if eps_in is None else _f64(eps_in, (T, K, 2))
     S = np.zeros(K)
     eps = np.zeros((T, K, 2))
+    q = np.zeros((T, K)) if stage_costs else None
     rc = lib().orc_rollout(ctypes.byref(c), _dp(x0), _dp(wp), wp.shape[0], _dp(ci), ci.shape[0],
-                           _dp(U), int(n_iter), _dp(ein), _dp(S), _dp(eps))
+                           _dp(U), int(n_iter), _dp(ein), _dp(S), _dp(eps), _dp(q))
     if rc != OK:
         raise ValueError("orc_rollout: status %d" % rc)
-    return S, eps
+    return (S, eps, q) if stage_costs else (S, eps)
 
 
 def rollout_samples(p, x0, waypoints, circles, U, ks, n_iter=0, eps_in=None):
@@ -341,3 +347,25 @@ def optimal_trajectory(p, x0, Us):
     applied = np.zeros((c.T, 2))
     lib().orc_optimal_trajectory(ctypes.byref(c), _dp(x0), _dp(Us), _dp(states), _dp(applied))
     return states, applied
+
+
+def update_per_step(U, q, eps, lam):
+    """Per-step update from stage costs q [T][K] and applied perturbations
+    eps [T][K][2]: returns (U_new, S_tk [T][K] cost-to-go, w0 [K] weights of
+    t = 0).  Raises when some step has no finite cost-to-go."""
+    U = _f64(U).copy()
+    T = U.shape[0]
+    q = _f64(q).reshape(T, -1)
+    K = q.shape[1]
+    eps = _f64(eps, (T, K, 2))
+    S = np.zeros((T, K))
+    w0 = np.zeros(K)
+    smin = ctypes.c_double()
+    logz = ctypes.c_double()
+    rc = lib().orc_update_per_step(_dp(U), T, K, _dp(q), _dp(eps), float(lam), _dp(S), _dp(w0),
+                                   ctypes.byref(smin), ctypes.byref(logz))
+    if rc == E_NONFINITE:
+        raise FloatingPointError("a step has no finite cost-to-go")
+    if rc != OK:
+        raise ValueError("orc_update_per_step: status %d" % rc)
+    return U, S, w0

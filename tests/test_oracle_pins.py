@@ -724,3 +724,67 @@ def test_steering_rate_model_integrates_the_clamped_rate():
     assert math.isclose(st_[1, 2], 0.1 + dt * v * math.tan(0.05) / L, rel_tol=1e-14)
     assert math.isclose(st_[2, 2], st_[1, 2] + dt * v * math.tan(0.05 + dt * ap[0, 1]) / L,
                         rel_tol=1e-14)
+
+
+# ---- per-step weights: U_t weighted by the cost-to-go S_{t,k}
+
+def test_per_step_weights_with_one_step_equal_total_weights():
+    """With T = 1 the cost-to-go is the total cost: the per-step iteration
+    equals the default one bit for bit."""
+    sc = scenes.tiny(K=300, T=1, n_c=3, seed=4)
+    p = dict(sc["params"])
+    U0 = np.array([[0.3, -0.05]])
+    a = O.iteration(p, sc["x0"], sc["waypoints"], sc["circles"], U0, n_iter=1)
+    p["per_step"] = 1
+    b = O.iteration(p, sc["x0"], sc["waypoints"], sc["circles"], U0, n_iter=1)
+    assert np.array_equal(a["U"], b["U"]) and np.array_equal(a["w"], b["w"])
+
+
+def test_per_step_last_step_uses_only_its_own_cost():
+    """S_{T-1,k} = q_{T-1,k}: the update of the last step is the total-cost
+    update computed from the last stage costs alone (pinned weights and
+    update functions)."""
+    sc = scenes.tiny(K=200, T=7, n_c=4, seed=8)
+    p = dict(sc["params"], lam=3.0)
+    U0 = np.tile([0.1, 0.02], (7, 1))
+    S, eps, q = O.rollout(p, sc["x0"], sc["waypoints"], sc["circles"], U0, n_iter=0,
+                          stage_costs=True)
+    assert np.allclose(q.sum(axis=0), S, rtol=1e-12)
+    Un, Stk, w0 = O.update_per_step(U0, q, eps, p["lam"])
+    w_last, _, _ = O.weights(q[-1], p["lam"])
+    ref = O.update(U0, w_last, eps)
+    assert np.allclose(Un[-1], ref[-1], rtol=0, atol=1e-15)
+    assert np.array_equal(Stk[0], np.sum(q[::-1], axis=0)) or np.allclose(Stk[0], S, rtol=1e-12)
+
+
+def test_per_step_small_lambda_picks_each_steps_argmin():
+    """lambda -> 0: U_t moves by the applied noise of the sample with the
+    smallest cost-to-go at t, and that sample differs between steps."""
+    sc = scenes.tiny(K=64, T=12, n_c=6, seed=13)
+    p = dict(sc["params"])
+    U0 = np.zeros((12, 2))
+    _, eps, q = O.rollout(p, sc["x0"], sc["waypoints"], sc["circles"], U0, n_iter=0,
+                          stage_costs=True)
+    Un, Stk, _ = O.update_per_step(U0, q, eps, 1e-12)
+    arg = np.argmin(Stk, axis=1)
+    assert len(set(arg.tolist())) > 1
+    for t in range(12):
+        assert np.allclose(Un[t], eps[t, arg[t]], rtol=0, atol=1e-12)
+
+
+def test_per_step_update_invariances():
+    """Adding a constant to every sample's cost at one step changes no
+    weight; permuting the samples changes U only by rounding."""
+    rng = np.random.Generator(np.random.PCG64(3))
+    T, K = 9, 50
+    q = rng.uniform(0, 5, (T, K))
+    eps = rng.normal(size=(T, K, 2))
+    U0 = rng.normal(size=(T, 2))
+    Un, _, _ = O.update_per_step(U0, q, eps, 0.7)
+    q2 = q.copy()
+    q2[4] += 123.0
+    Un2, _, _ = O.update_per_step(U0, q2, eps, 0.7)
+    assert np.allclose(Un, Un2, rtol=0, atol=1e-12)
+    perm = rng.permutation(K)
+    Un3, _, _ = O.update_per_step(U0, q[:, perm], eps[:, perm], 0.7)
+    assert np.allclose(Un, Un3, rtol=0, atol=1e-12)
