@@ -101,6 +101,10 @@ typedef struct mppi_config {
                               (sigma[1], u_min[1], u_max[1] then bound omega, e.g.
                               +-omega_max); the initial angle comes from
                               mppi_set_steering.  Served vehicles must use 0.          */
+    int32_t per_step_weights; /* 1: the update of U_t weights the samples by their
+                              cost-to-go from t, S_t,k = sum_{s>=t} q_s,k, with a
+                              minimum per t (eq. (update-input) indexed by t); 0: one
+                              total cost per sample for every t                        */
 } mppi_config;
 
 /* Scene and road model of one request, world coordinates. */
@@ -199,11 +203,17 @@ mppi_status mppi_get_state(mppi_t* h, double* U, size_t n, uint64_t* n_iter, uin
 mppi_status mppi_set_state(mppi_t* h, const double* U, size_t n, uint64_t n_iter);
 
 /* Results of the last step (synchronize).  Costs S_k as float32 [K];
- * normalised weights as float64 [K]; applied perturbations eps_eff as
- * float32 [T][K][2]; summary statistics. */
+ * normalised weights as float64 [K] (with per-step weights: those of step 0,
+ * formed from the float64 cost-to-go S_0,k); applied perturbations eps_eff
+ * as float32 [T][K][2]; summary statistics. */
 mppi_status mppi_get_costs(mppi_t* h, float* out, size_t n);
 mppi_status mppi_get_weights(mppi_t* h, double* out, size_t n);
 mppi_status mppi_get_noise(mppi_t* h, float* out, size_t n);
+
+/* Per-step stage costs of the last step (cfg.per_step_weights = 1 only):
+ * [T][K] float32, q_t,k on the state x_{t+1} of sample k; synchronises.
+ * MPPI_E_INVALID for a short buffer or when per-step weights are off. */
+mppi_status mppi_get_stage_costs(mppi_t* h, float* out, size_t n);
 
 /* Steering angle delta0 [rad] of the next steps' initial state for the
  * 5-state model (cfg.model = 1; ignored otherwise).  Default 0; kept until

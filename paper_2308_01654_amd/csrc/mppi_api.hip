@@ -106,6 +106,8 @@ mppi_status validate_config(const mppi_config* c)
     if (c->collision_only != 0 && c->collision_only != 1)
         return fail(MPPI_E_INVALID, "collision_only must be 0 or 1");
     if (c->model != 0 && c->model != 1) return fail(MPPI_E_INVALID, "model must be 0 or 1");
+    if (c->per_step_weights != 0 && c->per_step_weights != 1)
+        return fail(MPPI_E_INVALID, "per_step_weights must be 0 or 1");
     return MPPI_OK;
 }
 
@@ -296,6 +298,8 @@ void handle_release(mppi_t* h)
     (void)hipFree(h->S);
     (void)hipFree(h->eps);
     (void)hipFree(h->partials);
+    (void)hipFree(h->q);
+    (void)hipFree(h->Stk);
     (void)hipFree(h->wbuf);
     (void)hipFree(h->traj);
     (void)hipFree(h->st);
@@ -346,12 +350,17 @@ mppi_status handle_create(const mppi_config* cfg, void* hip_stream, bool with_sc
         struct { void** p; size_t n; } allocs[] = {
             {(void**)&h->S, sizeof(float) * K},
             {(void**)&h->eps, sizeof(float2) * (size_t)T * K},
-            {(void**)&h->partials, sizeof(double) * (size_t)h->max_tiles * (kPartialHead + 2 * T)},
+            {(void**)&h->partials,
+             sizeof(double) * (size_t)h->max_tiles * partial_stride(T, cfg->per_step_weights)},
             {(void**)&h->wbuf, sizeof(double) * (size_t)K},
             {(void**)&h->scene, h->scene_cap},
         };
         for (auto& a : allocs)
             if ((e = hipMalloc(a.p, a.n)) != hipSuccess) return bail(MPPI_E_NOMEM, "hipMalloc", e);
+        if (cfg->per_step_weights &&
+            ((e = hipMalloc((void**)&h->q, sizeof(float) * (size_t)T * K)) != hipSuccess ||
+             (e = hipMalloc((void**)&h->Stk, sizeof(double) * (size_t)T * K)) != hipSuccess))
+            return bail(MPPI_E_NOMEM, "hipMalloc", e);
         for (int i = 0; i < 2; ++i) {
             if ((e = hipHostMalloc((void**)&h->staging[i], h->scene_cap, hipHostMallocDefault)) !=
                 hipSuccess)
@@ -420,6 +429,7 @@ void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double or
     d.w_yaw = (float)c.w_yaw;
     d.coll_only = c.collision_only;
     d.model = c.model;
+    d.per_step = c.per_step_weights;
     d.steer0 = (float)h->steer0;
     d.ego_ext = 0.f;
     for (int e = 0; e < c.n_ego; ++e) d.ego_ext = fmaxf(d.ego_ext, (float)fabs(c.ego_off[e]));
@@ -433,6 +443,8 @@ void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double or
     d.S = h->S;
     d.eps = h->eps;
     d.partials = h->partials;
+    d.q = h->q;
+    d.Stk = h->Stk;
     d.st = h->st;
 }
 
@@ -556,7 +568,7 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
     InstDesc* descs = reinterpret_cast<InstDesc*>(host + off_descs);
     long total = 0;
     size_t smem = 0;
-    int any_shift = 0, any_out = 0;
+    int any_shift = 0, any_out = 0, any_per_step = 0;
     for (int j = 0; j < n; ++j) {
         const int i = order[j];
         mppi_t* hi = hs[i];
@@ -575,6 +587,8 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
             descs[j].S = ex->S;
             descs[j].eps = ex->eps;
             descs[j].partials = ex->partials;
+            descs[j].q = ex->q;
+            descs[j].Stk = ex->Stk;
             descs[j].out_slot = ex->out_slot;
             any_out |= ex->out_slot >= 0;
         }
@@ -583,6 +597,7 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
         smem = std::max(smem, lds_layout(descs[j].n_wp, descs[j].n_c, descs[j].T,
                                          kBlock / descs[j].lanes).total);
         any_shift |= sh;
+        any_per_step |= descs[j].per_step;
     }
     if (total > (1L << 30)) return fail(MPPI_E_INVALID, "batch too large");
     prefix[n] = (int)total;
@@ -605,6 +620,7 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
     const int n_blocks = (int)pow2_at_least((size_t)n, 1);
     const int shift_blocks = any_shift ? n_blocks : 0;
     const int gather_blocks = (gather_dev && any_out) ? n_blocks : 0;
+    const int merge_blocks = any_per_step ? n_blocks : 0;
     static const int kClassLanes[5] = {1, 2, 4, 8, 16};
     auto enqueue_device_work = [&](size_t copy_bytes) -> hipError_t {
         hipError_t e = hipMemcpyAsync(ws->arena, host, copy_bytes, hipMemcpyHostToDevice, stream);
@@ -613,6 +629,8 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
             if (grids[c] > 0)
                 e = launch_batch(kClassLanes[(c % 25) / 5], c % 5, c / 25, nullptr, hdr_dev, c,
                                  grids[c], smem_b, stream);
+        if (e == hipSuccess && merge_blocks)
+            e = launch_merge_per_step(nullptr, hdr_dev, merge_blocks, stream);
         if (e == hipSuccess && gather_blocks)
             e = launch_gather(hdr_dev, gather_blocks, gather_dev, slot_doubles, stream);
         return e;
@@ -625,7 +643,8 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
         GraphEntry* ge = nullptr;
         for (GraphEntry& g : ws->graphs)
             if (g.bytes == bucket && g.smem == smem_b && g.buf == b &&
-                g.shift_blocks == shift_blocks + 4096 * gather_blocks &&
+                g.shift_blocks == shift_blocks && g.gather_blocks == gather_blocks &&
+                g.merge_blocks == merge_blocks &&
                 memcmp(g.grids, grids, sizeof grids) == 0)
                 ge = &g;
         if (!ge) {
@@ -639,7 +658,9 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
             g.smem = smem_b;
             memcpy(g.grids, grids, sizeof grids);
             g.buf = b;
-            g.shift_blocks = shift_blocks + 4096 * gather_blocks;
+            g.shift_blocks = shift_blocks;
+            g.gather_blocks = gather_blocks;
+            g.merge_blocks = merge_blocks;
             g.graph = nullptr;
             g.exec = nullptr;
             HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
@@ -748,6 +769,7 @@ mppi_status mppi_step_resident(mppi_t* h, const double x0[4])
     if ((s = record_launch(h, 0, &a)) != MPPI_OK) return s;
     HIP_TRY(launch_batch(d.lanes, active_ego(d.n_ego, d.n_c), d.model, &d, nullptr, 0, d.n_tiles,
                          smem, h->stream));
+    if (d.per_step) HIP_TRY(launch_merge_per_step(&d, nullptr, 1, h->stream));
     if ((s = record_end(h, 0, a)) != MPPI_OK) return s;
     h->last_lanes = d.lanes;
     h->stepped = true;
@@ -879,6 +901,8 @@ mppi_status mppi_get_weights(mppi_t* h, double* out, size_t n)
     memset(&d, 0, sizeof d);
     d.K = h->cfg.K;
     d.S = h->S;
+    d.per_step = h->cfg.per_step_weights;
+    d.Stk = h->Stk;
     d.lambda = h->cfg.lambda;
     d.st = h->st;
     s = launch_aux(h, [&] { return launch_weights(d, h->wbuf, h->stream); });
@@ -932,6 +956,19 @@ mppi_status mppi_get_trajectory(mppi_t* h, double* states, size_t n_states, doub
         HIP_TRY(hipMemcpy(states, xs, sizeof(double) * cols * (T + 1), hipMemcpyDeviceToHost));
     if (controls)
         HIP_TRY(hipMemcpy(controls, us, sizeof(double) * 2 * T, hipMemcpyDeviceToHost));
+    return MPPI_OK;
+}
+
+mppi_status mppi_get_stage_costs(mppi_t* h, float* out, size_t n)
+{
+    mppi_status s = usable(h);
+    if (s != MPPI_OK) return s;
+    if (!h->cfg.per_step_weights || !h->q)
+        return fail(MPPI_E_INVALID, "stage costs are kept only with per-step weights");
+    const size_t need = (size_t)h->cfg.T * h->cfg.K;
+    if (!out || n < need) return fail(MPPI_E_INVALID, "buffer needs T*K floats");
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    HIP_TRY(hipMemcpy(out, h->q, sizeof(float) * need, hipMemcpyDeviceToHost));
     return MPPI_OK;
 }
 

@@ -20,7 +20,7 @@ mppi_status fail(mppi_status s, const char* fmt, ...) __attribute__((format(prin
 struct GraphEntry {
     size_t bytes, smem;
     int grids[kLaneClasses];
-    int buf, shift_blocks;
+    int buf, shift_blocks, gather_blocks, merge_blocks;
     hipGraph_t graph;
     hipGraphExec_t exec;
 };
@@ -54,6 +54,8 @@ struct InstExtra {
     float* S;
     float2* eps;
     double* partials;
+    float* q;
+    double* Stk;
     int shift;
     int out_slot;
 };
@@ -74,6 +76,8 @@ struct mppi {
     float* S = nullptr;
     float2* eps = nullptr;
     double* partials = nullptr;
+    float* q = nullptr;      // [T][K] stage costs (per-step weights)
+    double* Stk = nullptr;   // [T][K] cost-to-go (per-step weights)
     double* wbuf = nullptr;  // [K] weights export
     double* traj = nullptr;  // optimal trajectory: states [T+1][4], controls [T][2]
     mppi_impl::DevState* st = nullptr;

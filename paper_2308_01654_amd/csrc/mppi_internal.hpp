@@ -33,6 +33,14 @@ struct DevState {
 //   [0] m_b  [1] Z_b  [2] Q_b (sum of squares)  [3] unused  [4 + 2t + d] N_b
 constexpr int kPartialHead = 4;
 
+// With per-step weights a partial row holds, for every step t, the tile
+// minimum of the cost-to-go, the shifted exponential sums and the two
+// weighted perturbation sums ([5t .. 5t+4]), then 2T doubles of staging.
+inline __host__ __device__ int partial_stride(int T, int per_step)
+{
+    return per_step ? 7 * T : kPartialHead + 2 * T;
+}
+
 // Tile partials are merged by a tree of fixed shape: a node of level l + 1
 // merges up to kFanIn consecutive nodes of level l, and the root merges the
 // last level that has at most kFanIn nodes.  Each non-root group has a
@@ -72,6 +80,7 @@ struct InstDesc {
     int smooth;           // end with the Savitzky-Golay filter of eq. (sg)
     float w_target, w_yaw;// weights of c_target and c_yaw (0: term skipped)
     int coll_only;        // c_safe_dist only when d_obj <= 0
+    int per_step;         // 1: weights from the cost-to-go per step
     int model;            // 1: 5-state model of eq. (5), steering-rate control
     float steer0;         // its initial steering angle
     float ego_ext;        // max |ego_off|
@@ -85,7 +94,9 @@ struct InstDesc {
     double* U;            // [T][2]
     float* S;             // [K]
     float2* eps;          // [T][K]
-    double* partials;     // [n_tiles][kPartialHead + 2T]
+    double* partials;     // [n_tiles][partial_stride(T, per_step)]
+    float* q;             // [T][K] stage costs (per-step weights)
+    double* Stk;          // [T][K] cost-to-go (per-step weights)
     DevState* st;         // followed by the combine-tree tickets
 };
 
@@ -143,6 +154,11 @@ inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int sp
 hipError_t launch_batch(int lanes, int ne, int model, const InstDesc* d0,
                         const BatchHdr* hdr_dev, int cls, int grid, size_t smem,
                         hipStream_t stream);
+
+// Per-step weights: merge of the tile rows of one instance (d0, hdr_dev ==
+// nullptr) or of every per-step instance of a batch (n_blocks = n_inst).
+hipError_t launch_merge_per_step(const InstDesc* d0, const BatchHdr* hdr_dev, int n_blocks,
+                                 hipStream_t stream);
 
 // Ego circles that take part in the obstacle term of an instance.
 inline int active_ego(int n_ego, int n_c) { return n_c > 0 ? n_ego : 0; }

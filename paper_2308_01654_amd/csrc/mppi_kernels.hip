@@ -574,6 +574,20 @@ __device__ __forceinline__ double block_min(double v, double* red)
 
 // M5: the 5-state model of eq. (5) -- the steering angle is part of the state
 // and the second control is the steering rate.
+// Eq. (sg) on the updated sequence staged at un [T][2], written to U:
+// u*_t = (-3 u_{t-2} + 12 u_{t-1} + 17 u_t + 12 u_{t+1} - 3 u_{t+2}) / 35, the
+// end values repeated beyond the horizon.  The caller synchronises first.
+__device__ __forceinline__ void smooth_into(double* U, const double* un, int T)
+{
+    for (int col = threadIdx.x; col < 2 * T; col += blockDim.x) {
+        const int t = col >> 1, c2 = col & 1;
+        auto at = [&](int i) { return un[2 * min(max(i, 0), T - 1) + c2]; };
+        const double sm = -3.0 * at(t - 2) + 12.0 * at(t - 1) + 17.0 * at(t) +
+                          12.0 * at(t + 1) - 3.0 * at(t + 2);
+        U[col] = sm / 35.0;
+    }
+}
+
 template <int G, int NE, bool M5>
 __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
 {
@@ -728,6 +742,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
                                       min(t0 + G, T) - 1, mth, pxp, pyp);
         else if (act)
             q = stage_cost<NE>(d, s, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm, mth, pxp, pyp);
+        if (act && valid && d.per_step) d.q[(size_t)tm * K + k] = q;
         if (act) {
             const float yk = q - comp;
             const float tk = S + yk;
@@ -746,14 +761,58 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     if (valid && r == 0) d.S[k] = (float)Sd;
 
     // ---------------------------------------------------------------- phase 2
+    const int stride = partial_stride(T, d.per_step);
+    double* part = d.partials + (size_t)tile * stride;
+    const int n_valid = min(SPB, K - k_base);
+    if (d.per_step) {
+        // Per-step weights: the cost-to-go of every sample of the tile,
+        // summed in float64 from the last step back, then per step the tile
+        // minimum, the shifted exponential sums and the weighted
+        // perturbations (one thread per step, samples in index order).
+        __syncthreads();  // the tile's stage costs are stored
+        for (int j = tid; j < n_valid; j += kBlock) {
+            double acc = 0.0;
+            for (int t = T - 1; t >= 0; --t) {
+                acc += (double)d.q[(size_t)t * K + k_base + j];
+                d.Stk[(size_t)t * K + k_base + j] = acc;
+            }
+        }
+        __syncthreads();
+        for (int t = tid; t < T; t += kBlock) {
+            const double* St = d.Stk + (size_t)t * K + k_base;
+            const float2* e = d.eps + (size_t)t * K + k_base;
+            double m = INFINITY;
+            for (int j = 0; j < n_valid; ++j) {
+                const double v = St[j];
+                if (isfinite(v) && v < m) m = v;
+            }
+            double z = 0.0, qq = 0.0, na = 0.0, nd = 0.0;
+            if (isfinite(m)) {
+#pragma unroll 1
+                for (int j = 0; j < n_valid; ++j) {
+                    const double v = St[j];
+                    const double om = isfinite(v) ? exp(-(v - m) / d.lambda) : 0.0;
+                    const float2 ev = e[j];
+                    z += om;
+                    qq += om * om;
+                    na += om * (double)ev.x;
+                    nd += om * (double)ev.y;
+                }
+            }
+            double* o = part + 5 * t;
+            o[0] = m;
+            o[1] = z;
+            o[2] = qq;
+            o[3] = na;
+            o[4] = nd;
+        }
+    } else {
     const double m_b = block_min((double)Sk, s.red);
     double om = 0.0;
     if (r == 0 && isfinite(m_b) && Sk < INFINITY) om = exp(-((double)Sk - m_b) / d.lambda);
     if (r == 0) s.omega[grp] = (float)om;
     const double z_b = block_sum(om, s.red);
     const double q_b = block_sum(om * om, s.red);  // also orders omega stores
-    double* part = d.partials + (size_t)tile * (kPartialHead + 2 * T);
-    const int n_valid = min(SPB, K - k_base);
     for (int col = tid; col < 2 * T; col += kBlock) {
         const int t = col >> 1;
         const float* e = reinterpret_cast<const float*>(d.eps + (size_t)t * K + k_base) + (col & 1);
@@ -781,12 +840,16 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         part[2] = q_b;
         part[3] = 0.0;
     }
+    }
 
     // ---------------------------------------------------------------- phase 3
+    // Per-step weights: the tile rows are merged by k_merge_per_step, which
+    // runs after this kernel.
+    if (d.per_step) return;
     // Merge the tile partials up the combine tree.  A node's row is the row
     // of its first tile; children are merged in index order with the
-    // log-sum-exp shift to their common minimum.
-    const int stride = kPartialHead + 2 * T;
+    // log-sum-exp shift to their common minimum (per step with per-step
+    // weights).
     // first ticket on the 128-byte line after the state
     unsigned int* tickets = reinterpret_cast<unsigned int*>(
         (reinterpret_cast<uintptr_t>(d.st + 1) + 4 * kTicketStride - 1) & ~(uintptr_t)(4 * kTicketStride - 1));
@@ -867,17 +930,8 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         }
         if (root) {
             if (d.smooth) {
-                // eq. (sg): u*_t = (-3 u_{t-2} + 12 u_{t-1} + 17 u_t + 12 u_{t+1}
-                // - 3 u_{t+2}) / 35, the end values repeated beyond the horizon
                 __syncthreads();
-                const double* un = rows + kPartialHead;
-                for (int col = tid; col < 2 * T; col += kBlock) {
-                    const int t = col >> 1, c2 = col & 1;
-                    auto at = [&](int i) { return un[2 * min(max(i, 0), T - 1) + c2]; };
-                    const double sm = -3.0 * at(t - 2) + 12.0 * at(t - 1) + 17.0 * at(t) +
-                                      12.0 * at(t + 1) - 3.0 * at(t + 2);
-                    d.U[col] = sm / 35.0;
-                }
+                smooth_into(d.U, rows + kPartialHead, T);
             }
             if (tid == 0) {
                 d.st->s_min = mm;
@@ -899,6 +953,100 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         idx = g;
         span *= kFanIn;
     }
+}
+
+// Per-step weights: merges every tile row of one instance in tile order (one
+// workgroup, one thread per step): per step the smallest cost-to-go over the
+// tiles, each tile's sums shifted to it by exp(-(m_b - m)/lambda), then
+// U_t += N_t / Z_t (smoothed when configured) and the statistics of t = 0.
+// No step is updated unless every step has a finite cost-to-go.
+__device__ void merge_per_step(const InstDesc& d)
+{
+    const int T = d.T;
+    const size_t stride = partial_stride(T, 1);
+    double* rows = d.partials;
+    bool bad = false;
+    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+        double mm = INFINITY;
+        for (int b = 0; b < d.n_tiles; ++b) {
+            const double mb = rows[(size_t)b * stride + 5 * t];
+            if (mb < mm) mm = mb;
+        }
+        double zz = 0.0, qq = 0.0, na = 0.0, nd = 0.0;
+        if (isfinite(mm)) {
+            for (int b = 0; b < d.n_tiles; ++b) {
+                const double* h = rows + (size_t)b * stride + 5 * t;
+                const double sc = isfinite(h[0]) ? exp(-(h[0] - mm) / d.lambda) : 0.0;
+                zz += h[1] * sc;
+                qq += h[2] * sc * sc;
+                na += h[3] * sc;
+                nd += h[4] * sc;
+            }
+        } else {
+            bad = true;
+        }
+        double* o = rows + 5 * t;  // tile 0's row, at the steps this thread read
+        o[0] = mm;
+        o[1] = zz;
+        o[2] = qq;
+        o[3] = na;
+        o[4] = nd;
+    }
+    if (__syncthreads_or(bad)) {
+        if (threadIdx.x == 0) d.st->status = -4;  // MPPI_E_NONFINITE: U and n unchanged
+        return;
+    }
+    double* stage = rows + 5 * (size_t)T;  // 2T doubles
+    for (int t = threadIdx.x; t < T; t += blockDim.x) {
+        const double* o = rows + 5 * t;
+        const double ua = d.U[2 * t] + o[3] / o[1];
+        const double ud = d.U[2 * t + 1] + o[4] / o[1];
+        if (d.smooth) {
+            stage[2 * t] = ua;
+            stage[2 * t + 1] = ud;
+        } else {
+            d.U[2 * t] = ua;
+            d.U[2 * t + 1] = ud;
+        }
+    }
+    if (d.smooth) {
+        __syncthreads();
+        smooth_into(d.U, stage, T);
+    }
+    if (threadIdx.x == 0) {
+        d.st->s_min = rows[0];
+        d.st->z = rows[1];
+        d.st->log_z = log(rows[1]);
+        d.st->ess = rows[1] * rows[1] / rows[2];
+        d.st->status = 0;
+        d.st->n_iter = d.st->n_iter + 1ull;
+    }
+}
+
+// One instance (d0, hdr == nullptr) or every per-step instance of a batch
+// (one workgroup each).
+__global__ __launch_bounds__(kBlock) void k_merge_per_step(InstDesc d0,
+                                                           const BatchHdr* __restrict__ hdr)
+{
+    if (!hdr) {
+        if (blockIdx.x == 0) merge_per_step(d0);
+        return;
+    }
+    const InstDesc* descs = reinterpret_cast<const InstDesc*>(
+        reinterpret_cast<const unsigned char*>(hdr) + hdr->off_descs);
+    if ((int)blockIdx.x >= hdr->n_inst) return;
+    const InstDesc& d = descs[blockIdx.x];
+    if (d.per_step) merge_per_step(d);
+}
+
+hipError_t launch_merge_per_step(const InstDesc* d0, const BatchHdr* hdr_dev, int n_blocks,
+                                 hipStream_t stream)
+{
+    InstDesc zero;
+    memset(&zero, 0, sizeof zero);
+    hipLaunchKernelGGL(k_merge_per_step, dim3(n_blocks), dim3(kBlock), 0, stream,
+                       d0 ? *d0 : zero, hdr_dev);
+    return hipGetLastError();
 }
 
 // Optimal rollout of Alg. 1 in float64 and world coordinates: from x0,
@@ -1064,14 +1212,16 @@ hipError_t launch_gather(const BatchHdr* hdr_dev, int n_inst, double* out, int s
     return hipGetLastError();
 }
 
-// Normalised weights of the last iteration: w_k = exp(-(S_k - S_min)/lambda)/Z.
-__global__ void k_weights(const float* __restrict__ S, int K, double lambda,
-                          const DevState* __restrict__ st, double* __restrict__ w)
+// Normalised weights of the last iteration: w_k = exp(-(S_k - S_min)/lambda)/Z,
+// from the float32 totals S or, with per-step weights, from the float64
+// cost-to-go of step 0 (S0, the totals those weights were formed from).
+__global__ void k_weights(const float* __restrict__ S, const double* __restrict__ S0, int K,
+                          double lambda, const DevState* __restrict__ st, double* __restrict__ w)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= K) return;
-    const float sk = S[k];
-    w[k] = isfinite(sk) ? exp(-((double)sk - st->s_min) / lambda) / st->z : 0.0;
+    const double sk = S0 ? S0[k] : (double)S[k];
+    w[k] = isfinite(sk) ? exp(-(sk - st->s_min) / lambda) / st->z : 0.0;
 }
 
 hipError_t launch_trajectory(const TrajArgs& a, const double* U, double* states, double* applied,
@@ -1083,8 +1233,8 @@ hipError_t launch_trajectory(const TrajArgs& a, const double* U, double* states,
 
 hipError_t launch_weights(const InstDesc& d, double* w_out, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_weights, dim3((d.K + 255) / 256), dim3(256), 0, stream, d.S, d.K,
-                       d.lambda, d.st, w_out);
+    hipLaunchKernelGGL(k_weights, dim3((d.K + 255) / 256), dim3(256), 0, stream, d.S,
+                       d.per_step ? d.Stk : nullptr, d.K, d.lambda, d.st, w_out);
     return hipGetLastError();
 }
 

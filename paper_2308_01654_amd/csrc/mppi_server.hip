@@ -162,8 +162,11 @@ namespace {
 size_t request_bytes(const mppi_config& c, int lanes)
 {
     const size_t tiles = (size_t)(c.K + (kBlock / lanes) - 1) / (kBlock / lanes);
-    return a256(sizeof(float) * c.K) + a256(sizeof(float2) * (size_t)c.T * c.K) +
-           a256(sizeof(double) * tiles * (kPartialHead + 2 * c.T));
+    size_t b = a256(sizeof(float) * c.K) + a256(sizeof(float2) * (size_t)c.T * c.K) +
+               a256(sizeof(double) * tiles * partial_stride(c.T, c.per_step_weights));
+    if (c.per_step_weights)
+        b += a256(sizeof(float) * (size_t)c.T * c.K) + a256(sizeof(double) * (size_t)c.T * c.K);
+    return b;
 }
 
 void finish_request(mppi_server* srv, Req* r)
@@ -278,6 +281,14 @@ void scheduler_loop(mppi_server* srv)
             ex[i].eps = reinterpret_cast<float2*>(base);
             base += a256(sizeof(float2) * (size_t)c.T * c.K);
             ex[i].partials = reinterpret_cast<double*>(base);
+            base += a256(sizeof(double) * tiles * partial_stride(c.T, c.per_step_weights));
+            ex[i].q = nullptr;
+            ex[i].Stk = nullptr;
+            if (c.per_step_weights) {
+                ex[i].q = reinterpret_cast<float*>(base);
+                base += a256(sizeof(float) * (size_t)c.T * c.K);
+                ex[i].Stk = reinterpret_cast<double*>(base);
+            }
             ex[i].shift = v.admitted > 0 ? 1 : 0;
             ex[i].out_slot = i;
             ++v.admitted;

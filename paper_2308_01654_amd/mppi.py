@@ -51,6 +51,7 @@ class Config(ctypes.Structure):
         ("w_target", ctypes.c_double), ("w_yaw", ctypes.c_double),
         ("collision_only", ctypes.c_int32),
         ("model", ctypes.c_int32),
+        ("per_step_weights", ctypes.c_int32),
     ]
 
 
@@ -129,6 +130,7 @@ SIGNATURES = [
     ("mppi_get_noise", _i32, [_vp, _fp, _sz]),
     ("mppi_get_trajectory", _i32, [_vp, _dp, _sz, _dp, _sz]),
     ("mppi_set_steering", _i32, [_vp, ctypes.c_double]),
+    ("mppi_get_stage_costs", _i32, [_vp, _fp, _sz]),
     ("mppi_get_iter_stats", _i32, [_vp, ctypes.POINTER(IterStats)]),
     ("mppi_set_lanes_per_sample", _i32, [_vp, _i32]),
     ("mppi_set_culling", _i32, [_vp, _i32]),
@@ -208,6 +210,7 @@ def config_from_params(p, max_waypoints=2048, max_circles=1024) -> Config:
     c.w_yaw = float(p.get("w_yaw", 0.0))
     c.collision_only = int(p.get("collision_only", 0))
     c.model = int(p.get("model", 0))
+    c.per_step_weights = int(p.get("per_step", 0))
     return c
 
 
@@ -382,6 +385,12 @@ class Planner:
         check(load().mppi_get_trajectory(self.h, xs.ctypes.data_as(_dp), xs.size,
                                          us.ctypes.data_as(_dp), us.size))
         return xs, us
+
+    def stage_costs(self):
+        """Per-step stage costs [T][K] of the last step (per-step weights)."""
+        out = np.zeros((self.T, self.K), dtype=np.float32)
+        check(load().mppi_get_stage_costs(self.h, out.ctypes.data_as(_fp), out.size))
+        return out
 
     def set_steering(self, delta0):
         """Initial steering angle of the 5-state model for the next steps."""
