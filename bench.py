@@ -161,10 +161,29 @@ def sweep():
             pl.close()
 
 
+def _iteration_ms(p, x0, wp, circ, warmup, steps):
+    """Average device time of one iteration (HIP events around its launches)."""
+    from paper_2308_01654_amd import mppi
+    pl = mppi.Planner(p)
+    pl.set_scene(x0, wp, circ)
+    for _ in range(warmup):
+        pl.step_resident(x0)
+    pl.sync()
+    pl.set_profiling(True)
+    for _ in range(steps):
+        pl.step_resident(x0)
+    pl.sync()
+    prof = pl.profile()
+    pl.close()
+    return round(prof["iter_ms"] / max(prof["iter_launches"], 1), 5)
+
+
 def alg1_output(p, x0, wp, circ, warmup, steps):
     """The last steps of Alg. 1 on the same workload: iteration kernel time
-    with Savitzky-Golay smoothing in the root merge, and the latency of one
-    optimal-trajectory call (device rollout + copies, host clock)."""
+    with Savitzky-Golay smoothing in the root merge, the latency of one
+    optimal-trajectory call (device rollout + copies, host clock), and the
+    iteration time with per-step (cost-to-go) weights, whose launches are
+    the iteration kernel and the per-instance merge kernel."""
     from paper_2308_01654_amd import mppi
     ps = dict(p)
     ps["smoothing"] = 1
@@ -187,7 +206,9 @@ def alg1_output(p, x0, wp, circ, warmup, steps):
     pl.close()
     return {"smoothing_kernel_ms": round(prof["iter_ms"] / max(prof["iter_launches"], 1), 5),
             "trajectory_call_ms_p50": round(float(np.percentile(lat, 50)), 4),
-            "trajectory_call_ms_p99": round(float(np.percentile(lat, 99)), 4)}
+            "trajectory_call_ms_p99": round(float(np.percentile(lat, 99)), 4),
+            "per_step_weights_iteration_ms": _iteration_ms(dict(p, per_step=1), x0, wp, circ,
+                                                           warmup, steps)}
 
 
 def paper_cost_kernels(steps=50):

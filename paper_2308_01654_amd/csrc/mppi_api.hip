@@ -351,7 +351,7 @@ mppi_status handle_create(const mppi_config* cfg, void* hip_stream, bool with_sc
             {(void**)&h->S, sizeof(float) * K},
             {(void**)&h->eps, sizeof(float2) * (size_t)T * K},
             {(void**)&h->partials,
-             sizeof(double) * (size_t)h->max_tiles * partial_stride(T, cfg->per_step_weights)},
+             sizeof(double) * partial_doubles(T, cfg->per_step_weights, (size_t)h->max_tiles)},
             {(void**)&h->wbuf, sizeof(double) * (size_t)K},
             {(void**)&h->scene, h->scene_cap},
         };
@@ -385,6 +385,14 @@ mppi_status handle_create(const mppi_config* cfg, void* hip_stream, bool with_sc
 
 // Descriptor of one iteration of handle h from state x0 on the scene at
 // `scene` (device), staged relative to `origin`.
+// Whether the tiles of d keep their perturbations in LDS (see kLdsShared).
+static void choose_eps_stage(InstDesc& d, bool alone)
+{
+    const LdsLayout L = lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes, 1);
+    d.eps_stage = L.eps_staged && (L.total <= kLdsShared ||
+                                   (alone && d.n_tiles <= 512 && L.total <= kLdsAlone));
+}
+
 void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double origin[2],
                const unsigned char* scene, const SceneLayout& L, int n_wp, int n_c, int shift)
 {
@@ -446,6 +454,7 @@ void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double or
     d.q = h->q;
     d.Stk = h->Stk;
     d.st = h->st;
+    choose_eps_stage(d, false);
 }
 
 // ---- batched launches ---------------------------------------------------------------
@@ -568,7 +577,7 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
     InstDesc* descs = reinterpret_cast<InstDesc*>(host + off_descs);
     long total = 0;
     size_t smem = 0;
-    int any_shift = 0, any_out = 0, any_per_step = 0;
+    int any_shift = 0, any_out = 0, combine_g = 0;
     for (int j = 0; j < n; ++j) {
         const int i = order[j];
         mppi_t* hi = hs[i];
@@ -595,9 +604,9 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
         prefix[j] = (int)total;
         total += descs[j].n_tiles;
         smem = std::max(smem, lds_layout(descs[j].n_wp, descs[j].n_c, descs[j].T,
-                                         kBlock / descs[j].lanes).total);
+                                         kBlock / descs[j].lanes, descs[j].eps_stage).total);
         any_shift |= sh;
-        any_per_step |= descs[j].per_step;
+        combine_g = std::max(combine_g, combine_groups(descs[j].T));
     }
     if (total > (1L << 30)) return fail(MPPI_E_INVALID, "batch too large");
     prefix[n] = (int)total;
@@ -620,7 +629,6 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
     const int n_blocks = (int)pow2_at_least((size_t)n, 1);
     const int shift_blocks = any_shift ? n_blocks : 0;
     const int gather_blocks = (gather_dev && any_out) ? n_blocks : 0;
-    const int merge_blocks = any_per_step ? n_blocks : 0;
     static const int kClassLanes[5] = {1, 2, 4, 8, 16};
     auto enqueue_device_work = [&](size_t copy_bytes) -> hipError_t {
         hipError_t e = hipMemcpyAsync(ws->arena, host, copy_bytes, hipMemcpyHostToDevice, stream);
@@ -629,8 +637,8 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
             if (grids[c] > 0)
                 e = launch_batch(kClassLanes[(c % 25) / 5], c % 5, c / 25, nullptr, hdr_dev, c,
                                  grids[c], smem_b, stream);
-        if (e == hipSuccess && merge_blocks)
-            e = launch_merge_per_step(nullptr, hdr_dev, merge_blocks, stream);
+        if (e == hipSuccess && combine_g)
+            e = launch_combine(nullptr, hdr_dev, combine_g, n_blocks, stream);
         if (e == hipSuccess && gather_blocks)
             e = launch_gather(hdr_dev, gather_blocks, gather_dev, slot_doubles, stream);
         return e;
@@ -644,7 +652,7 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
         for (GraphEntry& g : ws->graphs)
             if (g.bytes == bucket && g.smem == smem_b && g.buf == b &&
                 g.shift_blocks == shift_blocks && g.gather_blocks == gather_blocks &&
-                g.merge_blocks == merge_blocks &&
+                g.combine_g == combine_g && g.combine_y == (combine_g ? n_blocks : 0) &&
                 memcmp(g.grids, grids, sizeof grids) == 0)
                 ge = &g;
         if (!ge) {
@@ -660,7 +668,8 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
             g.buf = b;
             g.shift_blocks = shift_blocks;
             g.gather_blocks = gather_blocks;
-            g.merge_blocks = merge_blocks;
+            g.combine_g = combine_g;
+            g.combine_y = combine_g ? n_blocks : 0;
             g.graph = nullptr;
             g.exec = nullptr;
             HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
@@ -764,12 +773,13 @@ mppi_status mppi_step_resident(mppi_t* h, const double x0[4])
         if (!isfinite(x0[i])) return fail(MPPI_E_INVALID, "x0[%d] is not finite", i);
     InstDesc d;
     fill_desc(d, h, x0, h->origin, h->scene, h->lay, h->n_wp, h->n_c, 0);
-    const size_t smem = lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes).total;
+    choose_eps_stage(d, true);
+    const size_t smem = lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes, d.eps_stage).total;
     hipEvent_t a = nullptr;
     if ((s = record_launch(h, 0, &a)) != MPPI_OK) return s;
     HIP_TRY(launch_batch(d.lanes, active_ego(d.n_ego, d.n_c), d.model, &d, nullptr, 0, d.n_tiles,
                          smem, h->stream));
-    if (d.per_step) HIP_TRY(launch_merge_per_step(&d, nullptr, 1, h->stream));
+    HIP_TRY(launch_combine(&d, nullptr, combine_groups(d.T), 1, h->stream));
     if ((s = record_end(h, 0, a)) != MPPI_OK) return s;
     h->last_lanes = d.lanes;
     h->stepped = true;
@@ -873,7 +883,7 @@ mppi_status mppi_set_state(mppi_t* h, const double* U, size_t n, uint64_t n_iter
     DevState st;
     HIP_TRY(hipMemcpy(&st, h->st, sizeof st, hipMemcpyDeviceToHost));
     st.n_iter = n_iter;
-    st.ticket = 0;
+    st.reserved = 0;
     st.status = 0;
     HIP_TRY(hipMemcpy(h->st, &st, sizeof st, hipMemcpyHostToDevice));
     h->stepped = false;

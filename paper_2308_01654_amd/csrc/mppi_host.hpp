@@ -20,7 +20,7 @@ mppi_status fail(mppi_status s, const char* fmt, ...) __attribute__((format(prin
 struct GraphEntry {
     size_t bytes, smem;
     int grids[kLaneClasses];
-    int buf, shift_blocks, gather_blocks, merge_blocks;
+    int buf, shift_blocks, gather_blocks, combine_g, combine_y;
     hipGraph_t graph;
     hipGraphExec_t exec;
 };

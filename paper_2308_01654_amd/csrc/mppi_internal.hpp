@@ -20,7 +20,7 @@ constexpr int kMaxK = 1 << 24;
 // zero between iterations).
 struct DevState {
     unsigned long long n_iter;  // Philox counter words 2-3: iteration number
-    unsigned int ticket;        // root nodes of the combine tree finished
+    unsigned int reserved;
     int status;                 // 0 or MPPI_E_NONFINITE of the last iteration
     double s_min;               // min_k S_k
     double z;                   // sum_k exp(-(S_k - s_min)/lambda)
@@ -35,17 +35,28 @@ constexpr int kPartialHead = 4;
 
 // With per-step weights a partial row holds, for every step t, the tile
 // minimum of the cost-to-go, the shifted exponential sums and the two
-// weighted perturbation sums ([5t .. 5t+4]), then 2T doubles of staging.
+// weighted perturbation sums ([5t .. 5t+4]).
 inline __host__ __device__ int partial_stride(int T, int per_step)
 {
-    return per_step ? 7 * T : kPartialHead + 2 * T;
+    return per_step ? 5 * T : kPartialHead + 2 * T;
 }
 
-// Tile partials are merged by a tree of fixed shape: a node of level l + 1
-// merges up to kFanIn consecutive nodes of level l, and the root merges the
-// last level that has at most kFanIn nodes.  Each non-root group has a
-// ticket; the member that completes it merges the group into the row of its
-// first tile.  The shape depends on the tile count only.
+// Doubles of the partials buffer of an instance: the tile rows, then 2T
+// doubles where the iteration kernel keeps the controls it sampled around
+// (read by the combine kernel when it smooths).
+inline __host__ __device__ size_t partial_doubles(int T, int per_step, size_t tiles)
+{
+    return tiles * (size_t)partial_stride(T, per_step) + 2 * (size_t)T;
+}
+
+// Tile partials are merged by the combine kernel, which takes up to kDirect
+// rows in one pass.  Larger instances first merge their tiles inside the
+// iteration kernel by a tree of fixed shape: a node of level l + 1 merges up
+// to kFanIn consecutive nodes of level l, until at most kDirect nodes
+// remain.  Each group has a ticket; the member that completes it merges the
+// group into the row of its first tile.  The shape depends on the tile count
+// only.
+constexpr int kDirect = 512;
 constexpr int kFanIn = 16;
 // Tickets sit on separate 128-byte lines so that groups finishing at the same
 // time do not contend for one line.
@@ -54,9 +65,26 @@ constexpr int kTicketStride = 32;
 inline __host__ __device__ int combine_tickets(int n_tiles)
 {
     int total = 0;
-    for (int n = n_tiles; n > kFanIn; n = (n + kFanIn - 1) / kFanIn) total += (n + kFanIn - 1) / kFanIn;
+    for (int n = n_tiles; n > kDirect; n = (n + kFanIn - 1) / kFanIn) total += (n + kFanIn - 1) / kFanIn;
     return total;
 }
+
+// Nodes left for the combine kernel and the tiles each one spans.
+inline __host__ __device__ int combine_nodes(int n_tiles, size_t* span)
+{
+    int n = n_tiles;
+    size_t sp = 1;
+    while (n > kDirect) {
+        n = (n + kFanIn - 1) / kFanIn;
+        sp *= kFanIn;
+    }
+    if (span) *span = sp;
+    return n;
+}
+
+// Steps of U each combine workgroup updates.
+constexpr int kCombineSteps = 4;
+inline __host__ __device__ int combine_groups(int T) { return (T + kCombineSteps - 1) / kCombineSteps; }
 
 // Everything one launch needs to run one MPPI iteration of one instance.
 // Scene arrays are in the ego frame (x0's position subtracted) and float32.
@@ -81,6 +109,7 @@ struct InstDesc {
     float w_target, w_yaw;// weights of c_target and c_yaw (0: term skipped)
     int coll_only;        // c_safe_dist only when d_obj <= 0
     int per_step;         // 1: weights from the cost-to-go per step
+    int eps_stage;        // 1: tiles keep their perturbations in LDS (lds_layout)
     int model;            // 1: 5-state model of eq. (5), steering-rate control
     float steer0;         // its initial steering angle
     float ego_ext;        // max |ego_off|
@@ -94,7 +123,7 @@ struct InstDesc {
     double* U;            // [T][2]
     float* S;             // [K]
     float2* eps;          // [T][K]
-    double* partials;     // [n_tiles][partial_stride(T, per_step)]
+    double* partials;     // partial_doubles(T, per_step, n_tiles)
     float* q;             // [T][K] stage costs (per-step weights)
     double* Stk;          // [T][K] cost-to-go (per-step weights)
     DevState* st;         // followed by the combine-tree tickets
@@ -118,8 +147,17 @@ struct BatchHdr {
 
 // Dynamic LDS layout of the iteration kernel for a given scene size.
 struct LdsLayout {
-    size_t c_pv, wp_box, wp_xy, U, red, wp_vref, wp_yaw, c_rr, omega, blk, total;
+    size_t c_pv, wp_box, wp_xy, U, red, wp_vref, wp_yaw, c_rr, omega, blk, eps, total;
+    int eps_staged;  // the tile's applied perturbations are kept at eps
 };
+
+// Largest LDS copy of a tile's applied perturbations ([2T][spb + 1] floats).
+constexpr size_t kEpsStageMax = 32 << 10;
+// The copy is made when the workgroup's LDS stays within kLdsShared (five
+// workgroups per compute unit), or within kLdsAlone for an instance launched
+// alone with at most two tiles per compute unit (256 units).
+constexpr size_t kLdsShared = 32 << 10;
+constexpr size_t kLdsAlone = 64 << 10;
 
 // Waypoints are grouped in chunks of this many consecutive points; each chunk
 // has an axis-aligned bounding box in LDS for the wave-level culling.
@@ -127,7 +165,7 @@ constexpr int kChunk = 8;
 
 inline __host__ __device__ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int spb)
+inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int spb, int eps_stage)
 {
     LdsLayout L;
     size_t o = 0;
@@ -142,6 +180,9 @@ inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int sp
     L.omega = o;   o += (size_t)spb * 4;
     o = align_up(o, 8);
     L.blk = o;     o += (size_t)spb * 8;   // block-start position per sample
+    const size_t eb = (size_t)2 * T * (spb + 1) * 4;
+    L.eps_staged = eps_stage && eb <= kEpsStageMax;
+    L.eps = o;     o += L.eps_staged ? eb : 0;
     L.total = align_up(o, 16);
     return L;
 }
@@ -155,10 +196,11 @@ hipError_t launch_batch(int lanes, int ne, int model, const InstDesc* d0,
                         const BatchHdr* hdr_dev, int cls, int grid, size_t smem,
                         hipStream_t stream);
 
-// Per-step weights: merge of the tile rows of one instance (d0, hdr_dev ==
-// nullptr) or of every per-step instance of a batch (n_blocks = n_inst).
-hipError_t launch_merge_per_step(const InstDesc* d0, const BatchHdr* hdr_dev, int n_blocks,
-                                 hipStream_t stream);
+// Combine of the tile rows of one instance (d0, hdr_dev == nullptr) or of
+// every instance of a batch (n_inst rows of the grid, groups = largest
+// combine_groups(T) among them).
+hipError_t launch_combine(const InstDesc* d0, const BatchHdr* hdr_dev, int groups, int n_inst,
+                          hipStream_t stream);
 
 // Ego circles that take part in the obstacle term of an instance.
 inline int active_ego(int n_ego, int n_c) { return n_c > 0 ? n_ego : 0; }

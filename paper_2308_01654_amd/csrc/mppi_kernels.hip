@@ -87,6 +87,7 @@ struct Lds {
     float* c_rr;
     float* omega;
     float2* blk;
+    float* eps;  // [2T][spb + 1]: column 2t + c, sample j at (2t + c)(spb + 1) + j
 };
 
 __device__ __forceinline__ Lds lds_bind(unsigned char* base, const LdsLayout& L)
@@ -102,6 +103,7 @@ __device__ __forceinline__ Lds lds_bind(unsigned char* base, const LdsLayout& L)
     s.c_rr = reinterpret_cast<float*>(base + L.c_rr);
     s.omega = reinterpret_cast<float*>(base + L.omega);
     s.blk = reinterpret_cast<float2*>(base + L.blk);
+    s.eps = reinterpret_cast<float*>(base + L.eps);
     return s;
 }
 
@@ -293,7 +295,30 @@ __device__ __forceinline__ WaveBox wave_box(bool inc, float x, float y, float ds
     return w;
 }
 
-// Wave minimum of non-negative floats (their bit patterns are ordered).
+// Wave minimum and maximum of non-negative floats (their bit patterns are
+// ordered), advanced stage by stage together.
+__device__ __forceinline__ void wave_minmax_nonneg(float vmin, float vmax, float& omin,
+                                                   float& omax)
+{
+    int a = __builtin_bit_cast(int, vmin);
+    int b = __builtin_bit_cast(int, vmax);
+    a = min(a, dpp_i<0xB1>(kIntMax, a));
+    b = max(b, dpp_i<0xB1>(kIntMin, b));
+    a = min(a, dpp_i<0x4E>(kIntMax, a));
+    b = max(b, dpp_i<0x4E>(kIntMin, b));
+    a = min(a, dpp_i<0x141>(kIntMax, a));
+    b = max(b, dpp_i<0x141>(kIntMin, b));
+    a = min(a, dpp_i<0x140>(kIntMax, a));
+    b = max(b, dpp_i<0x140>(kIntMin, b));
+    a = min(a, dpp_i<0x142, 0xa>(kIntMax, a));
+    b = max(b, dpp_i<0x142, 0xa>(kIntMin, b));
+    a = min(a, dpp_i<0x143, 0xc>(kIntMax, a));
+    b = max(b, dpp_i<0x143, 0xc>(kIntMin, b));
+    omin = __builtin_bit_cast(float, lane63(a));
+    omax = __builtin_bit_cast(float, lane63(b));
+}
+
+// Wave minimum of non-negative floats.
 __device__ __forceinline__ float wave_min_nonneg(float v)
 {
     int a = __builtin_bit_cast(int, v);
@@ -404,12 +429,15 @@ struct LaneCull {
 // The stage cost of stage_cost, with the two scans restricted to what can
 // matter for this wave (all 64 lanes call it; `act` lanes are evaluated).
 // The result is bit-identical to the full scans:
-//  * waypoints: UB = min over chunks of the largest distance^2 between the
-//    wave's position box and the chunk box bounds every lane's nearest
-//    distance^2; a chunk whose smallest distance^2 to the wave box exceeds
-//    UB (with a relative margin far above float32 rounding) holds no
-//    candidate, and the remaining chunks are scanned in index order, so
-//    ties resolve exactly as in the full scan;
+//  * waypoints: two bounds on every lane's nearest distance^2 -- the
+//    smallest over chunks of the largest distance^2 between the wave's
+//    position box and the chunk box, and the largest over lanes of the
+//    lane's own distance^2 (same arithmetic as the scan) to three waypoints
+//    ahead of its previous closest chunk; UB is the smaller.  A chunk whose
+//    smallest distance^2 to the wave box exceeds UB (with a relative margin
+//    far above float32 rounding) holds no candidate, and the remaining
+//    chunks are scanned in index order, so ties resolve exactly as in the
+//    full scan;
 //  * circles: a circle whose centre, swept over the wave's time range, stays
 //    farther than max(d_safe) + r_c + r_ego from the box of the wave's ego
 //    circles cannot make c_safe positive for any lane, so it is skipped.
@@ -418,7 +446,7 @@ struct LaneCull {
 template <int NE>
 __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds& s,
                                                    const LaneCull& lc, bool vref_uniform, bool act,
-                                                   float x, float y,
+                                                   int& seed, float x, float y,
                                                    float c, float sn, float v, float Ua, float Ud,
                                                    float ea, float ed, int t, int t_lo, int t_hi,
                                                    float th, float xp, float yp)
@@ -443,13 +471,32 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
         const float gy = fmaxf(fmaxf(b.z - wb.yhi, wb.ylo - b.w), 0.0f);
         return fmaf(gy, gy, gx * gx);
     };
+    // A second bound from the lane itself: its distance^2 to three waypoints
+    // ahead of the chunk it was closest to at its previous step (seed), the
+    // largest over the lanes of the wave; lanes without a seed give +inf.
+    float own = 0.0f;
+    if (inc) {
+        own = INFINITY;
+        if (seed >= 0) {
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const float2 w = s.wp_xy[min(seed * kChunk + (u + 1) * (kChunk / 2), d.n_wp - 1)];
+                const float dx = x - w.x;
+                const float dy = y - w.y;
+                own = fminf(own, fmaf(dy, dy, dx * dx));
+            }
+        }
+    }
     if (n_ch <= 64) {
-        const float ub = wave_min_nonneg(far2(lc.box));
-        const float thr = fmaf(ub, 1.0f + 1e-5f, 1e-6f);
+        float ub_box, ub_own;
+        wave_minmax_nonneg(far2(lc.box), own, ub_box, ub_own);
+        const float thr = fmaf(fminf(ub_box, ub_own), 1.0f + 1e-5f, 1e-6f);
         scan_chunks(wp4, 0, __ballot(near2(lc.box) <= thr), x, y, best, bch);
     } else {
         const float4 empty = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
-        float ub = wave_min_nonneg(far2(lc.box));
+        float ub, ub_own;
+        wave_minmax_nonneg(far2(lc.box), own, ub, ub_own);
+        ub = fminf(ub, ub_own);
         for (int base = 64; base < n_ch; base += 64)
             ub = fminf(ub, wave_min_nonneg(far2(base + lane < n_ch ? s.wp_box[base + lane] : empty)));
         const float thr = fmaf(ub, 1.0f + 1e-5f, 1e-6f);
@@ -459,6 +506,7 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
             scan_chunks(wp4, base, __ballot(near2(b) <= thr), x, y, best, bch);
         }
     }
+    if (best < INFINITY) seed = bch;
     // the closest index, needed for its reference speed (unless every
     // waypoint has the same one) and for its yaw
     const bool need_idx = !vref_uniform || d.w_yaw != 0.0f;
@@ -544,50 +592,8 @@ __device__ __forceinline__ double wave_min(double v)
     return v;
 }
 
-// Block-wide reductions over kBlock threads; every thread gets the result.
-// The combination order is fixed (xor tree inside a wave, waves in order).
-__device__ __forceinline__ double block_sum(double v, double* red)
-{
-    v = wave_sum(v);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[w] = v;
-    __syncthreads();
-    double r = red[0];
-#pragma unroll
-    for (int i = 1; i < kBlock / 64; ++i) r += red[i];
-    return r;
-}
-
-__device__ __forceinline__ double block_min(double v, double* red)
-{
-    v = wave_min(v);
-    const int w = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) red[w] = v;
-    __syncthreads();
-    double r = red[0];
-#pragma unroll
-    for (int i = 1; i < kBlock / 64; ++i) r = fmin(r, red[i]);
-    return r;
-}
-
 // M5: the 5-state model of eq. (5) -- the steering angle is part of the state
 // and the second control is the steering rate.
-// Eq. (sg) on the updated sequence staged at un [T][2], written to U:
-// u*_t = (-3 u_{t-2} + 12 u_{t-1} + 17 u_t + 12 u_{t+1} - 3 u_{t+2}) / 35, the
-// end values repeated beyond the horizon.  The caller synchronises first.
-__device__ __forceinline__ void smooth_into(double* U, const double* un, int T)
-{
-    for (int col = threadIdx.x; col < 2 * T; col += blockDim.x) {
-        const int t = col >> 1, c2 = col & 1;
-        auto at = [&](int i) { return un[2 * min(max(i, 0), T - 1) + c2]; };
-        const double sm = -3.0 * at(t - 2) + 12.0 * at(t - 1) + 17.0 * at(t) +
-                          12.0 * at(t + 1) - 3.0 * at(t + 2);
-        U[col] = sm / 35.0;
-    }
-}
-
 template <int G, int NE, bool M5>
 __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
 {
@@ -595,7 +601,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     constexpr int SPB = kBlock / G;  // samples per tile
     const int T = d.T;
     const int K = d.K;
-    const LdsLayout L = lds_layout(d.n_wp, d.n_c, T, SPB);
+    const LdsLayout L = lds_layout(d.n_wp, d.n_c, T, SPB, d.eps_stage);
     const Lds s = lds_bind(smem, L);
 
     for (int i = tid; i < d.n_c; i += kBlock) {
@@ -628,6 +634,11 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     }
     for (int i = tid; i < T; i += kBlock)
         s.U[i] = make_float2((float)d.U[2 * i], (float)d.U[2 * i + 1]);
+    // the controls sampled around, kept for the smoothing combine
+    if (d.smooth && tile == 0) {
+        double* keep = d.partials + (size_t)d.n_tiles * partial_stride(T, d.per_step);
+        for (int i = tid; i < 2 * T; i += kBlock) keep[i] = d.U[i];
+    }
     const unsigned long long n_iter = d.st->n_iter;
     // one reference speed for every waypoint: the closest index is not needed
     const bool vref_uniform = __syncthreads_and(same_vref) != 0;
@@ -652,6 +663,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     float delta = d.steer0;  // steering angle (5-state model only)
     float c = __cosf(th), sn = __sinf(th);
     float S = 0.0f, comp = 0.0f;  // Kahan pair of this lane's steps
+    int seed = -1;                // closest chunk at this lane's previous step
     for (int t0 = 0; t0 < T; t0 += G) {
         const int tm = t0 + r;
         // The lane's step within the block, opaque to the compiler so that the
@@ -677,7 +689,6 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         float apf[PF], tpf[PF];
 #pragma unroll
         for (int i = 0; i < G; ++i) {
-            const int t = t0 + i;
             if (i % PF == 0) {
 #pragma unroll
                 for (int u = 0; u < PF; ++u) {
@@ -690,7 +701,10 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
                     }
                 }
             }
-            if (G > 1 && t >= T) continue;
+            // Steps past the horizon (last block) are integrated too: only
+            // lanes whose own step lies past it keep their states, and those
+            // lanes are inactive.  The walk stays one basic block.
+            //
             // noise check: speed cap, braking bound last
             float a = fminf(apf[i % PF], (d.v_max - v) * d.inv_dt);
             a = fmaxf(a, d.a_min);
@@ -709,9 +723,12 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             v = fmaf(d.dt, a, v);
             c = __cosf(th);
             sn = __sinf(th);
-            if (i == rb) {
-                mx = x; my = y; mv = v; ma = a; mth = th;
-            }
+            const bool own = i == rb;
+            mx = own ? x : mx;
+            my = own ? y : my;
+            mv = own ? v : mv;
+            ma = own ? a : ma;
+            mth = own ? th : mth;
         }
         // the heading's cosine and sine at this lane's step, recomputed from the
         // kept heading with the instructions of the walk (same bits)
@@ -738,7 +755,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         }
         float q = 0.0f;
         if (d.cull)
-            q = stage_cost_culled<NE>(d, s, lc, vref_uniform, act, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm, t0,
+            q = stage_cost_culled<NE>(d, s, lc, vref_uniform, act, seed, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm, t0,
                                       min(t0 + G, T) - 1, mth, pxp, pyp);
         else if (act)
             q = stage_cost<NE>(d, s, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm, mth, pxp, pyp);
@@ -749,6 +766,10 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             comp = (tk - S) - yk;
             S = tk;
             if (valid) d.eps[(size_t)tm * K + k] = make_float2(mea, med);
+            if (L.eps_staged) {
+                s.eps[(2 * tm) * (SPB + 1) + grp] = mea;
+                s.eps[(2 * tm + 1) * (SPB + 1) + grp] = med;
+            }
         }
     }
 
@@ -807,49 +828,76 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             o[4] = nd;
         }
     } else {
-    const double m_b = block_min((double)Sk, s.red);
-    double om = 0.0;
-    if (r == 0 && isfinite(m_b) && Sk < INFINITY) om = exp(-((double)Sk - m_b) / d.lambda);
-    if (r == 0) s.omega[grp] = (float)om;
-    const double z_b = block_sum(om, s.red);
-    const double q_b = block_sum(om * om, s.red);  // also orders omega stores
-    for (int col = tid; col < 2 * T; col += kBlock) {
-        const int t = col >> 1;
-        const float* e = reinterpret_cast<const float*>(d.eps + (size_t)t * K + k_base) + (col & 1);
-        float acc = 0.0f, cp = 0.0f;
-        // loads issued eight at a time, summed in sample order
-        for (int i0 = 0; i0 < n_valid; i0 += 8) {
-            float ev[8];
+        // Tile minimum, then the tile's exponential sums: wave results through
+        // LDS, combined in wave order (two barriers).
+        const int wv = tid >> 6;
+        const bool lane0 = (tid & 63) == 0;
+        const double wmin = wave_min((double)Sk);
+        if (lane0) s.red[wv] = wmin;
+        __syncthreads();
+        double m_b = s.red[0];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) ev[u] = (i0 + u < n_valid) ? e[2 * (i0 + u)] : 0.0f;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                if (i0 + u < n_valid) {
-                    const float yk = s.omega[i0 + u] * ev[u] - cp;
-                    const float tk = acc + yk;
-                    cp = (tk - acc) - yk;
-                    acc = tk;
-                }
-            }
+        for (int i = 1; i < kBlock / 64; ++i) m_b = fmin(m_b, s.red[i]);
+        double om = 0.0;
+        if (r == 0 && isfinite(m_b) && Sk < INFINITY) om = exp(-((double)Sk - m_b) / d.lambda);
+        if (r == 0) s.omega[grp] = (float)om;
+        const double wz = wave_sum(om);
+        const double wq = wave_sum(om * om);
+        if (lane0) {
+            s.red[4 + wv] = wz;
+            s.red[8 + wv] = wq;
         }
-        part[kPartialHead + col] = (double)acc - (double)cp;
-    }
-    if (tid == 0) {
-        part[0] = m_b;
-        part[1] = z_b;
-        part[2] = q_b;
-        part[3] = 0.0;
-    }
+        __syncthreads();  // also orders the omega stores
+        double z_b = s.red[4], q_b = s.red[8];
+#pragma unroll
+        for (int i = 1; i < kBlock / 64; ++i) {
+            z_b += s.red[4 + i];
+            q_b += s.red[8 + i];
+        }
+        // Weighted perturbation sums, one column (step, control) per thread,
+        // the exact float products summed in float64 in sample order: from
+        // the tile's LDS copy of its perturbations (rows padded by one so
+        // that the lanes of a wave read distinct banks) or, when that copy
+        // does not fit, from global memory, sixteen loads in flight.
+        constexpr int NB = SPB < 16 ? SPB : 16;
+        for (int col = tid; col < 2 * T; col += kBlock) {
+            if (L.eps_staged) {
+                const float* e = s.eps + col * (SPB + 1);
+                double acc = 0.0;
+                for (int j = 0; j < n_valid; ++j)
+                    acc = fma((double)s.omega[j], (double)e[j], acc);
+                part[kPartialHead + col] = acc;
+                continue;
+            }
+            const int t = col >> 1;
+            const float* e =
+                reinterpret_cast<const float*>(d.eps + (size_t)t * K + k_base) + (col & 1);
+            double acc = 0.0;
+            for (int i0 = 0; i0 < n_valid; i0 += NB) {
+                float ev[NB];
+#pragma unroll
+                for (int u = 0; u < NB; ++u) ev[u] = (i0 + u < n_valid) ? e[2 * (i0 + u)] : 0.0f;
+#pragma unroll
+                for (int u = 0; u < NB; ++u)
+                    if (i0 + u < n_valid) acc = fma((double)s.omega[i0 + u], (double)ev[u], acc);
+            }
+            part[kPartialHead + col] = acc;
+        }
+        if (tid == 0) {
+            part[0] = m_b;
+            part[1] = z_b;
+            part[2] = q_b;
+            part[3] = 0.0;
+        }
     }
 
     // ---------------------------------------------------------------- phase 3
-    // Per-step weights: the tile rows are merged by k_merge_per_step, which
-    // runs after this kernel.
-    if (d.per_step) return;
-    // Merge the tile partials up the combine tree.  A node's row is the row
-    // of its first tile; children are merged in index order with the
-    // log-sum-exp shift to their common minimum (per step with per-step
-    // weights).
+    // The tile rows are merged by the combine kernel, which runs after this
+    // one.  More than kDirect tiles
+    // are first merged here, kFanIn at a time in tile order with the
+    // log-sum-exp shift to their common minimum, until at most kDirect nodes
+    // remain; a node's row is the row of its first tile.
+    if (d.per_step || d.n_tiles <= kDirect) return;
     // first ticket on the 128-byte line after the state
     unsigned int* tickets = reinterpret_cast<unsigned int*>(
         (reinterpret_cast<uintptr_t>(d.st + 1) + 4 * kTicketStride - 1) & ~(uintptr_t)(4 * kTicketStride - 1));
@@ -860,16 +908,15 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     size_t span = 1;             // tiles per node at this level
     int toff = 0;                // first ticket of this level
     for (;;) {
-        const bool root = n_l <= kFanIn;
-        const int g = root ? 0 : idx / kFanIn;
+        const int g = idx / kFanIn;
         const int first = g * kFanIn;
-        const int nc = root ? n_l : min(kFanIn, n_l - first);
+        const int nc = min(kFanIn, n_l - first);
         // The barrier orders the workgroup's row stores before the ticket;
         // the release increment publishes them device-wide.  Only the member
         // that completes the group pays for the acquire (below).
         __syncthreads();
         if (tid == 0) {
-            unsigned int* tk = root ? &d.st->ticket : &tickets[(size_t)(toff + g) * kTicketStride];
+            unsigned int* tk = &tickets[(size_t)(toff + g) * kTicketStride];
             const unsigned int prev =
                 __hip_atomic_fetch_add(tk, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             const bool last = prev == (unsigned int)(nc - 1);
@@ -901,150 +948,323 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             }
         }
         __syncthreads();
-        const double mm = s.red[0], zz = s.red[1], qq = s.red[2];
-        if (root && !isfinite(mm)) {
-            if (tid == 0) d.st->status = -4;  // MPPI_E_NONFINITE: U and n stay unchanged
-            return;
-        }
         for (int col = tid; col < 2 * T; col += kBlock) {
             const double* src = rows + kPartialHead + col;
+            // every child in flight at once, merged in child order
+            double pv[kFanIn];
+#pragma unroll
+            for (int u = 0; u < kFanIn; ++u) pv[u] = u < nc ? src[(size_t)u * cstride] : 0.0;
             double acc = 0.0;
-            // eight children in flight, merged in child order
-            for (int i0 = 0; i0 < nc; i0 += 8) {
-                double pv[8];
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    pv[u] = i0 + u < nc ? src[(size_t)(i0 + u) * cstride] : 0.0;
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (i0 + u < nc) acc += pv[u] * sc_lds[i0 + u];
-            }
-            if (root) {
-                const double un = d.U[col] + acc / zz;
-                // with smoothing the updated sequence is staged in the root row
-                if (d.smooth) rows[kPartialHead + col] = un;
-                else d.U[col] = un;
-            } else {
-                rows[kPartialHead + col] = acc;
-            }
-        }
-        if (root) {
-            if (d.smooth) {
-                __syncthreads();
-                smooth_into(d.U, rows + kPartialHead, T);
-            }
-            if (tid == 0) {
-                d.st->s_min = mm;
-                d.st->z = zz;
-                d.st->log_z = log(zz);
-                d.st->ess = zz * zz / qq;
-                d.st->status = 0;
-                d.st->n_iter = n_iter + 1ull;
-            }
-            return;
+            for (int u = 0; u < kFanIn; ++u)
+                if (u < nc) acc += pv[u] * sc_lds[u];
+            rows[kPartialHead + col] = acc;
         }
         if (tid == 0) {
-            rows[0] = mm;
-            rows[1] = zz;
-            rows[2] = qq;
+            rows[0] = s.red[0];
+            rows[1] = s.red[1];
+            rows[2] = s.red[2];
         }
         toff += (n_l + kFanIn - 1) / kFanIn;
         n_l = (n_l + kFanIn - 1) / kFanIn;
+        if (n_l <= kDirect) return;
         idx = g;
         span *= kFanIn;
     }
 }
 
-// Per-step weights: merges every tile row of one instance in tile order (one
-// workgroup, one thread per step): per step the smallest cost-to-go over the
-// tiles, each tile's sums shifted to it by exp(-(m_b - m)/lambda), then
-// U_t += N_t / Z_t (smoothed when configured) and the statistics of t = 0.
-// No step is updated unless every step has a finite cost-to-go.
-__device__ void merge_per_step(const InstDesc& d)
+// Combine (Alg. 1, the normaliser and the input update of eq.
+// (update-input)): merges the kDirect or fewer remaining node rows of one
+// instance.  Every workgroup forms the global minimum m and the node scales
+// exp(-(m_b - m)/lambda), Z and Q itself (node order, fixed trees), then
+// updates kCombineSteps steps of U: U_t += N_t / Z with N_t summed over the
+// nodes in node order (chunks of consecutive nodes, then the chunks in
+// order).  With smoothing it also updates the two steps on either side
+// (from the controls the iteration kernel kept) and writes its own steps
+// after eq. (sg).  Workgroup 0 records the statistics and bumps the
+// iteration counter.  Nothing is written if no sample cost is finite.
+__device__ void combine(const InstDesc& d, int cg)
 {
+    extern __shared__ __align__(16) unsigned char csm[];
+    double* sc = reinterpret_cast<double*>(csm);   // [kDirect] node scales
+    double* red = sc + kDirect;                    // [64] reductions
+    double* part = red + 64;                       // [kBlock] column partials
+    double* un = part + kBlock;                    // [16] updated worked columns
+    const int tid = threadIdx.x;
     const int T = d.T;
-    const size_t stride = partial_stride(T, 1);
-    double* rows = d.partials;
-    bool bad = false;
-    for (int t = threadIdx.x; t < T; t += blockDim.x) {
-        double mm = INFINITY;
-        for (int b = 0; b < d.n_tiles; ++b) {
-            const double mb = rows[(size_t)b * stride + 5 * t];
-            if (mb < mm) mm = mb;
-        }
-        double zz = 0.0, qq = 0.0, na = 0.0, nd = 0.0;
-        if (isfinite(mm)) {
-            for (int b = 0; b < d.n_tiles; ++b) {
-                const double* h = rows + (size_t)b * stride + 5 * t;
-                const double sc = isfinite(h[0]) ? exp(-(h[0] - mm) / d.lambda) : 0.0;
-                zz += h[1] * sc;
-                qq += h[2] * sc * sc;
-                na += h[3] * sc;
-                nd += h[4] * sc;
-            }
-        } else {
-            bad = true;
-        }
-        double* o = rows + 5 * t;  // tile 0's row, at the steps this thread read
-        o[0] = mm;
-        o[1] = zz;
-        o[2] = qq;
-        o[3] = na;
-        o[4] = nd;
+    const int s0 = cg * kCombineSteps;
+    if (s0 >= T) return;
+    const int s1 = min(s0 + kCombineSteps, T);
+    const int w0 = d.smooth ? max(s0 - 2, 0) : s0;
+    const int w1 = d.smooth ? min(s1 + 2, T) : s1;
+    const int ncol = 2 * (w1 - w0);          // worked columns, 2 * w0 first
+    const int slots = ncol <= 8 ? 8 : 16;    // threads per chunk
+    const int chunks = kBlock / slots;
+    const int stride = partial_stride(T, 0);
+    size_t span = 1;
+    const int n = combine_nodes(d.n_tiles, &span);
+    const size_t nstride = span * stride;    // between nodes
+    const double* rows = d.partials;
+
+    // One round trip: the node heads (kDirect / kBlock per thread) and the
+    // first sixteen nodes of this thread's chunk of its worked column.
+    constexpr int kH = kDirect / kBlock;
+    double mh[kH], zh[kH], qh[kH];
+#pragma unroll
+    for (int r = 0; r < kH; ++r) {
+        const int i = tid + r * kBlock;
+        const double* h = rows + (size_t)min(i, n - 1) * nstride;
+        mh[r] = i < n ? h[0] : INFINITY;
+        zh[r] = i < n ? h[1] : 0.0;
+        qh[r] = i < n ? h[2] : 0.0;
     }
-    if (__syncthreads_or(bad)) {
-        if (threadIdx.x == 0) d.st->status = -4;  // MPPI_E_NONFINITE: U and n unchanged
+    const int slot = tid % slots, chunk = tid / slots;
+    const int per = (n + chunks - 1) / chunks;
+    const int i0 = min(chunk * per, n), i1 = min(i0 + per, n);
+    const bool worked = slot < ncol;
+    const double* src = rows + kPartialHead + 2 * w0 + slot;
+    double pv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+        pv[u] = (worked && i0 + u < i1) ? src[(size_t)(i0 + u) * nstride] : 0.0;
+
+    // global minimum
+    double mloc = mh[0];
+#pragma unroll
+    for (int r = 1; r < kH; ++r) mloc = fmin(mloc, mh[r]);
+    const double wm = wave_min(mloc);
+    const int wv = tid >> 6;
+    if ((tid & 63) == 0) red[wv] = wm;
+    __syncthreads();
+    double m = red[0];
+#pragma unroll
+    for (int i = 1; i < kBlock / 64; ++i) m = fmin(m, red[i]);
+    if (!isfinite(m)) {
+        if (cg == 0 && tid == 0) d.st->status = -4;  // MPPI_E_NONFINITE: U and n unchanged
         return;
     }
-    double* stage = rows + 5 * (size_t)T;  // 2T doubles
-    for (int t = threadIdx.x; t < T; t += blockDim.x) {
-        const double* o = rows + 5 * t;
-        const double ua = d.U[2 * t] + o[3] / o[1];
-        const double ud = d.U[2 * t + 1] + o[4] / o[1];
-        if (d.smooth) {
-            stage[2 * t] = ua;
-            stage[2 * t + 1] = ud;
-        } else {
-            d.U[2 * t] = ua;
-            d.U[2 * t + 1] = ud;
+    // node scales, Z and Q (thread, wave, then waves in order)
+    double zl = 0.0, ql = 0.0;
+#pragma unroll
+    for (int r = 0; r < kH; ++r) {
+        const int i = tid + r * kBlock;
+        if (i < n) {
+            const double si = isfinite(mh[r]) ? exp(-(mh[r] - m) / d.lambda) : 0.0;
+            sc[i] = si;
+            zl += zh[r] * si;
+            ql += qh[r] * si * si;
         }
+    }
+    const double wz = wave_sum(zl), wq = wave_sum(ql);
+    if ((tid & 63) == 0) {
+        red[4 + wv] = wz;
+        red[8 + wv] = wq;
+    }
+    __syncthreads();  // also publishes the scales
+    double z = red[4], q = red[8];
+#pragma unroll
+    for (int i = 1; i < kBlock / 64; ++i) {
+        z += red[4 + i];
+        q += red[8 + i];
+    }
+
+    // weighted perturbation sums of the worked columns, nodes in order
+    double acc = 0.0;
+    if (worked) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (i0 + u < i1) acc += pv[u] * sc[i0 + u];
+        for (int b = i0 + 16; b < i1; b += 16) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) pv[u] = b + u < i1 ? src[(size_t)(b + u) * nstride] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (b + u < i1) acc += pv[u] * sc[b + u];
+        }
+    }
+    part[tid] = acc;
+    __syncthreads();
+    if (tid < ncol) {
+        double nsum = 0.0;
+        for (int c = 0; c < chunks; ++c) nsum += part[c * slots + tid];
+        const int col = 2 * w0 + tid;
+        // the controls the iteration sampled around: kept after the tile rows
+        // when smoothing (other workgroups rewrite U), else U itself
+        const double* u_old = d.smooth ? d.partials + (size_t)d.n_tiles * stride : d.U;
+        const double u = u_old[col] + nsum / z;
+        if (d.smooth) un[tid] = u;
+        else d.U[col] = u;
     }
     if (d.smooth) {
         __syncthreads();
-        smooth_into(d.U, stage, T);
+        // eq. (sg) on the own steps: u*_t = (-3 u_{t-2} + 12 u_{t-1} + 17 u_t +
+        // 12 u_{t+1} - 3 u_{t+2}) / 35, the end values repeated beyond the horizon
+        const int own = 2 * (s1 - s0);
+        if (tid < own) {
+            const int t = s0 + (tid >> 1), c2 = tid & 1;
+            auto at = [&](int i) { return un[2 * (min(max(i, 0), T - 1) - w0) + c2]; };
+            const double sm = -3.0 * at(t - 2) + 12.0 * at(t - 1) + 17.0 * at(t) +
+                              12.0 * at(t + 1) - 3.0 * at(t + 2);
+            d.U[2 * s0 + tid] = sm / 35.0;
+        }
     }
-    if (threadIdx.x == 0) {
-        d.st->s_min = rows[0];
-        d.st->z = rows[1];
-        d.st->log_z = log(rows[1]);
-        d.st->ess = rows[1] * rows[1] / rows[2];
+    if (cg == 0 && tid == 0) {
+        d.st->s_min = m;
+        d.st->z = z;
+        d.st->log_z = log(z);
+        d.st->ess = z * z / q;
         d.st->status = 0;
         d.st->n_iter = d.st->n_iter + 1ull;
     }
 }
 
-// One instance (d0, hdr == nullptr) or every per-step instance of a batch
-// (one workgroup each).
-__global__ __launch_bounds__(kBlock) void k_merge_per_step(InstDesc d0,
-                                                           const BatchHdr* __restrict__ hdr)
+// Combine with per-step weights: the tile rows hold, per step t, the tile
+// minimum m_b,t of the cost-to-go and the shifted sums Z, Q, N_a, N_d.  A
+// workgroup updates kCombineSteps steps (and, with smoothing, the two on
+// either side): per step the minimum over the tiles, each tile's sums
+// shifted to it by exp(-(m_b,t - m_t)/lambda) (tiles in chunks of
+// consecutive tiles, then the chunks in order), U_t += N_t / Z_t.  A sample
+// whose total cost is finite has a finite cost-to-go at every step, so every
+// step is finite exactly when step 0 is; without a finite step 0 nothing is
+// written.  Workgroup 0 records the statistics of step 0.
+__device__ void combine_per_step(const InstDesc& d, int cg)
 {
-    if (!hdr) {
-        if (blockIdx.x == 0) merge_per_step(d0);
+    extern __shared__ __align__(16) unsigned char csm[];
+    double* red = reinterpret_cast<double*>(csm);  // [64]
+    double* part = red + 64;                       // [kBlock][4] chunk partials
+    double* mt = part + 4 * kBlock;                // [8] step minima
+    double* un = mt + 8;                           // [16] updated worked columns
+    const int tid = threadIdx.x;
+    const int T = d.T;
+    const int s0 = cg * kCombineSteps;
+    if (s0 >= T) return;
+    const int s1 = min(s0 + kCombineSteps, T);
+    const int w0 = d.smooth ? max(s0 - 2, 0) : s0;
+    const int w1 = d.smooth ? min(s1 + 2, T) : s1;
+    const int nst = w1 - w0;                 // worked steps (at most 8)
+    constexpr int kSlots = 8;                // threads per chunk
+    constexpr int kChunks = kBlock / kSlots;
+    const size_t stride = partial_stride(T, 1);
+    const int n = d.n_tiles;
+    const double* rows = d.partials;
+
+    // step 0: minimum over the tiles (every workgroup)
+    double m0 = INFINITY;
+    for (int b = tid; b < n; b += kBlock) m0 = fmin(m0, rows[(size_t)b * stride]);
+    const double w0m = wave_min(m0);
+    const int wv = tid >> 6;
+    if ((tid & 63) == 0) red[wv] = w0m;
+    __syncthreads();
+    m0 = red[0];
+#pragma unroll
+    for (int i = 1; i < kBlock / 64; ++i) m0 = fmin(m0, red[i]);
+    if (!isfinite(m0)) {
+        if (cg == 0 && tid == 0) d.st->status = -4;  // MPPI_E_NONFINITE: U and n unchanged
         return;
     }
-    const InstDesc* descs = reinterpret_cast<const InstDesc*>(
-        reinterpret_cast<const unsigned char*>(hdr) + hdr->off_descs);
-    if ((int)blockIdx.x >= hdr->n_inst) return;
-    const InstDesc& d = descs[blockIdx.x];
-    if (d.per_step) merge_per_step(d);
+
+    const int slot = tid % kSlots, chunk = tid / kSlots;
+    const bool worked = slot < nst;
+    const int t = w0 + min(slot, nst - 1);
+    const int per = (n + kChunks - 1) / kChunks;
+    const int b0 = min(chunk * per, n), b1 = min(b0 + per, n);
+    const double* col = rows + 5 * (size_t)t;
+    // per-step minimum: chunks, then the chunks in order
+    double ml = INFINITY;
+    if (worked)
+        for (int b = b0; b < b1; ++b) ml = fmin(ml, col[(size_t)b * stride]);
+    part[4 * tid] = ml;
+    __syncthreads();
+    if (tid < nst) {
+        double m = INFINITY;
+        for (int c = 0; c < kChunks; ++c) m = fmin(m, part[4 * (c * kSlots + tid)]);
+        mt[tid] = m;
+    }
+    __syncthreads();
+    // shifted sums of the chunk's tiles in tile order
+    double z = 0.0, qq = 0.0, na = 0.0, nd = 0.0;
+    if (worked) {
+        const double m = mt[slot];
+        for (int b = b0; b < b1; ++b) {
+            const double* h = col + (size_t)b * stride;
+            const double sc = isfinite(h[0]) ? exp(-(h[0] - m) / d.lambda) : 0.0;
+            z += h[1] * sc;
+            qq += h[2] * sc * sc;
+            na += h[3] * sc;
+            nd += h[4] * sc;
+        }
+    }
+    __syncthreads();  // the minima in part are read
+    part[4 * tid] = z;
+    part[4 * tid + 1] = qq;
+    part[4 * tid + 2] = na;
+    part[4 * tid + 3] = nd;
+    __syncthreads();
+    double zt = 0.0, qt = 0.0;
+    if (tid < nst) {
+        double sa = 0.0, sd = 0.0;
+        for (int c = 0; c < kChunks; ++c) {
+            const double* pc = part + 4 * (c * kSlots + tid);
+            zt += pc[0];
+            qt += pc[1];
+            sa += pc[2];
+            sd += pc[3];
+        }
+        const int tt = w0 + tid;
+        const double* u_old = d.smooth ? d.partials + (size_t)n * stride : d.U;
+        const double ua = u_old[2 * tt] + sa / zt;
+        const double ud = u_old[2 * tt + 1] + sd / zt;
+        if (d.smooth) {
+            un[2 * tid] = ua;
+            un[2 * tid + 1] = ud;
+        } else {
+            d.U[2 * tt] = ua;
+            d.U[2 * tt + 1] = ud;
+        }
+        if (cg == 0 && tt == 0) {
+            d.st->s_min = mt[0];
+            d.st->z = zt;
+            d.st->log_z = log(zt);
+            d.st->ess = zt * zt / qt;
+            d.st->status = 0;
+            d.st->n_iter = d.st->n_iter + 1ull;
+        }
+    }
+    if (d.smooth) {
+        __syncthreads();
+        const int own = 2 * (s1 - s0);
+        if (tid < own) {
+            const int ts = s0 + (tid >> 1), c2 = tid & 1;
+            auto at = [&](int i) { return un[2 * (min(max(i, 0), T - 1) - w0) + c2]; };
+            const double sm = -3.0 * at(ts - 2) + 12.0 * at(ts - 1) + 17.0 * at(ts) +
+                              12.0 * at(ts + 1) - 3.0 * at(ts + 2);
+            d.U[2 * s0 + tid] = sm / 35.0;
+        }
+    }
 }
 
-hipError_t launch_merge_per_step(const InstDesc* d0, const BatchHdr* hdr_dev, int n_blocks,
-                                 hipStream_t stream)
+// One instance (d0, hdr == nullptr) or instance blockIdx.y of a batch.
+__global__ __launch_bounds__(kBlock) void k_combine(InstDesc d0, const BatchHdr* __restrict__ hdr)
+{
+    if (!hdr) {
+        if (d0.per_step) combine_per_step(d0, blockIdx.x);
+        else combine(d0, blockIdx.x);
+        return;
+    }
+    if ((int)blockIdx.y >= hdr->n_inst) return;
+    const InstDesc& d = reinterpret_cast<const InstDesc*>(
+        reinterpret_cast<const unsigned char*>(hdr) + hdr->off_descs)[blockIdx.y];
+    if (d.per_step) combine_per_step(d, blockIdx.x);
+    else combine(d, blockIdx.x);
+}
+
+hipError_t launch_combine(const InstDesc* d0, const BatchHdr* hdr_dev, int groups, int n_inst,
+                          hipStream_t stream)
 {
     InstDesc zero;
     memset(&zero, 0, sizeof zero);
-    hipLaunchKernelGGL(k_merge_per_step, dim3(n_blocks), dim3(kBlock), 0, stream,
+    const size_t smem = sizeof(double) * (kDirect + 64 + 4 * kBlock + 8 + 16);
+    hipLaunchKernelGGL(k_combine, dim3(groups, n_inst), dim3(kBlock), smem, stream,
                        d0 ? *d0 : zero, hdr_dev);
     return hipGetLastError();
 }

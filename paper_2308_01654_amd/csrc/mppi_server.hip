@@ -163,7 +163,7 @@ size_t request_bytes(const mppi_config& c, int lanes)
 {
     const size_t tiles = (size_t)(c.K + (kBlock / lanes) - 1) / (kBlock / lanes);
     size_t b = a256(sizeof(float) * c.K) + a256(sizeof(float2) * (size_t)c.T * c.K) +
-               a256(sizeof(double) * tiles * partial_stride(c.T, c.per_step_weights));
+               a256(sizeof(double) * partial_doubles(c.T, c.per_step_weights, tiles));
     if (c.per_step_weights)
         b += a256(sizeof(float) * (size_t)c.T * c.K) + a256(sizeof(double) * (size_t)c.T * c.K);
     return b;
@@ -281,7 +281,7 @@ void scheduler_loop(mppi_server* srv)
             ex[i].eps = reinterpret_cast<float2*>(base);
             base += a256(sizeof(float2) * (size_t)c.T * c.K);
             ex[i].partials = reinterpret_cast<double*>(base);
-            base += a256(sizeof(double) * tiles * partial_stride(c.T, c.per_step_weights));
+            base += a256(sizeof(double) * partial_doubles(c.T, c.per_step_weights, tiles));
             ex[i].q = nullptr;
             ex[i].Stk = nullptr;
             if (c.per_step_weights) {
