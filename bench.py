@@ -33,6 +33,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+from paper_2308_01654_amd.hip_events import HipEvents, time_steps  # noqa: E402
+
 PEAK_FP32_TFLOPS = 157.3      # MI355X published FP32 vector peak
 METRIC = "rollout-steps/s (K=8192,T=100) + p99 replan latency, served vs plain MPPI"
 KERNEL_SRC = os.path.join(ROOT, "paper_2308_01654_amd", "csrc", "mppi_kernels.hip")
@@ -45,38 +47,6 @@ def flops_per_rollout_step(n_wp, n_c, n_ego):
     and the compensated sum; 6 per waypoint; 7 per ego-circle x obstacle-circle
     pair."""
     return 73 + 6 * n_wp + 7 * n_ego * n_c
-
-
-class HipEvents:
-    """hipEvent timing on a given stream through the HIP runtime the library
-    itself links (found in this process's memory map)."""
-
-    def __init__(self):
-        paths = [l.split()[-1] for l in open("/proc/self/maps") if "libamdhip64" in l]
-        if not paths:
-            raise RuntimeError("HIP runtime not loaded")
-        H = ctypes.CDLL(paths[0])
-        vp = ctypes.c_void_p
-        H.hipEventCreate.argtypes = [ctypes.POINTER(vp)]
-        H.hipEventRecord.argtypes = [vp, vp]
-        H.hipEventSynchronize.argtypes = [vp]
-        H.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), vp, vp]
-        H.hipEventDestroy.argtypes = [vp]
-        self.H = H
-
-    def event(self):
-        e = ctypes.c_void_p()
-        assert self.H.hipEventCreate(ctypes.byref(e)) == 0
-        return e
-
-    def record(self, e, stream):
-        assert self.H.hipEventRecord(e, ctypes.c_void_p(stream)) == 0
-
-    def elapsed_ms(self, a, b):
-        assert self.H.hipEventSynchronize(b) == 0
-        ms = ctypes.c_float()
-        assert self.H.hipEventElapsedTime(ctypes.byref(ms), a, b) == 0
-        return float(ms.value)
 
 
 def kernel_source_hash():
@@ -148,13 +118,8 @@ def sweep():
             for _ in range(3):
                 pl.step_resident(sc["x0"])
             pl.sync()
-            n = 20 if K * T < 10**7 else 3
-            pl.set_profiling(True)
-            for _ in range(n):
-                pl.step_resident(sc["x0"])
-            pr = pl.profile()
-            pl.set_profiling(False)
-            ms = pr["iter_ms"] / pr["iter_launches"]
+            n = 40 if K * T < 10**7 else 3
+            ms = time_steps(pl, sc["x0"], n)
             print("%-13s K=%-7d T=%-4d lanes=%-2d kernel %.4f ms  %.3e steps/s  %.1f TFLOP/s"
                   % (sc["name"], K, T, lanes, ms, K * T / (ms * 1e-3), F * K * T / (ms * 1e-3) / 1e12),
                   flush=True)
@@ -162,49 +127,39 @@ def sweep():
 
 
 def _iteration_ms(p, x0, wp, circ, warmup, steps):
-    """Average device time of one iteration (HIP events around its launches)."""
+    """Average device time of one iteration (one HIP event pair around
+    `steps` back-to-back steps)."""
     from paper_2308_01654_amd import mppi
     pl = mppi.Planner(p)
     pl.set_scene(x0, wp, circ)
     for _ in range(warmup):
         pl.step_resident(x0)
     pl.sync()
-    pl.set_profiling(True)
-    for _ in range(steps):
-        pl.step_resident(x0)
-    pl.sync()
-    prof = pl.profile()
+    ms = time_steps(pl, x0, steps)
     pl.close()
-    return round(prof["iter_ms"] / max(prof["iter_launches"], 1), 5)
+    return round(ms, 5)
 
 
 def alg1_output(p, x0, wp, circ, warmup, steps):
-    """The last steps of Alg. 1 on the same workload: iteration kernel time
-    with Savitzky-Golay smoothing in the root merge, the latency of one
+    """The last steps of Alg. 1 on the same workload: iteration time with
+    Savitzky-Golay smoothing in the combine, the latency of one
     optimal-trajectory call (device rollout + copies, host clock), and the
-    iteration time with per-step (cost-to-go) weights, whose launches are
-    the iteration kernel and the per-instance merge kernel."""
+    iteration time with per-step (cost-to-go) weights."""
     from paper_2308_01654_amd import mppi
     ps = dict(p)
     ps["smoothing"] = 1
+    smooth_ms = _iteration_ms(ps, x0, wp, circ, warmup, steps)
     pl = mppi.Planner(ps)
     pl.set_scene(x0, wp, circ)
-    for _ in range(warmup):
-        pl.step_resident(x0)
+    pl.step_resident(x0)
     pl.sync()
-    pl.set_profiling(True)
-    for _ in range(steps):
-        pl.step_resident(x0)
-    pl.sync()
-    prof = pl.profile()
-    pl.set_profiling(False)
     lat = []
     for _ in range(50):
         a = time.perf_counter()
         pl.trajectory()
         lat.append((time.perf_counter() - a) * 1e3)
     pl.close()
-    return {"smoothing_kernel_ms": round(prof["iter_ms"] / max(prof["iter_launches"], 1), 5),
+    return {"smoothing_iteration_ms": smooth_ms,
             "trajectory_call_ms_p50": round(float(np.percentile(lat, 50)), 4),
             "trajectory_call_ms_p99": round(float(np.percentile(lat, 99)), 4),
             "per_step_weights_iteration_ms": _iteration_ms(dict(p, per_step=1), x0, wp, circ,
@@ -212,7 +167,7 @@ def alg1_output(p, x0, wp, circ, warmup, steps):
 
 
 def paper_cost_kernels(steps=50):
-    """Iteration kernel time (HIP events, tuned launch shape) of the paper's
+    """Iteration time (HIP events, tuned launch shape) of the paper's
     full-cost scenarios at the Table I shape (K=2560, T=16, dt=0.25), with
     the 4-state model and with the 5-state model of eq. (5)."""
     from paper_2308_01654_amd import mppi, scenes
@@ -220,18 +175,8 @@ def paper_cost_kernels(steps=50):
     cases = [f() for f in (scenes.paper_merge, scenes.paper_avoid, scenes.paper_follow)]
     cases += [scenes.paper_model5(sc) for sc in list(cases)]
     for sc in cases:
-        pl = mppi.Planner(sc["params"])
-        pl.set_scene(sc["x0"], sc["waypoints"], sc["circles"])
-        for _ in range(5):
-            pl.step_resident(sc["x0"])
-        pl.sync()
-        pl.set_profiling(True)
-        for _ in range(steps):
-            pl.step_resident(sc["x0"])
-        pl.sync()
-        prof = pl.profile()
-        pl.close()
-        out[sc["name"] + "_kernel_ms"] = round(prof["iter_ms"] / max(prof["iter_launches"], 1), 5)
+        out[sc["name"] + "_iteration_ms"] = _iteration_ms(sc["params"], sc["x0"], sc["waypoints"],
+                                                          sc["circles"], 5, steps)
     return out
 
 
@@ -317,6 +262,8 @@ def main(argv=None):
     ap.add_argument("--served-seconds", type=float, default=5.0,
                     help="duration of the served load (0 skips the served comparison)")
     ap.add_argument("--plain-seconds", type=float, default=1.0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the smoothing, trajectory, per-step and paper-scenario timings")
     args = ap.parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the iteration on a single "
@@ -346,7 +293,6 @@ def main(argv=None):
     pl.sync()
 
     # ---- timed region: inputs resident in HBM, one iteration per step ----
-    pl.set_profiling(True)
     e0, e1 = ev.event(), ev.event()
     ev.record(e0, stream)
     t0 = time.perf_counter()
@@ -355,21 +301,31 @@ def main(argv=None):
     ev.record(e1, stream)
     pl.sync()
     t1 = time.perf_counter()
-    prof = pl.profile()
-    pl.set_profiling(False)
     ms = ev.elapsed_ms(e0, e1)
     ms_per_step = ms / args.steps
     value = K * T * args.steps / (ms * 1e-3)
+    # ---- kernel times: the same steps again with the library's per-launch
+    # HIP events on the handle's stream (kept out of the timed region: the
+    # extra event records between the two kernels of a step cost host time)
+    pl.set_profiling(True)
+    for _ in range(args.steps):
+        pl.step_resident(x0)
+    prof = pl.profile()
+    pl.set_profiling(False)
     st = pl.stats()
 
-    kern_ms = prof["iter_ms"] / max(prof["iter_launches"], 1)
+    # the dominant kernel: the iteration kernel alone (its own event pair);
+    # an iteration is that kernel and the combine kernel (the timed region)
+    kern_ms = prof["rollout_ms"] / max(prof["rollout_launches"], 1)
+    iter_ms = ms_per_step
     F = flops_per_rollout_step(n_wp, n_c, n_ego)
     achieved = F * K * T / (kern_ms * 1e-3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS,
                     unit="TFLOP/s", frac=round(achieved / PEAK_FP32_TFLOPS, 4),
                     traffic=load_traffic(K * T),
-                    kernel="k_batch<G,NE> (fused sample/rollout/cost/weight/update)",
-                    kernel_ms=round(kern_ms, 5), flops_per_rollout_step=F,
+                    kernel="k_batch<G,NE,M5> (sampling, rollouts, costs, tile partials)",
+                    kernel_ms=round(kern_ms, 5), iteration_ms=round(iter_ms, 5),
+                    combine_ms=round(iter_ms - kern_ms, 5), flops_per_rollout_step=F,
                     lanes_per_sample=st["lanes"])
 
     # ---- plain one-at-a-time replan latency (host call to controls on host) ----
@@ -388,8 +344,10 @@ def main(argv=None):
     pl.sync()
     pcie_value = K * T * 50 / (time.perf_counter() - a)
     pl.close()
-    smooth = alg1_output(p, x0, wp, circ, args.warmup, args.steps)
-    smooth.update(paper_cost_kernels())
+    smooth = None
+    if not args.no_extras:
+        smooth = alg1_output(p, x0, wp, circ, args.warmup, args.steps)
+        smooth.update(paper_cost_kernels())
 
     out = {
         "metric": METRIC,

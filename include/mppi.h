@@ -128,12 +128,15 @@ typedef struct mppi_iter_stats {
     int32_t lanes_per_sample; /* launch shape used by the last step                */
 } mppi_iter_stats;
 
-/* Accumulated device time per kernel while profiling is on (HIP events). */
+/* Accumulated device time while profiling is on (HIP events). */
 typedef struct mppi_profile {
-    double iter_ms;        /* fused sample/rollout/weight/update kernel               */
+    double iter_ms;        /* iterations: iteration kernel and combine kernel         */
     int64_t iter_launches;
     double aux_ms;         /* every other kernel of the handle                        */
     int64_t aux_launches;
+    double rollout_ms;     /* the iteration kernel alone (sampling, rollouts, costs,
+                              tile partials) of single-instance steps                */
+    int64_t rollout_launches;
 } mppi_profile;
 
 /* ---- single planning instance -------------------------------------------- */

@@ -3,7 +3,7 @@
 For every shape bucket -- K in powers of two, T buckets (<=32, <=64, <=128,
 <=256, >256) and circle-count buckets (0, <=16, <=64, <=256, >256) -- it runs
 a representative sine-lane instance with every lanes-per-sample shape
-(1, 2, 4, 8, 16), times the iteration kernel with HIP events, and writes the
+(1, 2, 4, 8, 16), times whole iterations with HIP events, and writes the
 fastest shape as a line "k_log2 t_bucket c_bucket lanes" of ``tuning.txt``.
 The library reads that file at its first launch (next to libmppi.so, or the
 file named by MPPI_TUNING_FILE).  A bucket's choice depends only on the
@@ -41,16 +41,13 @@ def shape_scene(K, T, n_c):
 
 def time_shape(sc, lanes, reps):
     from paper_2308_01654_amd import mppi
+    from paper_2308_01654_amd.hip_events import time_steps
     pl = mppi.Planner(sc["params"], lanes=lanes)
     try:
         pl.set_scene(sc["x0"], sc["waypoints"], sc["circles"])
         pl.step_resident(sc["x0"])
         pl.sync()
-        pl.set_profiling(True)
-        for _ in range(reps):
-            pl.step_resident(sc["x0"])
-        pr = pl.profile()
-        return pr["iter_ms"] / pr["iter_launches"]
+        return time_steps(pl, sc["x0"], reps)
     finally:
         pl.close()
 
@@ -64,7 +61,7 @@ def main(argv=None):
     ap.add_argument("--c-buckets", default="0,1,2,3,4")
     args = ap.parse_args(argv)
     lines = ["# lanes-per-sample tuning table of the MPPI iteration kernel",
-             "# written by: python -m paper_2308_01654_amd.autotune (HIP-event kernel time, "
+             "# written by: python -m paper_2308_01654_amd.autotune (HIP-event iteration time, "
              "fastest of lanes 1/2/4/8/16)",
              "# columns: k_log2 t_bucket c_bucket lanes   (t: <=32,<=64,<=128,<=256,>256; "
              "c: 0,<=16,<=64,<=256,>256)"]
@@ -75,7 +72,7 @@ def main(argv=None):
             T = T_REPS[tb]
             for cb in [int(v) for v in args.c_buckets.split(",")]:
                 sc = shape_scene(K, T, C_REPS[cb])
-                reps = 5 if K * T < 2_000_000 else 2
+                reps = 20 if K * T < 2_000_000 else 3
                 times = {g: time_shape(sc, g, reps) for g in LANES if g <= T}
                 best = min(times, key=times.get)
                 lines.append("%d %d %d %d" % (kb, tb, cb, best))

@@ -229,11 +229,23 @@ int auto_lanes(const mppi_config& c, int n_c)
 
 // ---- profiling --------------------------------------------------------------------
 
+// Events come from the handle's pool (created on first use) so that
+// profiling adds little host time between launches.
+static hipError_t pool_event(mppi_t* h, hipEvent_t* e)
+{
+    if (!h->event_pool.empty()) {
+        *e = h->event_pool.back();
+        h->event_pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
+}
+
 mppi_status record_launch(mppi_t* h, int kind, hipEvent_t* a)
 {
     (void)kind;
     if (!h || !h->prof) return MPPI_OK;
-    HIP_TRY(hipEventCreate(a));
+    HIP_TRY(pool_event(h, a));
     HIP_TRY(hipEventRecord(*a, h->stream));
     return MPPI_OK;
 }
@@ -242,7 +254,7 @@ mppi_status record_end(mppi_t* h, int kind, hipEvent_t a)
 {
     if (!h || !h->prof) return MPPI_OK;
     hipEvent_t b;
-    HIP_TRY(hipEventCreate(&b));
+    HIP_TRY(pool_event(h, &b));
     HIP_TRY(hipEventRecord(b, h->stream));
     h->events.push_back(ProfEvent{a, b, kind});
     return MPPI_OK;
@@ -257,8 +269,8 @@ static mppi_status drain_profile(mppi_t* h)
         HIP_TRY(hipEventElapsedTime(&ms, e.a, e.b));
         h->prof_ms[e.kind] += ms;
         h->prof_n[e.kind] += 1;
-        (void)hipEventDestroy(e.a);
-        (void)hipEventDestroy(e.b);
+        h->event_pool.push_back(e.a);
+        h->event_pool.push_back(e.b);
     }
     h->events.clear();
     return MPPI_OK;
@@ -294,6 +306,7 @@ void handle_release(mppi_t* h)
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
     }
+    for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
     (void)hipFree(h->U);
     (void)hipFree(h->S);
     (void)hipFree(h->eps);
@@ -388,7 +401,7 @@ mppi_status handle_create(const mppi_config* cfg, void* hip_stream, bool with_sc
 // Whether the tiles of d keep their perturbations in LDS (see kLdsShared).
 static void choose_eps_stage(InstDesc& d, bool alone)
 {
-    const LdsLayout L = lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes, 1);
+    const LdsLayout L = lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes, 1, d.per_step);
     d.eps_stage = L.eps_staged && (L.total <= kLdsShared ||
                                    (alone && d.n_tiles <= 512 && L.total <= kLdsAlone));
 }
@@ -604,7 +617,8 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
         prefix[j] = (int)total;
         total += descs[j].n_tiles;
         smem = std::max(smem, lds_layout(descs[j].n_wp, descs[j].n_c, descs[j].T,
-                                         kBlock / descs[j].lanes, descs[j].eps_stage).total);
+                                         kBlock / descs[j].lanes, descs[j].eps_stage,
+                                         descs[j].per_step).total);
         any_shift |= sh;
         combine_g = std::max(combine_g, combine_groups(descs[j].T));
     }
@@ -774,11 +788,15 @@ mppi_status mppi_step_resident(mppi_t* h, const double x0[4])
     InstDesc d;
     fill_desc(d, h, x0, h->origin, h->scene, h->lay, h->n_wp, h->n_c, 0);
     choose_eps_stage(d, true);
-    const size_t smem = lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes, d.eps_stage).total;
+    const size_t smem =
+        lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes, d.eps_stage, d.per_step).total;
     hipEvent_t a = nullptr;
     if ((s = record_launch(h, 0, &a)) != MPPI_OK) return s;
+    hipEvent_t a2 = nullptr;
+    if ((s = record_launch(h, 2, &a2)) != MPPI_OK) return s;
     HIP_TRY(launch_batch(d.lanes, active_ego(d.n_ego, d.n_c), d.model, &d, nullptr, 0, d.n_tiles,
                          smem, h->stream));
+    if ((s = record_end(h, 2, a2)) != MPPI_OK) return s;
     HIP_TRY(launch_combine(&d, nullptr, combine_groups(d.T), 1, h->stream));
     if ((s = record_end(h, 0, a)) != MPPI_OK) return s;
     h->last_lanes = d.lanes;
@@ -1042,8 +1060,15 @@ mppi_status mppi_set_profiling(mppi_t* h, int32_t on)
     if ((s = drain_profile(h)) != MPPI_OK) return s;
     h->prof = on != 0;
     if (on) {
-        h->prof_ms[0] = h->prof_ms[1] = 0.0;
-        h->prof_n[0] = h->prof_n[1] = 0;
+        h->prof_ms[0] = h->prof_ms[1] = h->prof_ms[2] = 0.0;
+        h->prof_n[0] = h->prof_n[1] = h->prof_n[2] = 0;
+        // events for a few hundred profiled steps, created now rather than
+        // between launches
+        while (h->event_pool.size() < 1024) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            h->event_pool.push_back(e);
+        }
     }
     return MPPI_OK;
 }
@@ -1058,6 +1083,8 @@ mppi_status mppi_get_profile(mppi_t* h, mppi_profile* out)
     out->iter_launches = h->prof_n[0];
     out->aux_ms = h->prof_ms[1];
     out->aux_launches = h->prof_n[1];
+    out->rollout_ms = h->prof_ms[2];
+    out->rollout_launches = h->prof_n[2];
     return MPPI_OK;
 }
 

@@ -39,7 +39,8 @@ struct BatchWs {
 
 struct ProfEvent {
     hipEvent_t a, b;
-    int kind;  // 0 = iteration kernel, 1 = auxiliary
+    int kind;  // 0 = iteration (iteration and combine kernels), 1 = auxiliary,
+               // 2 = iteration kernel alone
 };
 
 // Offsets of the four scene arrays inside a staged scene block.
@@ -103,8 +104,9 @@ struct mppi {
     // profiling
     bool prof = false;
     std::vector<mppi_impl::ProfEvent> events;
-    double prof_ms[2] = {0.0, 0.0};
-    int64_t prof_n[2] = {0, 0};
+    std::vector<hipEvent_t> event_pool;  // recorded and read events, for reuse
+    double prof_ms[3] = {0.0, 0.0, 0.0};
+    int64_t prof_n[3] = {0, 0, 0};
 };
 
 namespace mppi_impl {

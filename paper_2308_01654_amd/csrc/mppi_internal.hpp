@@ -125,7 +125,8 @@ struct InstDesc {
     float2* eps;          // [T][K]
     double* partials;     // partial_doubles(T, per_step, n_tiles)
     float* q;             // [T][K] stage costs (per-step weights)
-    double* Stk;          // [T][K] cost-to-go (per-step weights)
+    double* Stk;          // [T][K] cost-to-go (per-step weights; row 0 always, the
+                          // other rows only when a tile works in global memory)
     DevState* st;         // followed by the combine-tree tickets
 };
 
@@ -147,12 +148,16 @@ struct BatchHdr {
 
 // Dynamic LDS layout of the iteration kernel for a given scene size.
 struct LdsLayout {
-    size_t c_pv, wp_box, wp_xy, U, red, wp_vref, wp_yaw, c_rr, omega, blk, eps, total;
-    int eps_staged;  // the tile's applied perturbations are kept at eps
+    size_t c_pv, wp_box, wp_xy, U, red, wp_vref, wp_yaw, c_rr, omega, eps, qs, ss, total;
+    int eps_staged;  // the tile's applied perturbations are kept at eps, and
+                     // with per-step weights its stage costs at qs and its
+                     // cost-to-go at ss
 };
 
-// Largest LDS copy of a tile's applied perturbations ([2T][spb + 1] floats).
-constexpr size_t kEpsStageMax = 32 << 10;
+// Largest LDS copy of a tile's applied perturbations ([2T][spb + 1] floats)
+// and, with per-step weights, stage costs ([T][spb + 1] floats) and
+// cost-to-go ([T][spb] doubles).
+constexpr size_t kEpsStageMax = 48 << 10;
 // The copy is made when the workgroup's LDS stays within kLdsShared (five
 // workgroups per compute unit), or within kLdsAlone for an instance launched
 // alone with at most two tiles per compute unit (256 units).
@@ -165,7 +170,8 @@ constexpr int kChunk = 8;
 
 inline __host__ __device__ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int spb, int eps_stage)
+inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int spb, int eps_stage,
+                                                int per_step)
 {
     LdsLayout L;
     size_t o = 0;
@@ -178,11 +184,14 @@ inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int sp
     L.wp_yaw = o;  o += (size_t)n_wp * 4;
     L.c_rr = o;    o += (size_t)n_c * 4;
     L.omega = o;   o += (size_t)spb * 4;
-    o = align_up(o, 8);
-    L.blk = o;     o += (size_t)spb * 8;   // block-start position per sample
     const size_t eb = (size_t)2 * T * (spb + 1) * 4;
-    L.eps_staged = eps_stage && eb <= kEpsStageMax;
+    const size_t qb = per_step ? align_up((size_t)T * (spb + 1) * 4, 8) : 0;
+    const size_t sb = per_step ? (size_t)T * spb * 8 : 0;
+    L.eps_staged = eps_stage && eb + qb + sb <= kEpsStageMax;
     L.eps = o;     o += L.eps_staged ? eb : 0;
+    o = align_up(o, 8);
+    L.qs = o;      o += L.eps_staged ? qb : 0;
+    L.ss = o;      o += L.eps_staged ? sb : 0;
     L.total = align_up(o, 16);
     return L;
 }

@@ -86,8 +86,9 @@ struct Lds {
     float* wp_yaw;
     float* c_rr;
     float* omega;
-    float2* blk;
     float* eps;  // [2T][spb + 1]: column 2t + c, sample j at (2t + c)(spb + 1) + j
+    float* qs;   // [T][spb + 1] stage costs (per-step weights)
+    double* ss;  // [T][spb] cost-to-go (per-step weights)
 };
 
 __device__ __forceinline__ Lds lds_bind(unsigned char* base, const LdsLayout& L)
@@ -102,8 +103,9 @@ __device__ __forceinline__ Lds lds_bind(unsigned char* base, const LdsLayout& L)
     s.wp_yaw = reinterpret_cast<float*>(base + L.wp_yaw);
     s.c_rr = reinterpret_cast<float*>(base + L.c_rr);
     s.omega = reinterpret_cast<float*>(base + L.omega);
-    s.blk = reinterpret_cast<float2*>(base + L.blk);
     s.eps = reinterpret_cast<float*>(base + L.eps);
+    s.qs = reinterpret_cast<float*>(base + L.qs);
+    s.ss = reinterpret_cast<double*>(base + L.ss);
     return s;
 }
 
@@ -249,6 +251,37 @@ __device__ __forceinline__ int dpp_i(int idv, int x)
 }
 constexpr int kIntMax = 0x7fffffff;
 constexpr int kIntMin = (int)0x80000000u;
+
+// Prefix sums inside aligned groups of G lanes (G <= 16, so a group lies in
+// one DPP row): the inclusive sum up to lane r of the group, the value of
+// lane r - 1 (0 for the first lane), and the group's last lane's value.
+template <int N>
+__device__ __forceinline__ float dpp_shr(float v)
+{
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x110 + N, 0xf, 0xf, true));
+}
+template <int G>
+__device__ __forceinline__ float seg_scan(float v, int r)
+{
+    if (G >= 2) { const float u = dpp_shr<1>(v); v += r >= 1 ? u : 0.0f; }
+    if (G >= 4) { const float u = dpp_shr<2>(v); v += r >= 2 ? u : 0.0f; }
+    if (G >= 8) { const float u = dpp_shr<4>(v); v += r >= 4 ? u : 0.0f; }
+    if (G >= 16) { const float u = dpp_shr<8>(v); v += r >= 8 ? u : 0.0f; }
+    return v;
+}
+template <int G>
+__device__ __forceinline__ float seg_prev(float incl, int r)
+{
+    if (G == 1) return 0.0f;
+    const float u = dpp_shr<1>(incl);
+    return r >= 1 ? u : 0.0f;
+}
+template <int G>
+__device__ __forceinline__ float group_last(float v, int gbase)
+{
+    return G > 1 ? __shfl(v, gbase + G - 1, 64) : v;
+}
 
 // Wave-wide reduction stages: swap neighbours and quad halves, mirror inside
 // half rows and rows (every lane then holds its row's result), broadcast lane
@@ -601,7 +634,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     constexpr int SPB = kBlock / G;  // samples per tile
     const int T = d.T;
     const int K = d.K;
-    const LdsLayout L = lds_layout(d.n_wp, d.n_c, T, SPB, d.eps_stage);
+    const LdsLayout L = lds_layout(d.n_wp, d.n_c, T, SPB, d.eps_stage, d.per_step);
     const Lds s = lds_bind(smem, L);
 
     for (int i = tid; i < d.n_c; i += kBlock) {
@@ -661,9 +694,9 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     }
     float x = d.px0, y = d.py0, th = d.th0, v = d.v0;
     float delta = d.steer0;  // steering angle (5-state model only)
-    float c = __cosf(th), sn = __sinf(th);
     float S = 0.0f, comp = 0.0f;  // Kahan pair of this lane's steps
     int seed = -1;                // closest chunk at this lane's previous step
+    const int gbase = tid & ~(G - 1);  // first lane of this sample's group
     for (int t0 = 0; t0 < T; t0 += G) {
         const int tm = t0 + r;
         // The lane's step within the block, opaque to the compiler so that the
@@ -674,92 +707,84 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         const int tc = tm < T ? tm : T - 1;
         // This lane's step: perturbation, the state-independent part of the
         // noise check (control bounds) and -- for the steering-angle control --
-        // its tangent, computed once per step and handed to the G lanes that
-        // integrate it.  With the 5-state model the second control is the
-        // steering rate, handed over as it is.
+        // its tangent.  With the 5-state model the second control is the
+        // steering rate.
         const float2 em = draw_noise(d, kk, tc, n_iter);
         const float2 Um = s.U[tc];
         const float a0m = fminf(fmaxf(Um.x + em.x, d.a_min), d.a_max);
         const float dlm = fminf(fmaxf(Um.y + em.y, d.d_min), d.d_max);
         const float tnm = M5 ? dlm : __tanf(dlm);
-        // position at the start of the block, for c_target of its first step
-        if (d.w_target != 0.0f && r == 0) s.blk[grp] = make_float2(x, y);
-        float mx = 0.f, my = 0.f, mc = 1.f, ms = 0.f, mv = 0.f, ma = 0.f, mth = 0.f;
-        constexpr int PF = G < 4 ? G : 4;  // steps whose inputs are exchanged together
-        float apf[PF], tpf[PF];
+        // Speed: the speed cap of the noise check depends on the speed before
+        // each step, so the G lanes run the speed recursion of the block
+        // together (accelerations exchanged PF at a time) and each keeps the
+        // speed before its own step.  Steps past the horizon (last block) are
+        // run too; the lanes that own them are inactive.
+        float vr = v;
+        constexpr int PF = G < 4 ? G : 4;
+        float apf[PF];
 #pragma unroll
         for (int i = 0; i < G; ++i) {
             if (i % PF == 0) {
 #pragma unroll
-                for (int u = 0; u < PF; ++u) {
-                    apf[u] = a0m;
-                    tpf[u] = tnm;
-                    if (G > 1) {
-                        const int src = (tid & ~(G - 1)) + i + u;
-                        apf[u] = __shfl(a0m, src, 64);
-                        tpf[u] = __shfl(tnm, src, 64);
-                    }
-                }
+                for (int u = 0; u < PF; ++u)
+                    apf[u] = G > 1 ? __shfl(a0m, gbase + i + u, 64) : a0m;
             }
-            // Steps past the horizon (last block) are integrated too: only
-            // lanes whose own step lies past it keep their states, and those
-            // lanes are inactive.  The walk stays one basic block.
-            //
+            vr = i == rb ? v : vr;
             // noise check: speed cap, braking bound last
             float a = fminf(apf[i % PF], (d.v_max - v) * d.inv_dt);
             a = fmaxf(a, d.a_min);
-            // eq. (5), explicit Euler from the old state
-            const float vdt = v * d.dt;
-            x = fmaf(vdt, c, x);
-            y = fmaf(vdt, sn, y);
-            if (M5) {
-                // eq. (5): the heading turns with the steering angle before
-                // the step, which then moves at the applied rate
-                th = fmaf(vdt * d.inv_L, __tanf(delta), th);
-                delta = fmaf(d.dt, tpf[i % PF], delta);
-            } else {
-                th = fmaf(vdt * d.inv_L, tpf[i % PF], th);
-            }
             v = fmaf(d.dt, a, v);
-            c = __cosf(th);
-            sn = __sinf(th);
-            const bool own = i == rb;
-            mx = own ? x : mx;
-            my = own ? y : my;
-            mv = own ? v : mv;
-            ma = own ? a : ma;
-            mth = own ? th : mth;
         }
-        // the heading's cosine and sine at this lane's step, recomputed from the
-        // kept heading with the instructions of the walk (same bits)
-        mc = __cosf(mth);
-        ms = __sinf(mth);
+        // the own step's applied acceleration and the speed after it (the
+        // operations of the recursion: the same bits)
+        float ma = fminf(a0m, (d.v_max - vr) * d.inv_dt);
+        ma = fmaxf(ma, d.a_min);
+        const float mv = fmaf(d.dt, ma, vr);
+        // Eq. (5), explicit Euler: given the speeds, heading and position are
+        // sums of per-step increments, formed by prefix sums over the G lanes
+        // of the group (each lane adds its own step's increment).  With the
+        // 5-state model the heading turns with the steering angle before the
+        // step, itself the sum of the applied rates.
+        const float vdt = vr * d.dt;
+        float tn = tnm;
+        float ddel_blk = 0.0f;
+        if (M5) {
+            const float dincl = seg_scan<G>(d.dt * tnm, r);
+            tn = __tanf(delta + seg_prev<G>(dincl, r));
+            ddel_blk = group_last<G>(dincl, gbase);
+        }
+        const float thincl = seg_scan<G>(vdt * d.inv_L * tn, r);
+        const float thb = th + seg_prev<G>(thincl, r);  // heading before the own step
+        const float mth = th + thincl;                  // and after it
+        const float xincl = seg_scan<G>(vdt * __cosf(thb), r);
+        const float yincl = seg_scan<G>(vdt * __sinf(thb), r);
+        const float mx = x + xincl, my = y + yincl;
+        // position before this lane's step (for c_target): the previous
+        // lane's position after its step, the block start for the first
+        float pxp = 0.0f, pyp = 0.0f;
+        if (d.w_target != 0.0f) {
+            pxp = x + seg_prev<G>(xincl, r);
+            pyp = y + seg_prev<G>(yincl, r);
+        }
+        // the state at the end of the block (the last lane's), for the next
+        x += group_last<G>(xincl, gbase);
+        y += group_last<G>(yincl, gbase);
+        th += group_last<G>(thincl, gbase);
+        if (M5) delta += ddel_blk;
+        const float mc = __cosf(mth), ms = __sinf(mth);
         const float mUa = Um.x, mUd = Um.y;
         const float mea = ma - Um.x, med = dlm - Um.y;
         const bool act = tm < T;
-        // position before this lane's step (for c_target): the block start for
-        // the first step of the block, else the state the previous lane kept
-        float pxp = 0.0f, pyp = 0.0f;
-        if (d.w_target != 0.0f) {
-            const float2 b0 = s.blk[grp];  // written by this wave's lane r = 0
-            pxp = b0.x;
-            pyp = b0.y;
-            if (G > 1) {
-                const int src = (tid & ~(G - 1)) + (r > 0 ? r - 1 : 0);
-                const float sx = __shfl(mx, src, 64), sy = __shfl(my, src, 64);
-                if (r > 0) {
-                    pxp = sx;
-                    pyp = sy;
-                }
-            }
-        }
         float q = 0.0f;
         if (d.cull)
             q = stage_cost_culled<NE>(d, s, lc, vref_uniform, act, seed, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm, t0,
                                       min(t0 + G, T) - 1, mth, pxp, pyp);
         else if (act)
             q = stage_cost<NE>(d, s, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm, mth, pxp, pyp);
-        if (act && valid && d.per_step) d.q[(size_t)tm * K + k] = q;
+        if (act && d.per_step) {
+            if (valid) d.q[(size_t)tm * K + k] = q;
+            if (L.eps_staged) s.qs[tm * (SPB + 1) + grp] = q;
+        }
         if (act) {
             const float yk = q - comp;
             const float tk = S + yk;
@@ -789,35 +814,50 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         // Per-step weights: the cost-to-go of every sample of the tile,
         // summed in float64 from the last step back, then per step the tile
         // minimum, the shifted exponential sums and the weighted
-        // perturbations (one thread per step, samples in index order).
+        // perturbations (one thread per step, samples in index order).  The
+        // cost-to-go of step 0 (the total the weights of step 0 are formed
+        // from) is also written out.  From the tile's LDS copies when they
+        // fit, else through global memory.
         __syncthreads();  // the tile's stage costs are stored
+        const bool lds = L.eps_staged;
         for (int j = tid; j < n_valid; j += kBlock) {
             double acc = 0.0;
             for (int t = T - 1; t >= 0; --t) {
-                acc += (double)d.q[(size_t)t * K + k_base + j];
-                d.Stk[(size_t)t * K + k_base + j] = acc;
+                acc += lds ? (double)s.qs[t * (SPB + 1) + j] : (double)d.q[(size_t)t * K + k_base + j];
+                if (lds) s.ss[t * SPB + j] = acc;
+                else d.Stk[(size_t)t * K + k_base + j] = acc;
             }
+            if (lds) d.Stk[k_base + j] = acc;
         }
         __syncthreads();
         for (int t = tid; t < T; t += kBlock) {
-            const double* St = d.Stk + (size_t)t * K + k_base;
-            const float2* e = d.eps + (size_t)t * K + k_base;
+            auto st_at = [&](int j) {
+                return lds ? s.ss[t * SPB + j] : d.Stk[(size_t)t * K + k_base + j];
+            };
             double m = INFINITY;
             for (int j = 0; j < n_valid; ++j) {
-                const double v = St[j];
+                const double v = st_at(j);
                 if (isfinite(v) && v < m) m = v;
             }
             double z = 0.0, qq = 0.0, na = 0.0, nd = 0.0;
             if (isfinite(m)) {
 #pragma unroll 1
                 for (int j = 0; j < n_valid; ++j) {
-                    const double v = St[j];
+                    const double v = st_at(j);
                     const double om = isfinite(v) ? exp(-(v - m) / d.lambda) : 0.0;
-                    const float2 ev = e[j];
+                    float ea, ed;
+                    if (lds) {
+                        ea = s.eps[(2 * t) * (SPB + 1) + j];
+                        ed = s.eps[(2 * t + 1) * (SPB + 1) + j];
+                    } else {
+                        const float2 ev = d.eps[(size_t)t * K + k_base + j];
+                        ea = ev.x;
+                        ed = ev.y;
+                    }
                     z += om;
                     qq += om * om;
-                    na += om * (double)ev.x;
-                    nd += om * (double)ev.y;
+                    na += om * (double)ea;
+                    nd += om * (double)ed;
                 }
             }
             double* o = part + 5 * t;
@@ -1086,6 +1126,7 @@ __device__ void combine(const InstDesc& d, int cg)
     __syncthreads();
     if (tid < ncol) {
         double nsum = 0.0;
+#pragma unroll 4
         for (int c = 0; c < chunks; ++c) nsum += part[c * slots + tid];
         const int col = 2 * w0 + tid;
         // the controls the iteration sampled around: kept after the tile rows
@@ -1177,6 +1218,7 @@ __device__ void combine_per_step(const InstDesc& d, int cg)
     __syncthreads();
     if (tid < nst) {
         double m = INFINITY;
+#pragma unroll 4
         for (int c = 0; c < kChunks; ++c) m = fmin(m, part[4 * (c * kSlots + tid)]);
         mt[tid] = m;
     }
@@ -1203,6 +1245,7 @@ __device__ void combine_per_step(const InstDesc& d, int cg)
     double zt = 0.0, qt = 0.0;
     if (tid < nst) {
         double sa = 0.0, sd = 0.0;
+#pragma unroll 4
         for (int c = 0; c < kChunks; ++c) {
             const double* pc = part + 4 * (c * kSlots + tid);
             zt += pc[0];

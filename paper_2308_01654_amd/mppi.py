@@ -74,6 +74,7 @@ class Profile(ctypes.Structure):
     _fields_ = [
         ("iter_ms", ctypes.c_double), ("iter_launches", ctypes.c_int64),
         ("aux_ms", ctypes.c_double), ("aux_launches", ctypes.c_int64),
+        ("rollout_ms", ctypes.c_double), ("rollout_launches", ctypes.c_int64),
     ]
 
 
@@ -431,7 +432,8 @@ class Planner:
         p = Profile()
         check(load().mppi_get_profile(self.h, ctypes.byref(p)))
         return dict(iter_ms=p.iter_ms, iter_launches=p.iter_launches, aux_ms=p.aux_ms,
-                    aux_launches=p.aux_launches)
+                    aux_launches=p.aux_launches, rollout_ms=p.rollout_ms,
+                    rollout_launches=p.rollout_launches)
 
 
 class Server:
