@@ -13,6 +13,8 @@ Gates, in the style of the total-cost path:
 and the end-to-end comparison against the fully independent oracle
 iteration, bit identity of batched / served runs with runs alone, and of
 culled with full scans."""
+import json
+import os
 import sys
 
 import numpy as np
@@ -34,6 +36,15 @@ def _mppi():
 def _say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
+
+
+OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+
+
+def _dump(name, obj):
+    os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, "parity_per_step_%s.json" % name), "w") as f:
+        json.dump(obj, f, indent=1, default=float)
 
 
 def _per_step(sc, **kw):
@@ -88,13 +99,16 @@ def test_per_step_staged_parity(name, lanes):
     sc = _per_step(scenes.by_name(name))
     p = sc["params"]
     _say("per-step staged", name, lanes)
+    reps = []
     with mppi.Planner(p, lanes=lanes) as pl:
         pl.set_controls(np.tile([0.3, -0.01], (p["T"], 1)))
         for it in range(2):
             g = _step(pl, sc)
             rep = _staged(p, sc, g, it)
             _say(" ", it, rep)
+            reps.append(rep)
             _assert_staged(rep)
+    _dump("%s_lanes%d" % (name, lanes), reps)
 
 
 @pytest.mark.parametrize("K,T", [(1, 1), (37, 3), (300, 1), (1000, 23), (4099, 130)])
@@ -131,6 +145,7 @@ def test_per_step_end_to_end_c0():
     dw = float(np.max(np.abs(g["w"] - r["w"])))
     beta = float(np.max(np.abs(g["S"] - r["S"])))
     _say("per-step e2e", dict(U_max_over_tol=du, w_max_abs=dw, beta=beta, lam=p["lam"]))
+    _dump("c0_e2e", dict(U_max_over_tol=du, w_max_abs=dw, beta=beta, lam=p["lam"]))
     assert du <= 1.0 and dw <= P.W_TOL
 
 
