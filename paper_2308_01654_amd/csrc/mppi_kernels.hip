@@ -253,8 +253,9 @@ constexpr int kIntMax = 0x7fffffff;
 constexpr int kIntMin = (int)0x80000000u;
 
 // Prefix sums inside aligned groups of G lanes (G <= 16, so a group lies in
-// one DPP row): the inclusive sum up to lane r of the group, the value of
-// lane r - 1 (0 for the first lane), and the group's last lane's value.
+// one DPP row): the inclusive sum (or maximum) up to lane r of the group,
+// the value of lane r - 1 (0 for the first lane), and the group's last
+// lane's value.
 template <int N>
 __device__ __forceinline__ float dpp_shr(float v)
 {
@@ -268,6 +269,15 @@ __device__ __forceinline__ float seg_scan(float v, int r)
     if (G >= 4) { const float u = dpp_shr<2>(v); v += r >= 2 ? u : 0.0f; }
     if (G >= 8) { const float u = dpp_shr<4>(v); v += r >= 4 ? u : 0.0f; }
     if (G >= 16) { const float u = dpp_shr<8>(v); v += r >= 8 ? u : 0.0f; }
+    return v;
+}
+template <int G>
+__device__ __forceinline__ float seg_scan_max(float v, int r)
+{
+    if (G >= 2) { const float u = dpp_shr<1>(v); v = r >= 1 ? fmaxf(v, u) : v; }
+    if (G >= 4) { const float u = dpp_shr<2>(v); v = r >= 2 ? fmaxf(v, u) : v; }
+    if (G >= 8) { const float u = dpp_shr<4>(v); v = r >= 4 ? fmaxf(v, u) : v; }
+    if (G >= 16) { const float u = dpp_shr<8>(v); v = r >= 8 ? fmaxf(v, u) : v; }
     return v;
 }
 template <int G>
@@ -714,32 +724,46 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         const float a0m = fminf(fmaxf(Um.x + em.x, d.a_min), d.a_max);
         const float dlm = fminf(fmaxf(Um.y + em.y, d.d_min), d.d_max);
         const float tnm = M5 ? dlm : __tanf(dlm);
-        // Speed: the speed cap of the noise check depends on the speed before
-        // each step, so the G lanes run the speed recursion of the block
-        // together (accelerations exchanged PF at a time) and each keeps the
-        // speed before its own step.  Steps past the horizon (last block) are
-        // run too; the lanes that own them are inactive.
+        // Speed before the own step.  The noise check caps the acceleration
+        // so that v <= v_max and applies the braking bound last.  While the
+        // speed at the block start is within v_max the braking bound cannot
+        // bind (a >= a_min already), and the capped recursion
+        // v_{i+1} = min(v_i + dt a_i, v_max) has the closed form
+        //   v_r = min(v_0 + S_r, v_max + S_r - max_{1<=k<=r} S_k),
+        // S_k = sum_{j<k} dt a_j: a prefix sum and a prefix maximum over the G
+        // lanes.  Otherwise (a wave with a sample above v_max) the G lanes run
+        // the recursion step by step (accelerations exchanged PF at a time),
+        // each keeping the speed before its own step.  Steps past the horizon
+        // (last block) are run too; the lanes that own them are inactive.
         float vr = v;
-        constexpr int PF = G < 4 ? G : 4;
-        float apf[PF];
+        if (__ballot(v > d.v_max) == 0ull) {
+            const float sincl = seg_scan<G>(d.dt * a0m, r);
+            const float sr = seg_prev<G>(sincl, r);
+            const float qr = seg_scan_max<G>(r >= 1 ? sr : -INFINITY, r);
+            vr = fminf(v + sr, d.v_max + (sr - qr));
+        } else {
+            constexpr int PF = G < 4 ? G : 4;
+            float apf[PF];
 #pragma unroll
-        for (int i = 0; i < G; ++i) {
-            if (i % PF == 0) {
+            for (int i = 0; i < G; ++i) {
+                if (i % PF == 0) {
 #pragma unroll
-                for (int u = 0; u < PF; ++u)
-                    apf[u] = G > 1 ? __shfl(a0m, gbase + i + u, 64) : a0m;
+                    for (int u = 0; u < PF; ++u)
+                        apf[u] = G > 1 ? __shfl(a0m, gbase + i + u, 64) : a0m;
+                }
+                vr = i == rb ? v : vr;
+                float a = fminf(apf[i % PF], (d.v_max - v) * d.inv_dt);
+                a = fmaxf(a, d.a_min);
+                v = fmaf(d.dt, a, v);
             }
-            vr = i == rb ? v : vr;
-            // noise check: speed cap, braking bound last
-            float a = fminf(apf[i % PF], (d.v_max - v) * d.inv_dt);
-            a = fmaxf(a, d.a_min);
-            v = fmaf(d.dt, a, v);
         }
-        // the own step's applied acceleration and the speed after it (the
-        // operations of the recursion: the same bits)
+        // the own step's applied acceleration (noise check: speed cap,
+        // braking bound last) and the speed after it; the block ends at the
+        // last lane's
         float ma = fminf(a0m, (d.v_max - vr) * d.inv_dt);
         ma = fmaxf(ma, d.a_min);
         const float mv = fmaf(d.dt, ma, vr);
+        v = group_last<G>(mv, gbase);
         // Eq. (5), explicit Euler: given the speeds, heading and position are
         // sums of per-step increments, formed by prefix sums over the G lanes
         // of the group (each lane adds its own step's increment).  With the

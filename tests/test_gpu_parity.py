@@ -132,6 +132,27 @@ def test_single_waypoint_and_unbounded_controls():
         P.assert_staged(P.staged(p, sc, g, n_iter=0))
 
 
+@pytest.mark.parametrize("lanes", [1, 4, 16])
+def test_initial_speed_above_cap_and_binding_cap(lanes):
+    """The speed cap of the noise check in both regimes of the walk: a start
+    above v_max (the braking bound binds, the step-by-step recursion runs)
+    and a start just under it with acceleration noise that keeps hitting the
+    cap (the closed form with its prefix maximum)."""
+    mppi = _mppi()
+    base = scenes.c0()
+    for v0, U0 in ((13.0, 0.5), (9.9, 1.0)):
+        x0 = np.array(base["x0"], dtype=np.float64)
+        x0[3] = v0
+        sc = dict(base, x0=x0)
+        p = sc["params"]
+        _say("speed cap", lanes, v0)
+        with mppi.Planner(p, lanes=lanes) as pl:
+            pl.set_controls(np.tile([U0, 0.0], (p["T"], 1)))
+            for it in range(2):
+                g = P.gpu_step(pl, sc)
+                P.assert_staged(P.staged(p, sc, g, n_iter=it))
+
+
 def test_zero_noise_gives_uniform_weights_and_no_update():
     mppi = _mppi()
     sc = scenes.tiny(K=2048, T=30, n_c=5)
