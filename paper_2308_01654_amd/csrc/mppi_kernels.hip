@@ -409,16 +409,17 @@ __device__ __forceinline__ float chunk_min(const float4 (&q)[4], float x, float 
 
 // Scans the chunks whose bits are set in m (ascending, two per memory round
 // trip, read from global memory with scalar loads): best = smallest squared
-// distance, bch = first chunk that attains it.
+// distance, bch = first chunk that attains it.  An odd last chunk is paired
+// with itself: the repeat cannot be strictly smaller, so nothing changes,
+// and the pair's loads are issued together without a branch between them.
 __device__ __forceinline__ void scan_chunks(const_ptr<float> wp4, int base, unsigned long long m,
                                             float x, float y, float& best, int& bch)
 {
     while (m) {
         const int c0 = base + __builtin_ctzll(m);
         m &= m - 1;
-        const bool two = m != 0;
-        const int c1 = two ? base + __builtin_ctzll(m) : c0;
-        if (two) m &= m - 1;
+        const int c1 = m ? base + __builtin_ctzll(m) : c0;
+        m &= m - 1;
         float4 q0[4], q1[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -426,16 +427,14 @@ __device__ __forceinline__ void scan_chunks(const_ptr<float> wp4, int base, unsi
             q1[u] = ld4(wp4, c1 * 4 + u);
         }
         const float m0 = chunk_min(q0, x, y);
+        const float m1 = chunk_min(q1, x, y);
         if (m0 < best) {
             best = m0;
             bch = c0;
         }
-        if (two) {
-            const float m1 = chunk_min(q1, x, y);
-            if (m1 < best) {
-                best = m1;
-                bch = c1;
-            }
+        if (m1 < best) {
+            best = m1;
+            bch = c1;
         }
     }
 }
@@ -595,13 +594,15 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
             }
             unsigned long long m = __ballot(need);
             while (m) {
-                // up to four candidates per round trip, merged in index order
+                // four candidates per round trip, loads issued together; a
+                // short last group repeats its first candidate (the minimum
+                // is unchanged)
                 int idx[4];
-                int cnt = 0;
+                idx[0] = base + __builtin_ctzll(m);
+                m &= m - 1;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    idx[u] = base + (m ? __builtin_ctzll(m) : 0);
-                    cnt += m ? 1 : 0;
+                for (int u = 1; u < 4; ++u) {
+                    idx[u] = m ? base + __builtin_ctzll(m) : idx[0];
                     m &= m - 1;
                 }
                 float4 p[4];
@@ -612,8 +613,7 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
                     rr[u] = crr[idx[u]];
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (u < cnt) d_obj = fminf(d_obj, circle_gap<NE>(ex, ey, p[u], rr[u], tau));
+                for (int u = 0; u < 4; ++u) d_obj = fminf(d_obj, circle_gap<NE>(ex, ey, p[u], rr[u], tau));
             }
         }
         cost = fmaf(d.w_coll, safe_cost(d, ds, d_obj), cost);
