@@ -130,7 +130,10 @@ SceneLayout scene_layout(int n_wp, int n_c)
     L.o_vr = L.o_xy + align_up((size_t)(n_wp + kChunk - 1) / kChunk * kChunk * 8, 16);
     L.o_yw = L.o_vr + align_up((size_t)n_wp * 4, 16);
     L.o_rr = L.o_yw + align_up((size_t)n_wp * 4, 16);
-    L.bytes = L.o_rr + align_up((size_t)n_c * 4, 16);
+    // bounding box of every chunk, then the scene's flags
+    L.o_box = L.o_rr + align_up((size_t)n_c * 4, 16);
+    L.o_flags = L.o_box + (size_t)(n_wp + kChunk - 1) / kChunk * 16;
+    L.bytes = L.o_flags + 16;
     return L;
 }
 
@@ -150,6 +153,24 @@ void write_scene(unsigned char* dst, const SceneLayout& L, const mppi_config& c,
         yw[i] = (float)w[2];
     }
     for (int i = sc->n_waypoints; i % kChunk; ++i) xy[i] = make_float2(INFINITY, INFINITY);
+    // (x_lo, x_hi, y_lo, y_hi) of each chunk's float32 positions, for the
+    // culling; flag 0: one reference speed for every waypoint
+    float4* box = reinterpret_cast<float4*>(dst + L.o_box);
+    for (int c = 0; c * kChunk < sc->n_waypoints; ++c) {
+        float4 b = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+        for (int j = c * kChunk; j < std::min((c + 1) * kChunk, (int)sc->n_waypoints); ++j) {
+            b.x = fminf(b.x, xy[j].x);
+            b.y = fmaxf(b.y, xy[j].x);
+            b.z = fminf(b.z, xy[j].y);
+            b.w = fmaxf(b.w, xy[j].y);
+        }
+        box[c] = b;
+    }
+    int* flags = reinterpret_cast<int*>(dst + L.o_flags);
+    flags[0] = 1;
+    for (int i = 1; i < sc->n_waypoints; ++i)
+        if (vr[i] != vr[0]) flags[0] = 0;
+    flags[1] = flags[2] = flags[3] = 0;
     for (int i = 0; i < sc->n_circles; ++i) {
         const double* o = sc->circles + 5 * i;
         pv[i] = make_float4((float)(o[0] - origin[0]), (float)(o[1] - origin[1]), (float)o[3],
@@ -459,6 +480,8 @@ void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double or
     d.wp_xy = reinterpret_cast<const float2*>(scene + L.o_xy);
     d.wp_vref = reinterpret_cast<const float*>(scene + L.o_vr);
     d.wp_yaw = reinterpret_cast<const float*>(scene + L.o_yw);
+    d.wp_box = reinterpret_cast<const float4*>(scene + L.o_box);
+    d.scene_flags = reinterpret_cast<const int*>(scene + L.o_flags);
     d.c_rr = reinterpret_cast<const float*>(scene + L.o_rr);
     d.U = h->U;
     d.S = h->S;

@@ -45,7 +45,7 @@ struct ProfEvent {
 
 // Offsets of the four scene arrays inside a staged scene block.
 struct SceneLayout {
-    size_t o_pv, o_xy, o_vr, o_yw, o_rr, bytes;
+    size_t o_pv, o_xy, o_vr, o_yw, o_rr, o_box, o_flags, bytes;
 };
 
 // Per-instance extras of a batched launch: scratch buffers that replace the

@@ -118,6 +118,8 @@ struct InstDesc {
     const float2* wp_xy;  // [n_wp]
     const float* wp_vref; // [n_wp]
     const float* wp_yaw;  // [n_wp]
+    const float4* wp_box; // [chunks] (x_lo, x_hi, y_lo, y_hi) of each chunk
+    const int* scene_flags; // [0]: every waypoint has the same reference speed
     const float4* c_pv;   // [n_c] (x, y, vx, vy)
     const float* c_rr;    // [n_c] r_c + r_ego
     double* U;            // [T][2]

@@ -652,29 +652,16 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         s.c_rr[i] = d.c_rr[i];
     }
     const int n_wp_pad = (d.n_wp + kChunk - 1) / kChunk * kChunk;
-    const float vref0 = d.wp_vref[0];
-    bool same_vref = true;
     for (int i = tid; i < n_wp_pad; i += kBlock) {
         // padding points at infinity are never the closest
-        s.wp_xy[i] = i < d.n_wp ? d.wp_xy[i] : make_float2(INFINITY, INFINITY);
+        s.wp_xy[i] = d.wp_xy[i];
         if (i < d.n_wp) {
-            const float vr = d.wp_vref[i];
-            s.wp_vref[i] = vr;
+            s.wp_vref[i] = d.wp_vref[i];
             s.wp_yaw[i] = d.wp_yaw[i];
-            same_vref = same_vref && vr == vref0;
         }
     }
-    for (int c = tid; c * kChunk < d.n_wp; c += kBlock) {
-        float4 b = make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
-        for (int j = c * kChunk; j < min((c + 1) * kChunk, d.n_wp); ++j) {
-            const float2 w = d.wp_xy[j];
-            b.x = fminf(b.x, w.x);
-            b.y = fmaxf(b.y, w.x);
-            b.z = fminf(b.z, w.y);
-            b.w = fmaxf(b.w, w.y);
-        }
-        s.wp_box[c] = b;  // (x_lo, x_hi, y_lo, y_hi)
-    }
+    // (x_lo, x_hi, y_lo, y_hi) of every chunk, formed with the scene
+    for (int c = tid; c * kChunk < d.n_wp; c += kBlock) s.wp_box[c] = d.wp_box[c];
     for (int i = tid; i < T; i += kBlock)
         s.U[i] = make_float2((float)d.U[2 * i], (float)d.U[2 * i + 1]);
     // the controls sampled around, kept for the smoothing combine
@@ -684,7 +671,8 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     }
     const unsigned long long n_iter = d.st->n_iter;
     // one reference speed for every waypoint: the closest index is not needed
-    const bool vref_uniform = __syncthreads_and(same_vref) != 0;
+    const bool vref_uniform = d.scene_flags[0] != 0;
+    __syncthreads();
 
     // ---------------------------------------------------------------- phase 1
     const int grp = tid / G;
