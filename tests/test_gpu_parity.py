@@ -153,6 +153,26 @@ def test_initial_speed_above_cap_and_binding_cap(lanes):
                 P.assert_staged(P.staged(p, sc, g, n_iter=it))
 
 
+@pytest.mark.parametrize("K,smoothing", [(8192, 0), (8208, 0), (16 * 8193, 0), (8208, 1)])
+def test_combine_at_the_direct_limit_and_above(K, smoothing):
+    """512 tiles of 16 samples go to the combine kernel directly; 513 tiles
+    and 8193 tiles are first merged by one and two levels of the in-kernel
+    tree (down to 33 and 513 -> 33 nodes); with smoothing the combine reads
+    the controls the first tile kept."""
+    mppi = _mppi()
+    sc = scenes.tiny(K=K, T=12, n_c=6, seed=K % 1000)
+    p = dict(sc["params"], smoothing=smoothing)
+    sc = dict(sc, params=p)
+    _say("combine limit", K, smoothing)
+    ks = None if K <= 8208 else np.arange(0, K, 257)
+    with mppi.Planner(p, lanes=16) as pl:
+        pl.set_controls(np.tile([0.1, -0.02], (12, 1)))
+        for it in range(2):
+            g = P.gpu_step(pl, sc)
+            rep = P.staged(p, sc, g, n_iter=it, ks=ks)
+            P.assert_staged(rep)
+
+
 def test_zero_noise_gives_uniform_weights_and_no_update():
     mppi = _mppi()
     sc = scenes.tiny(K=2048, T=30, n_c=5)

@@ -122,6 +122,19 @@ def test_per_step_ragged_shapes(K, T):
         _assert_staged(_staged(p, sc, g, 0))
 
 
+@pytest.mark.parametrize("smoothing", [0, 1])
+def test_per_step_above_the_direct_limit(smoothing):
+    """600 tiles of 16 samples: the per-step combine walks more tile rows
+    than the total-cost combine takes in one pass."""
+    mppi = _mppi()
+    sc = _per_step(scenes.tiny(K=9600, T=20, n_c=5, seed=31), smoothing=smoothing)
+    p = sc["params"]
+    with mppi.Planner(p, lanes=16) as pl:
+        for it in range(2):
+            g = _step(pl, sc)
+            _assert_staged(_staged(p, sc, g, it))
+
+
 def test_per_step_with_smoothing_and_model5():
     mppi = _mppi()
     sc = _per_step(scenes.paper_model5(scenes.paper_follow(), steer0=0.02), smoothing=1)
