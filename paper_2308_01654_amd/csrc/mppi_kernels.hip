@@ -1075,6 +1075,10 @@ __device__ void combine(const InstDesc& d, int cg)
     const int i0 = min(chunk * per, n), i1 = min(i0 + per, n);
     const bool worked = slot < ncol;
     const double* src = rows + kPartialHead + 2 * w0 + slot;
+    // the controls the iteration sampled around (kept after the tile rows when
+    // smoothing, since other workgroups rewrite U), loaded with the rest
+    const double* u_old = d.smooth ? d.partials + (size_t)d.n_tiles * stride : d.U;
+    const double u_prev = tid < ncol ? u_old[2 * w0 + tid] : 0.0;
     double pv[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u)
@@ -1141,10 +1145,7 @@ __device__ void combine(const InstDesc& d, int cg)
 #pragma unroll 4
         for (int c = 0; c < chunks; ++c) nsum += part[c * slots + tid];
         const int col = 2 * w0 + tid;
-        // the controls the iteration sampled around: kept after the tile rows
-        // when smoothing (other workgroups rewrite U), else U itself
-        const double* u_old = d.smooth ? d.partials + (size_t)d.n_tiles * stride : d.U;
-        const double u = u_old[col] + nsum / z;
+        const double u = u_prev + nsum / z;
         if (d.smooth) un[tid] = u;
         else d.U[col] = u;
     }
@@ -1222,6 +1223,9 @@ __device__ void combine_per_step(const InstDesc& d, int cg)
     const int per = (n + kChunks - 1) / kChunks;
     const int b0 = min(chunk * per, n), b1 = min(b0 + per, n);
     const double* col = rows + 5 * (size_t)t;
+    const double* u_old = d.smooth ? d.partials + (size_t)n * stride : d.U;
+    const double ua_prev = tid < nst ? u_old[2 * (w0 + tid)] : 0.0;
+    const double ud_prev = tid < nst ? u_old[2 * (w0 + tid) + 1] : 0.0;
     // per-step minimum: chunks, then the chunks in order
     double ml = INFINITY;
     if (worked)
@@ -1266,9 +1270,8 @@ __device__ void combine_per_step(const InstDesc& d, int cg)
             sd += pc[3];
         }
         const int tt = w0 + tid;
-        const double* u_old = d.smooth ? d.partials + (size_t)n * stride : d.U;
-        const double ua = u_old[2 * tt] + sa / zt;
-        const double ud = u_old[2 * tt + 1] + sd / zt;
+        const double ua = ua_prev + sa / zt;
+        const double ud = ud_prev + sd / zt;
         if (d.smooth) {
             un[2 * tid] = ua;
             un[2 * tid + 1] = ud;
