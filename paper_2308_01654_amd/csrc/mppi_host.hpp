@@ -123,7 +123,7 @@ namespace mppi_impl {
     } while (0)
 
 SceneLayout scene_layout(int n_wp, int n_c);
-// Bytes of a handle's device state: DevState and the combine-tree tickets
+// Bytes of a handle's device state: DevState and the partial-tree tickets
 // for up to max_tiles tiles.
 inline size_t state_bytes(int max_tiles)
 {

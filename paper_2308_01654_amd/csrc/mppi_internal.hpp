@@ -15,9 +15,9 @@ constexpr int kMaxCircles = 1024;
 constexpr int kMaxK = 1 << 24;
 
 // Per-instance state that stays resident on the device between iterations.
-// The allocation continues with the group tickets of the combine tree
-// (combine_tickets(max tiles) tickets of kTicketStride unsigned ints each,
-// zero between iterations).
+// The allocation continues with the group tickets of the in-kernel partial
+// tree (combine_tickets(max tiles) tickets of kTicketStride unsigned ints
+// each, zero between iterations).
 struct DevState {
     unsigned long long n_iter;  // Philox counter words 2-3: iteration number
     unsigned int reserved;
@@ -129,7 +129,7 @@ struct InstDesc {
     float* q;             // [T][K] stage costs (per-step weights)
     double* Stk;          // [T][K] cost-to-go (per-step weights; row 0 always, the
                           // other rows only when a tile works in global memory)
-    DevState* st;         // followed by the combine-tree tickets
+    DevState* st;         // followed by the partial-tree tickets
 };
 
 // Header of a batch arena in device memory: followed by the tile prefix

@@ -2,32 +2,33 @@
 // arXiv 2308.01654 (Algorithm 1, noise generation through the input update,
 // with the costs of Sec. III and Sec. IV-C).
 //
-// One fused kernel runs the whole iteration.  A workgroup owns a tile of
-// samples; G lanes ("lanes per sample", 1..16) cooperate on one sample:
+// An iteration is two launches.  The iteration kernel (k_batch) gives each
+// workgroup a tile of samples; G lanes ("lanes per sample", 1..16)
+// cooperate on one sample:
 //
 //   phase 1  rollout.  The horizon is walked in blocks of G steps.  Lane r of
-//            a group draws the Philox/Box-Muller perturbation of step t0+r,
-//            the G perturbations are exchanged inside the group, and every
-//            lane advances the (cheap) bicycle recursion of all G steps,
-//            keeping the state reached at its own step.  Each lane then
+//            a group draws the Philox/Box-Muller perturbation of step t0+r
+//            and applies the control bounds; the speed before each step
+//            (the noise check's speed cap) and the heading and position of
+//            eq. (5) come from prefix sums over the G lanes, so each lane
+//            holds the state reached at its own step.  Each lane then
 //            evaluates the (expensive) stage cost of its own step: the
 //            waypoint scan and the ego-circle x obstacle-circle distances,
-//            with the scene staged in LDS and read as wave-uniform
-//            broadcasts.  Costs are Kahan-summed per lane and combined per
-//            sample in float64.  Applied perturbations are stored time-major
-//            [T][K] as float2.
+//            culled per wave.  Costs are Kahan-summed per lane and combined
+//            per sample in float64.  Applied perturbations are stored
+//            time-major [T][K] as float2 (and kept in LDS for phase 2).
 //   phase 2  tile partials.  Tile minimum m_b, then (float64)
 //            omega_i = exp(-(S_i - m_b)/lambda), Z_b = sum omega_i and, for
-//            every (t, control) column, a Kahan-compensated float32 sum of
-//            omega_i * eps_eff[t][i] over the tile (re-read while L2-hot).
-//   phase 3  combine.  The last tile to finish (agent-scope ticket) merges
-//            the tile partials in tile order with the rescale
-//            exp(-(m_b - m)/lambda), and updates U in float64:
-//            U_t += N_t / Z (eq. (update-input)).  It bumps the iteration
-//            counter and records S_min, log Z and the effective sample size.
+//            every (t, control) column, the float64 sum of the exact
+//            products omega_i * eps_eff[t][i] over the tile.
+//   phase 3  (tiles above kDirect only) a fixed-shape tree merges tiles
+//            until kDirect nodes remain.
 //
-// The tile order of the combine is fixed, so results do not depend on which
-// workgroup finishes first.
+// The combine kernel (k_combine) merges the node rows in node order with the
+// rescale exp(-(m_b - m)/lambda) and updates U in float64: U_t += N_t / Z
+// (eq. (update-input)); it bumps the iteration counter and records S_min,
+// log Z and the effective sample size.  Every order of summation is fixed,
+// so results do not depend on which workgroup finishes first.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
