@@ -999,14 +999,17 @@ mppi_status mppi_get_trajectory(mppi_t* h, double* states, size_t n_states, doub
     a.d_min = c.u_min[1];
     a.d_max = c.u_max[1];
     a.v_max = c.v_max;
+    // states then controls, contiguous: one copy back
+    const size_t ns = cols * (T + 1), nu = (size_t)2 * T;
     double* xs = h->traj;
-    double* us = h->traj + 5 * (size_t)(T + 1);
+    double* us = h->traj + ns;
     HIP_TRY(launch_trajectory(a, h->U, xs, us, h->stream));
+    std::vector<double> host(ns + nu);
+    HIP_TRY(hipMemcpyAsync(host.data(), xs, sizeof(double) * (ns + nu), hipMemcpyDeviceToHost,
+                           h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    if (states)
-        HIP_TRY(hipMemcpy(states, xs, sizeof(double) * cols * (T + 1), hipMemcpyDeviceToHost));
-    if (controls)
-        HIP_TRY(hipMemcpy(controls, us, sizeof(double) * 2 * T, hipMemcpyDeviceToHost));
+    if (states) memcpy(states, host.data(), sizeof(double) * ns);
+    if (controls) memcpy(controls, host.data() + ns, sizeof(double) * nu);
     return MPPI_OK;
 }
 

@@ -1328,17 +1328,49 @@ hipError_t launch_combine(const InstDesc* d0, const BatchHdr* hdr_dev, int group
     return hipGetLastError();
 }
 
+// Exclusive prefix sum (MAX = false) or maximum (MAX = true) over the
+// threads of a workgroup in thread order (float64): shuffles inside a wave,
+// the totals of the earlier waves through LDS (red: kBlock / 64 doubles).
+// Thread 0 gets 0 (sum) or -inf (maximum).
+template <bool MAX>
+__device__ __forceinline__ double block_excl(double v, double* red)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const double id = MAX ? -INFINITY : 0.0;
+    double incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl = MAX ? fmax(incl, u) : incl + u;
+    }
+    double excl = __shfl_up(incl, 1, 64);
+    if (lane == 0) excl = id;
+    __syncthreads();  // red is free
+    if (lane == 63) red[wv] = incl;
+    __syncthreads();
+    double before = id;
+    for (int i = 0; i < wv; ++i) before = MAX ? fmax(before, red[i]) : before + red[i];
+    return MAX ? fmax(before, excl) : before + excl;
+}
+
 // Optimal rollout of Alg. 1 in float64 and world coordinates: from x0,
 // x*_{t+1} = F(x*_t, u*_t) (eq. (5), explicit Euler from the old state), each
 // nominal control put through the noise check with zero noise (bounds, speed
-// cap, braking bound last).  One thread walks the horizon.
-__global__ void k_trajectory(TrajArgs a, const double* __restrict__ U, double* __restrict__ xs,
-                             double* __restrict__ us)
+// cap, braking bound last).  One workgroup, each thread a run of consecutive
+// steps.  While the start is within v_max the braking bound cannot bind and
+// the capped speeds have the closed form of the iteration kernel's walk
+// (v_t = min(v_0 + S_t, v_max + S_t - max_{1<=k<=t} S_k), S_t the sum of the
+// first t commanded changes); heading, steering angle (5-state model) and
+// position are prefix sums of their increments.  A start above v_max is
+// walked step by step by one thread.
+__global__ __launch_bounds__(kBlock) void k_trajectory(TrajArgs a, const double* __restrict__ U,
+                                                       double* __restrict__ xs,
+                                                       double* __restrict__ us)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double red[kBlock / 64];
     const int cols = a.model ? 5 : 4;  // the 5-state model also writes delta
-    double x = a.x0[0], y = a.x0[1], th = a.x0[2], v = a.x0[3], delta = a.steer0;
-    auto put = [&](int t) {
+    const int T = a.T;
+    auto put = [&](int t, double x, double y, double th, double v, double delta) {
         double* o = xs + (size_t)cols * t;
         o[0] = x;
         o[1] = y;
@@ -1346,24 +1378,109 @@ __global__ void k_trajectory(TrajArgs a, const double* __restrict__ U, double* _
         o[3] = v;
         if (a.model) o[4] = delta;
     };
-    put(0);
-    for (int t = 0; t < a.T; ++t) {
-        double acc = fmin(fmax(U[2 * t], a.a_min), a.a_max);
-        acc = fmax(fmin(acc, (a.v_max - v) / a.dt), a.a_min);
-        const double u2 = fmin(fmax(U[2 * t + 1], a.d_min), a.d_max);
-        const double vdt = a.dt * v;
-        const double xn = x + vdt * cos(th);
-        const double yn = y + vdt * sin(th);
-        // the steering angle is the control, or (5-state model) the state
-        const double thn = th + vdt * tan(a.model ? delta : u2) / a.wheelbase;
-        if (a.model) delta += a.dt * u2;
-        v += a.dt * acc;
-        x = xn;
-        y = yn;
-        th = thn;
-        us[2 * t] = acc;
-        us[2 * t + 1] = u2;
-        put(t + 1);
+    if (!(a.x0[3] <= a.v_max)) {
+        if (threadIdx.x != 0) return;
+        double x = a.x0[0], y = a.x0[1], th = a.x0[2], v = a.x0[3], delta = a.steer0;
+        put(0, x, y, th, v, delta);
+        for (int t = 0; t < T; ++t) {
+            double acc = fmin(fmax(U[2 * t], a.a_min), a.a_max);
+            acc = fmax(fmin(acc, (a.v_max - v) / a.dt), a.a_min);
+            const double u2 = fmin(fmax(U[2 * t + 1], a.d_min), a.d_max);
+            const double vdt = a.dt * v;
+            const double xn = x + vdt * cos(th);
+            const double yn = y + vdt * sin(th);
+            // the steering angle is the control, or (5-state model) the state
+            const double thn = th + vdt * tan(a.model ? delta : u2) / a.wheelbase;
+            if (a.model) delta += a.dt * u2;
+            v += a.dt * acc;
+            x = xn;
+            y = yn;
+            th = thn;
+            us[2 * t] = acc;
+            us[2 * t + 1] = u2;
+            put(t + 1, x, y, th, v, delta);
+        }
+        return;
+    }
+    constexpr int kP = kMaxT / kBlock;  // steps per thread at most
+    const int P = (T + kBlock - 1) / kBlock;
+    const int t0 = threadIdx.x * P;
+    double acmd[kP], u2[kP], ds[kP];
+    // commanded speed changes and their sums before each own step
+    double run = 0.0;
+#pragma unroll
+    for (int j = 0; j < kP; ++j) {
+        const int t = t0 + j;
+        acmd[j] = u2[j] = 0.0;
+        if (j < P && t < T) {
+            acmd[j] = fmin(fmax(U[2 * t], a.a_min), a.a_max);
+            u2[j] = fmin(fmax(U[2 * t + 1], a.d_min), a.d_max);
+        }
+        ds[j] = run;
+        run += a.dt * acmd[j];
+    }
+    const double s_before = block_excl<false>(run, red);  // S at this thread's first step
+    // S_t of every own step, and the maximum of S_k over 1 <= k <= t: the
+    // earlier threads' maximum, then this thread's running one
+    double sv[kP], qv[kP];
+    double qrun = -INFINITY;
+#pragma unroll
+    for (int j = 0; j < kP; ++j) {
+        sv[j] = s_before + ds[j];
+        if (j < P && t0 + j >= 1 && t0 + j < T) qrun = fmax(qrun, sv[j]);
+        qv[j] = qrun;
+    }
+    const double qp = block_excl<true>(qrun, red);
+    double v[kP], acc[kP], dth[kP], dd[kP];
+    double drun = 0.0;
+#pragma unroll
+    for (int j = 0; j < kP; ++j) {
+        const double q = fmax(qp, qv[j]);
+        v[j] = t0 + j == 0 ? a.x0[3] : fmin(a.x0[3] + sv[j], a.v_max + sv[j] - q);
+        acc[j] = fmax(fmin(acmd[j], (a.v_max - v[j]) / a.dt), a.a_min);
+        dd[j] = drun;  // steering change before the own step, within the thread
+        drun += a.model ? a.dt * u2[j] : 0.0;
+    }
+    const double d_before = a.model ? block_excl<false>(drun, red) : 0.0;
+    double run_th = 0.0;
+#pragma unroll
+    for (int j = 0; j < kP; ++j) {
+        const double delta = a.steer0 + d_before + dd[j];
+        const double tn = tan(a.model ? delta : u2[j]);
+        dth[j] = run_th;
+        run_th += (j < P && t0 + j < T) ? a.dt * v[j] * tn / a.wheelbase : 0.0;
+    }
+    const double th_before = block_excl<false>(run_th, red);
+    double run_x = 0.0, run_y = 0.0, dx[kP], dy[kP];
+#pragma unroll
+    for (int j = 0; j < kP; ++j) {
+        const double th = a.x0[2] + th_before + dth[j];
+        dx[j] = run_x;
+        dy[j] = run_y;
+        if (j < P && t0 + j < T) {
+            run_x += a.dt * v[j] * cos(th);
+            run_y += a.dt * v[j] * sin(th);
+        }
+    }
+    const double x_before = block_excl<false>(run_x, red);
+    const double y_before = block_excl<false>(run_y, red);
+#pragma unroll
+    for (int j = 0; j < kP; ++j) {
+        const int t = t0 + j;
+        if (j >= P || t >= T) break;
+        us[2 * t] = acc[j];
+        us[2 * t + 1] = u2[j];
+        put(t, a.x0[0] + x_before + dx[j], a.x0[1] + y_before + dy[j], a.x0[2] + th_before + dth[j],
+            v[j], a.steer0 + d_before + dd[j]);
+        if (t == T - 1) {
+            // the state after the last step
+            const double vdt = a.dt * v[j];
+            const double th = a.x0[2] + th_before + dth[j];
+            const double delta = a.steer0 + d_before + dd[j];
+            put(T, a.x0[0] + x_before + dx[j] + vdt * cos(th), a.x0[1] + y_before + dy[j] + vdt * sin(th),
+                th + vdt * tan(a.model ? delta : u2[j]) / a.wheelbase, v[j] + a.dt * acc[j],
+                delta + (a.model ? a.dt * u2[j] : 0.0));
+        }
     }
 }
 
@@ -1506,7 +1623,7 @@ __global__ void k_weights(const float* __restrict__ S, const double* __restrict_
 hipError_t launch_trajectory(const TrajArgs& a, const double* U, double* states, double* applied,
                              hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_trajectory, dim3(1), dim3(64), 0, stream, a, U, states, applied);
+    hipLaunchKernelGGL(k_trajectory, dim3(1), dim3(kBlock), 0, stream, a, U, states, applied);
     return hipGetLastError();
 }
 

@@ -95,6 +95,31 @@ def test_trajectory_matches_oracle_rollout(smoothing):
             assert np.array_equal(xs[0], np.asarray(sc["x0"], dtype=np.float64))
 
 
+@pytest.mark.parametrize("T,v0,model", [(700, 9.0, 0), (700, 16.0, 0), (300, 9.5, 1), (1, 3.0, 0)])
+def test_trajectory_long_horizon_and_start_above_cap(T, v0, model):
+    """Several steps per thread (T = 700, 300), the start above v_max (the
+    step-by-step branch), the 5-state model and T = 1: equal to the oracle's
+    optimal rollout."""
+    mppi = _mppi()
+    sc = scenes.tiny(K=256, T=T, n_c=4, seed=T)
+    p = dict(sc["params"], v_max=12.0)
+    if model:
+        p = scenes.paper_model5(dict(sc, params=p), steer0=0.03)["params"]
+    x0 = np.array(sc["x0"], dtype=np.float64)
+    x0[3] = v0
+    with mppi.Planner(p) as pl:
+        if model:
+            pl.set_steering(0.03)
+        pl.set_controls(np.tile([0.8, 0.02], (T, 1)))
+        pl.step(x0, sc["waypoints"], sc["circles"])
+        xs, us = pl.trajectory()
+        ref_x, ref_u = O.optimal_trajectory(p, x0, pl.controls())
+    _say("trajectory", T, v0, model, float(np.max(np.abs(xs - ref_x))))
+    assert np.max(np.abs(us - ref_u)) <= 1e-12
+    assert np.max(np.abs(xs - ref_x)) <= TRAJ_ABS
+    assert np.array_equal(xs[0, :4], x0)
+
+
 def test_trajectory_before_any_step_is_rejected():
     mppi = _mppi()
     with mppi.Planner(scenes.c0()["params"]) as pl:
