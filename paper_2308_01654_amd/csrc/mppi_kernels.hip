@@ -824,29 +824,94 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     double* part = d.partials + (size_t)tile * stride;
     const int n_valid = min(SPB, K - k_base);
     if (d.per_step) {
-        // Per-step weights: the cost-to-go of every sample of the tile,
-        // summed in float64 from the last step back, then per step the tile
-        // minimum, the shifted exponential sums and the weighted
-        // perturbations (one thread per step, samples in index order).  The
-        // cost-to-go of step 0 (the total the weights of step 0 are formed
-        // from) is also written out.  From the tile's LDS copies when they
-        // fit, else through global memory.
+        // Per-step weights: the cost-to-go of every sample of the tile in
+        // float64, then per step the tile minimum, the shifted exponential
+        // sums and the weighted perturbations (one thread per step, samples
+        // in index order).  The cost-to-go is summed by segments of steps, G
+        // threads per sample: each sums its segment from its end back, then
+        // adds the totals of the later segments, last first.  The cost-to-go
+        // of step 0 (the total the weights of step 0 are formed from) is also
+        // written out.  From the tile's LDS copies when they fit, else
+        // through global memory.
         __syncthreads();  // the tile's stage costs are stored
         const bool lds = L.eps_staged;
-        for (int j = tid; j < n_valid; j += kBlock) {
-            double acc = 0.0;
-            for (int t = T - 1; t >= 0; --t) {
-                acc += lds ? (double)s.qs[t * (SPB + 1) + j] : (double)d.q[(size_t)t * K + k_base + j];
-                if (lds) s.ss[t * SPB + j] = acc;
-                else d.Stk[(size_t)t * K + k_base + j] = acc;
-            }
-            if (lds) d.Stk[k_base + j] = acc;
-        }
-        __syncthreads();
-        for (int t = tid; t < T; t += kBlock) {
-            auto st_at = [&](int j) {
+        {
+            const int j = tid % SPB, p = tid / SPB;
+            const int len = (T + G - 1) / G;
+            const int ta = min(p * len, T), tb = min(ta + len, T);
+            const bool on = j < n_valid;
+            auto st_ld = [&](int t) {
                 return lds ? s.ss[t * SPB + j] : d.Stk[(size_t)t * K + k_base + j];
             };
+            auto st_st = [&](int t, double v) {
+                if (lds) s.ss[t * SPB + j] = v;
+                else d.Stk[(size_t)t * K + k_base + j] = v;
+            };
+            if (on) {
+                double acc = 0.0;
+                for (int t = tb - 1; t >= ta; --t) {
+                    acc += lds ? (double)s.qs[t * (SPB + 1) + j] : (double)d.q[(size_t)t * K + k_base + j];
+                    st_st(t, acc);
+                }
+            }
+            __syncthreads();
+            double off = 0.0;
+            if (on)
+                for (int pp = G - 1; pp > p; --pp)
+                    if (pp * len < T) off += st_ld(pp * len);
+            __syncthreads();  // segment totals are read before they change
+            if (on && p < G - 1 && ta < T) {
+                for (int t = ta; t < tb; ++t) st_st(t, st_ld(t) + off);
+                if (lds && p == 0) d.Stk[k_base + j] = st_ld(0);
+            } else if (on && lds && p == 0) {
+                d.Stk[k_base + j] = st_ld(0);
+            }
+        }
+        __syncthreads();
+        if (lds) {
+            // In LDS the three passes spread over the whole workgroup: the
+            // per-step minima (one thread per step, kept where the stage
+            // costs were), every sample's shifted exponential of every step
+            // (written over its cost-to-go), then the sums per step in
+            // sample order.
+            double* mt = reinterpret_cast<double*>(s.qs);
+            for (int t = tid; t < T; t += kBlock) {
+                double m = INFINITY;
+#pragma unroll 4
+                for (int j = 0; j < n_valid; ++j) {
+                    const double v = s.ss[t * SPB + j];
+                    if (isfinite(v) && v < m) m = v;
+                }
+                mt[t] = m;
+            }
+            __syncthreads();
+            for (int i = tid; i < T * SPB; i += kBlock) {
+                const int t = i / SPB, j = i % SPB;
+                if (j >= n_valid) continue;
+                const double m = mt[t], v = s.ss[i];
+                s.ss[i] = isfinite(m) && isfinite(v) ? exp(-(v - m) / d.lambda) : 0.0;
+            }
+            __syncthreads();
+            for (int t = tid; t < T; t += kBlock) {
+                double z = 0.0, qq = 0.0, na = 0.0, nd = 0.0;
+#pragma unroll 4
+                for (int j = 0; j < n_valid; ++j) {
+                    const double om = s.ss[t * SPB + j];
+                    z += om;
+                    qq += om * om;
+                    na += om * (double)s.eps[(2 * t) * (SPB + 1) + j];
+                    nd += om * (double)s.eps[(2 * t + 1) * (SPB + 1) + j];
+                }
+                double* o = part + 5 * t;
+                o[0] = mt[t];
+                o[1] = z;
+                o[2] = qq;
+                o[3] = na;
+                o[4] = nd;
+            }
+        }
+        for (int t = tid; t < T && !lds; t += kBlock) {
+            auto st_at = [&](int j) { return d.Stk[(size_t)t * K + k_base + j]; };
             double m = INFINITY;
             for (int j = 0; j < n_valid; ++j) {
                 const double v = st_at(j);
@@ -854,23 +919,15 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             }
             double z = 0.0, qq = 0.0, na = 0.0, nd = 0.0;
             if (isfinite(m)) {
-#pragma unroll 1
+#pragma unroll 4
                 for (int j = 0; j < n_valid; ++j) {
                     const double v = st_at(j);
                     const double om = isfinite(v) ? exp(-(v - m) / d.lambda) : 0.0;
-                    float ea, ed;
-                    if (lds) {
-                        ea = s.eps[(2 * t) * (SPB + 1) + j];
-                        ed = s.eps[(2 * t + 1) * (SPB + 1) + j];
-                    } else {
-                        const float2 ev = d.eps[(size_t)t * K + k_base + j];
-                        ea = ev.x;
-                        ed = ev.y;
-                    }
+                    const float2 ev = d.eps[(size_t)t * K + k_base + j];
                     z += om;
                     qq += om * om;
-                    na += om * (double)ea;
-                    nd += om * (double)ed;
+                    na += om * (double)ev.x;
+                    nd += om * (double)ev.y;
                 }
             }
             double* o = part + 5 * t;
@@ -1227,10 +1284,19 @@ __device__ void combine_per_step(const InstDesc& d, int cg)
     const double* u_old = d.smooth ? d.partials + (size_t)n * stride : d.U;
     const double ua_prev = tid < nst ? u_old[2 * (w0 + tid)] : 0.0;
     const double ud_prev = tid < nst ? u_old[2 * (w0 + tid) + 1] : 0.0;
-    // per-step minimum: chunks, then the chunks in order
+    // per-step minimum: chunks (loads eight tiles at a time), then the chunks
+    // in order
+    constexpr int kB = 8;
     double ml = INFINITY;
-    if (worked)
-        for (int b = b0; b < b1; ++b) ml = fmin(ml, col[(size_t)b * stride]);
+    if (worked) {
+        for (int b = b0; b < b1; b += kB) {
+            double mm[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) mm[u] = b + u < b1 ? col[(size_t)(b + u) * stride] : INFINITY;
+#pragma unroll
+            for (int u = 0; u < kB; ++u) ml = fmin(ml, mm[u]);
+        }
+    }
     part[4 * tid] = ml;
     __syncthreads();
     if (tid < nst) {
@@ -1244,13 +1310,24 @@ __device__ void combine_per_step(const InstDesc& d, int cg)
     double z = 0.0, qq = 0.0, na = 0.0, nd = 0.0;
     if (worked) {
         const double m = mt[slot];
-        for (int b = b0; b < b1; ++b) {
-            const double* h = col + (size_t)b * stride;
-            const double sc = isfinite(h[0]) ? exp(-(h[0] - m) / d.lambda) : 0.0;
-            z += h[1] * sc;
-            qq += h[2] * sc * sc;
-            na += h[3] * sc;
-            nd += h[4] * sc;
+        for (int b = b0; b < b1; b += kB) {
+            double hv[kB][5];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const double* h = col + (size_t)min(b + u, b1 - 1) * stride;
+#pragma unroll
+                for (int c = 0; c < 5; ++c) hv[u][c] = h[c];
+            }
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                if (b + u < b1) {
+                    const double sc = isfinite(hv[u][0]) ? exp(-(hv[u][0] - m) / d.lambda) : 0.0;
+                    z += hv[u][1] * sc;
+                    qq += hv[u][2] * sc * sc;
+                    na += hv[u][3] * sc;
+                    nd += hv[u][4] * sc;
+                }
+            }
         }
     }
     __syncthreads();  // the minima in part are read
