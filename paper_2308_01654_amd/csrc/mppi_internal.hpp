@@ -167,8 +167,18 @@ constexpr size_t kLdsShared = 32 << 10;
 constexpr size_t kLdsAlone = 64 << 10;
 
 // Waypoints are grouped in chunks of this many consecutive points; each chunk
-// has an axis-aligned bounding box in LDS for the wave-level culling.
+// has an axis-aligned bounding box in LDS for the wave-level culling.  A
+// chunk is kChunkQ 16-byte (two-point) reads; the culled scan fetches
+// kChunkTrip chunks per memory round trip.  (At the sine-lane workload
+// chunks of 16 are 2% faster and chunks of 4 are 4% slower; at the paper's
+// small scenes chunks of 16 are 5-8% slower.)
 constexpr int kChunk = 8;
+static_assert(kChunk == 4 || kChunk == 8 || kChunk == 16, "chunks of 4, 8 or 16 waypoints");
+constexpr int kChunkQ = kChunk / 2;
+constexpr int kChunkTrip = kChunk < 16 ? 16 / kChunk : 1;
+// The per-lane culling bound takes the waypoints kSeedAhead, 2 kSeedAhead and
+// 3 kSeedAhead after the start of the lane's previous closest chunk.
+constexpr int kSeedAhead = 4;
 
 inline __host__ __device__ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 

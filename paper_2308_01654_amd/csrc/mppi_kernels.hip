@@ -61,20 +61,28 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 // iteration n: counter (k, t/2, n_lo, n_hi); words (r0, r1) for even t and
 // (r2, r3) for odd t; u = ((r >> 9) + 1/2) 2^-23 is exact in float32;
 // Box-Muller with the angle taken in revolutions by the hardware sin/cos.
-__device__ __forceinline__ float2 draw_noise(const InstDesc& d, int k, int t,
+__device__ __forceinline__ uint4 noise_words(const InstDesc& d, int k, int pair,
                                              unsigned long long n)
 {
-    const uint4 r = philox4x32_10(make_uint4((uint32_t)k, (uint32_t)(t >> 1), (uint32_t)n,
-                                             (uint32_t)(n >> 32)),
-                                  d.key0, d.key1);
-    const uint32_t ra = (t & 1) ? r.z : r.x;
-    const uint32_t rb = (t & 1) ? r.w : r.y;
+    return philox4x32_10(make_uint4((uint32_t)k, (uint32_t)pair, (uint32_t)n, (uint32_t)(n >> 32)),
+                         d.key0, d.key1);
+}
+
+__device__ __forceinline__ float2 noise_from_words(const InstDesc& d, uint32_t ra, uint32_t rb)
+{
     const float u1 = ((float)(ra >> 9) + 0.5f) * 0x1p-23f;
     const float u2 = ((float)(rb >> 9) + 0.5f) * 0x1p-23f;
     // -2 ln u1 = -2 ln(2) log2(u1)
     const float rho = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
     return make_float2(d.sig_a * rho * __builtin_amdgcn_cosf(u2),
                        d.sig_d * rho * __builtin_amdgcn_sinf(u2));
+}
+
+__device__ __forceinline__ float2 draw_noise(const InstDesc& d, int k, int t,
+                                             unsigned long long n)
+{
+    const uint4 r = noise_words(d, k, t >> 1, n);
+    return noise_from_words(d, (t & 1) ? r.z : r.x, (t & 1) ? r.w : r.y);
 }
 
 struct Lds {
@@ -111,24 +119,25 @@ __device__ __forceinline__ Lds lds_bind(unsigned char* base, const LdsLayout& L)
 }
 
 // Closest-waypoint update over chunk ch (kChunk consecutive waypoints, padded
-// with points at infinity): the chunk is read with four 16-byte LDS reads and
-// its distances are compared in index order, so ties keep the lowest index.
+// with points at infinity): the chunk is read with 16-byte LDS reads (two
+// points each) and its distances are compared in index order, so ties keep
+// the lowest index.
 __device__ __forceinline__ void scan_chunk(const Lds& s, int ch, float x, float y, float& best,
                                            int& bj)
 {
-    static_assert(kChunk == 8, "chunk layout");
-    const float4* p = reinterpret_cast<const float4*>(s.wp_xy) + ch * (kChunk / 2);
-    const float4 q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
-    const float wx[8] = {q0.x, q0.z, q1.x, q1.z, q2.x, q2.z, q3.x, q3.z};
-    const float wy[8] = {q0.y, q0.w, q1.y, q1.w, q2.y, q2.w, q3.y, q3.w};
+    const float4* p = reinterpret_cast<const float4*>(s.wp_xy) + ch * kChunkQ;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const float dx = x - wx[u];
-        const float dy = y - wy[u];
-        const float dd = fmaf(dy, dy, dx * dx);
-        if (dd < best) {
-            best = dd;
-            bj = ch * kChunk + u;
+    for (int u = 0; u < kChunkQ; ++u) {
+        const float4 q = p[u];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float dx = x - (h ? q.z : q.x);
+            const float dy = y - (h ? q.w : q.y);
+            const float dd = fmaf(dy, dy, dx * dx);
+            if (dd < best) {
+                best = dd;
+                bj = ch * kChunk + 2 * u + h;
+            }
         }
     }
 }
@@ -394,48 +403,49 @@ __device__ __forceinline__ float4 ld4(const_ptr<float> p, int i)
 
 // Smallest squared distance from (x, y) to the 8 points of a waypoint chunk
 // (padded at the end with points at infinity).
-__device__ __forceinline__ float chunk_min(const float4 (&q)[4], float x, float y)
+__device__ __forceinline__ float chunk_min(const float4 (&q)[kChunkQ], float x, float y)
 {
-    const float wx[8] = {q[0].x, q[0].z, q[1].x, q[1].z, q[2].x, q[2].z, q[3].x, q[3].z};
-    const float wy[8] = {q[0].y, q[0].w, q[1].y, q[1].w, q[2].y, q[2].w, q[3].y, q[3].w};
     float m = INFINITY;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-        const float dx = x - wx[u];
-        const float dy = y - wy[u];
-        m = fminf(m, fmaf(dy, dy, dx * dx));
+    for (int u = 0; u < kChunkQ; ++u) {
+        const float dx0 = x - q[u].x, dy0 = y - q[u].y;
+        const float dx1 = x - q[u].z, dy1 = y - q[u].w;
+        m = fminf(m, fmaf(dy0, dy0, dx0 * dx0));
+        m = fminf(m, fmaf(dy1, dy1, dx1 * dx1));
     }
     return m;
 }
 
-// Scans the chunks whose bits are set in m (ascending, two per memory round
-// trip, read from global memory with scalar loads): best = smallest squared
-// distance, bch = first chunk that attains it.  An odd last chunk is paired
-// with itself: the repeat cannot be strictly smaller, so nothing changes,
-// and the pair's loads are issued together without a branch between them.
+// Scans the chunks whose bits are set in m (ascending, kChunkTrip per memory
+// round trip, read from global memory with scalar loads): best = smallest
+// squared distance, bch = first chunk that attains it.  A short last group
+// repeats its first chunk: the repeat cannot be strictly smaller, so nothing
+// changes, and the group's loads are issued together without a branch
+// between them.
 __device__ __forceinline__ void scan_chunks(const_ptr<float> wp4, int base, unsigned long long m,
                                             float x, float y, float& best, int& bch)
 {
     while (m) {
-        const int c0 = base + __builtin_ctzll(m);
+        int c[kChunkTrip];
+        c[0] = base + __builtin_ctzll(m);
         m &= m - 1;
-        const int c1 = m ? base + __builtin_ctzll(m) : c0;
-        m &= m - 1;
-        float4 q0[4], q1[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            q0[u] = ld4(wp4, c0 * 4 + u);
-            q1[u] = ld4(wp4, c1 * 4 + u);
+        for (int i = 1; i < kChunkTrip; ++i) {
+            c[i] = m ? base + __builtin_ctzll(m) : c[0];
+            m &= m - 1;
         }
-        const float m0 = chunk_min(q0, x, y);
-        const float m1 = chunk_min(q1, x, y);
-        if (m0 < best) {
-            best = m0;
-            bch = c0;
-        }
-        if (m1 < best) {
-            best = m1;
-            bch = c1;
+        float4 q[kChunkTrip][kChunkQ];
+#pragma unroll
+        for (int i = 0; i < kChunkTrip; ++i)
+#pragma unroll
+            for (int u = 0; u < kChunkQ; ++u) q[i][u] = ld4(wp4, c[i] * kChunkQ + u);
+#pragma unroll
+        for (int i = 0; i < kChunkTrip; ++i) {
+            const float mi = chunk_min(q[i], x, y);
+            if (mi < best) {
+                best = mi;
+                bch = c[i];
+            }
         }
     }
 }
@@ -446,16 +456,17 @@ __device__ __forceinline__ void scan_chunks(const_ptr<float> wp4, int base, unsi
 __device__ __forceinline__ int chunk_argmin(const Lds& s, int bch, float best, float x, float y)
 {
     if (!(best < INFINITY)) return 0;
-    const float4* p = reinterpret_cast<const float4*>(s.wp_xy) + bch * (kChunk / 2);
-    const float4 q0 = p[0], q1 = p[1], q2 = p[2], q3 = p[3];
-    const float wx[8] = {q0.x, q0.z, q1.x, q1.z, q2.x, q2.z, q3.x, q3.z};
-    const float wy[8] = {q0.y, q0.w, q1.y, q1.w, q2.y, q2.w, q3.y, q3.w};
+    const float4* p = reinterpret_cast<const float4*>(s.wp_xy) + bch * kChunkQ;
     int bj = bch * kChunk;
 #pragma unroll
-    for (int u = 7; u >= 0; --u) {
-        const float dx = x - wx[u];
-        const float dy = y - wy[u];
-        if (fmaf(dy, dy, dx * dx) == best) bj = bch * kChunk + u;
+    for (int u = kChunkQ - 1; u >= 0; --u) {
+        const float4 q = p[u];
+#pragma unroll
+        for (int h = 1; h >= 0; --h) {
+            const float dx = x - (h ? q.z : q.x);
+            const float dy = y - (h ? q.w : q.y);
+            if (fmaf(dy, dy, dx * dx) == best) bj = bch * kChunk + 2 * u + h;
+        }
     }
     return bj;
 }
@@ -523,7 +534,7 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
         if (seed >= 0) {
 #pragma unroll
             for (int u = 0; u < 3; ++u) {
-                const float2 w = s.wp_xy[min(seed * kChunk + (u + 1) * (kChunk / 2), d.n_wp - 1)];
+                const float2 w = s.wp_xy[min(seed * kChunk + (u + 1) * kSeedAhead, d.n_wp - 1)];
                 const float dx = x - w.x;
                 const float dy = y - w.y;
                 own = fminf(own, fmaf(dy, dy, dx * dx));
@@ -696,6 +707,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     float S = 0.0f, comp = 0.0f;  // Kahan pair of this lane's steps
     int seed = -1;                // closest chunk at this lane's previous step
     const int gbase = tid & ~(G - 1);  // first lane of this sample's group
+    uint4 held = make_uint4(0u, 0u, 0u, 0u);  // Philox words kept for the next block
     for (int t0 = 0; t0 < T; t0 += G) {
         const int tm = t0 + r;
         // The lane's step within the block, opaque to the compiler so that the
@@ -708,7 +720,32 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         // noise check (control bounds) and -- for the steering-angle control --
         // its tangent.  With the 5-state model the second control is the
         // steering rate.
-        const float2 em = draw_noise(d, kk, tc, n_iter);
+        // One Philox call gives the words of two consecutive steps.  With
+        // G >= 2 lanes per sample the calls of two blocks are made together
+        // in the first of them: lane 2i holds step pair i of that block and
+        // lane 2i + 1 pair i of the next, and each lane takes its step's two
+        // words from itself or its neighbour (quad-permute DPP).  Lanes past
+        // the horizon draw the words of their own (unused) steps.
+        float2 em;
+        if (G == 1) {
+            em = draw_noise(d, kk, tc, n_iter);
+        } else {
+            const bool second = ((t0 / G) & 1) != 0;
+            if (!second) held = noise_words(d, kk, t0 / 2 + ((r & 1) ? G / 2 : 0) + (r >> 1), n_iter);
+            uint32_t ra, rb;
+            if (!second) {  // odd lanes take the odd-step words of the even lane below
+                const uint32_t nz = (uint32_t)dpp_i<0xA0>(0, (int)held.z);
+                const uint32_t nw = (uint32_t)dpp_i<0xA0>(0, (int)held.w);
+                ra = (r & 1) ? nz : held.x;
+                rb = (r & 1) ? nw : held.y;
+            } else {        // even lanes take the even-step words of the odd lane above
+                const uint32_t nx = (uint32_t)dpp_i<0xF5>(0, (int)held.x);
+                const uint32_t ny = (uint32_t)dpp_i<0xF5>(0, (int)held.y);
+                ra = (r & 1) ? held.z : nx;
+                rb = (r & 1) ? held.w : ny;
+            }
+            em = noise_from_words(d, ra, rb);
+        }
         const float2 Um = s.U[tc];
         const float a0m = fminf(fmaxf(Um.x + em.x, d.a_min), d.a_max);
         const float dlm = fminf(fmaxf(Um.y + em.y, d.d_min), d.d_max);
