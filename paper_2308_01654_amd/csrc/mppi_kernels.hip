@@ -297,10 +297,26 @@ __device__ __forceinline__ float seg_prev(float incl, int r)
     const float u = dpp_shr<1>(incl);
     return r >= 1 ? u : 0.0f;
 }
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+// The group's last lane's value in every lane of the group, by DPP: quad
+// permutes for groups of 2 and 4, row broadcasts (row_newbcast) of lanes 7
+// and 15 for groups of 8 and 16.
 template <int G>
 __device__ __forceinline__ float group_last(float v, int gbase)
 {
-    return G > 1 ? __shfl(v, gbase + G - 1, 64) : v;
+    (void)gbase;
+    if (G == 1) return v;
+    if (G == 2) return dpp_f<0xF5>(v);   // quad_perm [1, 1, 3, 3]
+    if (G == 4) return dpp_f<0xFF>(v);   // quad_perm [3, 3, 3, 3]
+    const float hi = dpp_f<0x15F>(v);    // row_newbcast:15
+    if (G == 16) return hi;
+    const float lo = dpp_f<0x157>(v);    // row_newbcast:7
+    return (threadIdx.x & 8) ? hi : lo;
 }
 
 // Wave-wide reduction stages: swap neighbours and quad halves, mirror inside
