@@ -266,8 +266,8 @@ def main(argv=None):
                     help="skip the smoothing, trajectory, per-step and paper-scenario timings")
     args = ap.parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build runs the iteration on a single "
-              "MI355X (--gpus 1); multi-GPU runs are not part of it.", file=sys.stderr)
+        print("bench.py measures one GPU only: the iteration runs on a single MI355X "
+              "(--gpus 1); runs on several GPUs are not supported.", file=sys.stderr)
         return 2
 
     if args.probe:

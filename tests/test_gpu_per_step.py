@@ -38,10 +38,13 @@ def _say(*a):
     sys.stdout.flush()
 
 
-OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+# parity reports are written as JSON when MPPI_PARITY_OUT names a folder
+OUT = os.environ.get("MPPI_PARITY_OUT")
 
 
 def _dump(name, obj):
+    if not OUT:
+        return
     os.makedirs(OUT, exist_ok=True)
     with open(os.path.join(OUT, "parity_per_step_%s.json" % name), "w") as f:
         json.dump(obj, f, indent=1, default=float)
