@@ -180,6 +180,53 @@ def paper_cost_kernels(steps=50):
     return out
 
 
+def batched(n=256, steps=10):
+    """The batched workload: n uneven sine-lane instances (K, T and circle
+    counts drawn per instance) stepped together by mppi_step_batch (one
+    graph replay per step, resident scenes), against the same instances
+    stepped one at a time on the same stream.  Total rollout-steps/s of
+    each, HIP events around `steps` warm-started steps."""
+    from paper_2308_01654_amd import mppi, scenes
+    insts = scenes.c2(n)
+    pls = [mppi.Planner(insts[0]["params"])]
+    try:
+        st = pls[0].stream()
+        pls += [mppi.Planner(sc["params"], hip_stream=st) for sc in insts[1:]]
+        for pl, sc in zip(pls, insts):
+            pl.set_scene(sc["x0"], sc["waypoints"], sc["circles"])
+        x0s = [sc["x0"] for sc in insts]
+        work = sum(sc["params"]["K"] * sc["params"]["T"] for sc in insts)
+        ev = HipEvents()
+
+        def timed(fn):
+            for _ in range(2):
+                fn()
+            pls[0].sync()
+            e0, e1 = ev.event(), ev.event()
+            ev.record(e0, st)
+            for _ in range(steps):
+                fn()
+            ev.record(e1, st)
+            ms = ev.elapsed_ms(e0, e1) / steps
+            ev.destroy(e0)
+            ev.destroy(e1)
+            return ms
+
+        def alone():
+            for pl, x0 in zip(pls, x0s):
+                pl.step_resident(x0)
+
+        ms_b = timed(lambda: mppi.step_batch(pls, x0s))
+        ms_a = timed(alone)
+    finally:
+        for pl in reversed(pls):
+            pl.close()
+    return {"instances": n, "rollout_steps_per_batch": int(work),
+            "batch_ms": round(ms_b, 4), "batch_rollout_steps_per_s": round(work / (ms_b * 1e-3), 1),
+            "one_at_a_time_ms": round(ms_a, 4),
+            "one_at_a_time_rollout_steps_per_s": round(work / (ms_a * 1e-3), 1)}
+
+
 def c3_load(n_vehicles, duration_s, pool_size=512, seed=33):
     """Served load: vehicles with their own (K, T) and seeds replanning at
     20 Hz with exponential inter-arrival times (mean 50 ms) and a random
@@ -263,7 +310,7 @@ def main(argv=None):
                     help="duration of the served load (0 skips the served comparison)")
     ap.add_argument("--plain-seconds", type=float, default=1.0)
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the smoothing, trajectory, per-step and paper-scenario timings")
+                    help="skip the smoothing, trajectory, per-step, paper-scenario and batched timings")
     args = ap.parse_args(argv)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the iteration runs on a single MI355X "
@@ -344,10 +391,11 @@ def main(argv=None):
     pl.sync()
     pcie_value = K * T * 50 / (time.perf_counter() - a)
     pl.close()
-    smooth = None
+    smooth = bat = None
     if not args.no_extras:
         smooth = alg1_output(p, x0, wp, circ, args.warmup, args.steps)
         smooth.update(paper_cost_kernels())
+        bat = batched()
 
     out = {
         "metric": METRIC,
@@ -372,6 +420,7 @@ def main(argv=None):
         "wall_s_timed": round(t1 - t0, 4),
         "host_staged_value": round(pcie_value, 1),
         "alg1_output": smooth,
+        "batched": bat,
     }
     if args.served_seconds > 0:
         sv = served(duration_s=args.served_seconds, plain_duration_s=args.plain_seconds)
