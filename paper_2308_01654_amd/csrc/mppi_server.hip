@@ -324,6 +324,12 @@ void scheduler_loop(mppi_server* srv)
             srv->done_cv.notify_all();
             continue;
         }
+        // the scenes were staged by the launch; the requests keep only what
+        // poll returns
+        for (Req* r : b) {
+            std::vector<double>().swap(r->wp);
+            std::vector<double>().swap(r->ci);
+        }
         sc->batch = std::move(b);
         sc->launched = true;
         sc->cv.notify_one();
@@ -620,6 +626,14 @@ mppi_status mppi_server_replay(mppi_server_t* srv, const mppi_replay_plan* plan,
         if (plan->scene[i] < 0 || plan->scene[i] >= plan->n_scenes)
             return fail(MPPI_E_INVALID, "scene index out of range at request %d", i);
     std::vector<uint64_t> tickets(n, 0), t_arr(n, 0);
+    {
+        // every request stays in the ticket table until it is polled below:
+        // size the table now, so that no rehash runs under the server lock
+        // while requests are in flight
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->live.reserve(srv->live.size() + (size_t)n);
+        srv->lat_ms.reserve(srv->lat_ms.size() + (size_t)n);
+    }
     const uint64_t t0 = now_ns() + 2000000;  // start 2 ms from now
     for (int i = 0; i < n; ++i) {
         const uint64_t target = t0 + plan->arrival_ns[i];
