@@ -1287,16 +1287,22 @@ __device__ void combine(const InstDesc& d, int cg)
 // minimum m_b,t of the cost-to-go and the shifted sums Z, Q, N_a, N_d.  A
 // workgroup updates kCombineSteps steps (and, with smoothing, the two on
 // either side): per step the minimum over the tiles, each tile's sums
-// shifted to it by exp(-(m_b,t - m_t)/lambda) (tiles in chunks of
-// consecutive tiles, then the chunks in order), U_t += N_t / Z_t.  A sample
-// whose total cost is finite has a finite cost-to-go at every step, so every
-// step is finite exactly when step 0 is; without a finite step 0 nothing is
-// written.  Workgroup 0 records the statistics of step 0.
+// shifted to it by exp(-(m_b,t - m_t)/lambda), U_t += N_t / Z_t.  Thread
+// (chunk, slot) takes step slot over a chunk of consecutive tiles, in tile
+// order; the chunks of a wave are merged by a fixed butterfly, then the four
+// waves in order.  The step-0 heads and the first kPsBatch rows of the
+// thread's chunk are loaded in one round trip and kept in registers for both
+// passes.  A sample whose total cost is finite has a finite cost-to-go at
+// every step, so every step is finite exactly when step 0 is; without a
+// finite step 0 nothing is written.  Workgroup 0 records the statistics of
+// step 0.
+constexpr int kPsBatch = 16;
+
 __device__ void combine_per_step(const InstDesc& d, int cg)
 {
     extern __shared__ __align__(16) unsigned char csm[];
     double* red = reinterpret_cast<double*>(csm);  // [64]
-    double* part = red + 64;                       // [kBlock][4] chunk partials
+    double* part = red + 64;                       // [4 waves][8 slots][4] wave partials
     double* mt = part + 4 * kBlock;                // [8] step minima
     double* un = mt + 8;                           // [16] updated worked columns
     const int tid = threadIdx.x;
@@ -1312,21 +1318,7 @@ __device__ void combine_per_step(const InstDesc& d, int cg)
     const size_t stride = partial_stride(T, 1);
     const int n = d.n_tiles;
     const double* rows = d.partials;
-
-    // step 0: minimum over the tiles (every workgroup)
-    double m0 = INFINITY;
-    for (int b = tid; b < n; b += kBlock) m0 = fmin(m0, rows[(size_t)b * stride]);
-    const double w0m = wave_min(m0);
     const int wv = tid >> 6;
-    if ((tid & 63) == 0) red[wv] = w0m;
-    __syncthreads();
-    m0 = red[0];
-#pragma unroll
-    for (int i = 1; i < kBlock / 64; ++i) m0 = fmin(m0, red[i]);
-    if (!isfinite(m0)) {
-        if (cg == 0 && tid == 0) d.st->status = -4;  // MPPI_E_NONFINITE: U and n unchanged
-        return;
-    }
 
     const int slot = tid % kSlots, chunk = tid / kSlots;
     const bool worked = slot < nst;
@@ -1337,64 +1329,96 @@ __device__ void combine_per_step(const InstDesc& d, int cg)
     const double* u_old = d.smooth ? d.partials + (size_t)n * stride : d.U;
     const double ua_prev = tid < nst ? u_old[2 * (w0 + tid)] : 0.0;
     const double ud_prev = tid < nst ? u_old[2 * (w0 + tid) + 1] : 0.0;
-    // per-step minimum: chunks (loads eight tiles at a time), then the chunks
-    // in order
-    constexpr int kB = 8;
-    double ml = INFINITY;
-    if (worked) {
-        for (int b = b0; b < b1; b += kB) {
-            double mm[kB];
+
+    // one round trip: the step-0 heads and the chunk's first rows
+    double m0 = INFINITY;
 #pragma unroll
-            for (int u = 0; u < kB; ++u) mm[u] = b + u < b1 ? col[(size_t)(b + u) * stride] : INFINITY;
-#pragma unroll
-            for (int u = 0; u < kB; ++u) ml = fmin(ml, mm[u]);
-        }
+    for (int r = 0; r < 2; ++r) {
+        const int b = tid + r * kBlock;
+        if (b < n) m0 = fmin(m0, rows[(size_t)b * stride]);
     }
-    part[4 * tid] = ml;
+    for (int b = tid + 2 * kBlock; b < n; b += kBlock) m0 = fmin(m0, rows[(size_t)b * stride]);
+    double hv[kPsBatch][5];
+#pragma unroll
+    for (int u = 0; u < kPsBatch; ++u) {
+        const bool on = worked && b0 + u < b1;
+        const double* h = col + (size_t)(on ? b0 + u : 0) * stride;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) hv[u][c] = on ? h[c] : (c == 0 ? INFINITY : 0.0);
+    }
+
+    // step 0: minimum over the tiles (every workgroup)
+    const double w0m = wave_min(m0);
+    if ((tid & 63) == 0) red[wv] = w0m;
     __syncthreads();
-    if (tid < nst) {
-        double m = INFINITY;
-#pragma unroll 4
-        for (int c = 0; c < kChunks; ++c) m = fmin(m, part[4 * (c * kSlots + tid)]);
+    m0 = red[0];
+#pragma unroll
+    for (int i = 1; i < kBlock / 64; ++i) m0 = fmin(m0, red[i]);
+    if (!isfinite(m0)) {
+        if (cg == 0 && tid == 0) d.st->status = -4;  // MPPI_E_NONFINITE: U and n unchanged
+        return;
+    }
+
+    // per-step minimum: the chunk (rows past the first batch loaded again),
+    // the chunks of the wave, then the waves
+    double ml = INFINITY;
+#pragma unroll
+    for (int u = 0; u < kPsBatch; ++u) ml = fmin(ml, hv[u][0]);
+    if (worked)
+        for (int b = b0 + kPsBatch; b < b1; ++b) ml = fmin(ml, col[(size_t)b * stride]);
+#pragma unroll
+    for (int o = kSlots; o < 64; o <<= 1) ml = fmin(ml, __shfl_xor(ml, o, 64));
+    if ((tid & 63) < kSlots) part[4 * (wv * kSlots + slot)] = ml;
+    __syncthreads();
+    if (tid < kSlots) {
+        double m = part[4 * tid];
+#pragma unroll
+        for (int w = 1; w < kBlock / 64; ++w) m = fmin(m, part[4 * (w * kSlots + tid)]);
         mt[tid] = m;
     }
     __syncthreads();
+
     // shifted sums of the chunk's tiles in tile order
     double z = 0.0, qq = 0.0, na = 0.0, nd = 0.0;
     if (worked) {
         const double m = mt[slot];
-        for (int b = b0; b < b1; b += kB) {
-            double hv[kB][5];
+        auto add = [&](const double (&h)[5]) {
+            const double sc = isfinite(h[0]) ? exp(-(h[0] - m) / d.lambda) : 0.0;
+            z += h[1] * sc;
+            qq += h[2] * sc * sc;
+            na += h[3] * sc;
+            nd += h[4] * sc;
+        };
 #pragma unroll
-            for (int u = 0; u < kB; ++u) {
-                const double* h = col + (size_t)min(b + u, b1 - 1) * stride;
-#pragma unroll
-                for (int c = 0; c < 5; ++c) hv[u][c] = h[c];
-            }
-#pragma unroll
-            for (int u = 0; u < kB; ++u) {
-                if (b + u < b1) {
-                    const double sc = isfinite(hv[u][0]) ? exp(-(hv[u][0] - m) / d.lambda) : 0.0;
-                    z += hv[u][1] * sc;
-                    qq += hv[u][2] * sc * sc;
-                    na += hv[u][3] * sc;
-                    nd += hv[u][4] * sc;
-                }
-            }
+        for (int u = 0; u < kPsBatch; ++u)
+            if (b0 + u < b1) add(hv[u]);
+        for (int b = b0 + kPsBatch; b < b1; ++b) {
+            const double* hp = col + (size_t)b * stride;
+            const double h[5] = {hp[0], hp[1], hp[2], hp[3], hp[4]};
+            add(h);
         }
     }
+#pragma unroll
+    for (int o = kSlots; o < 64; o <<= 1) {
+        z += __shfl_xor(z, o, 64);
+        qq += __shfl_xor(qq, o, 64);
+        na += __shfl_xor(na, o, 64);
+        nd += __shfl_xor(nd, o, 64);
+    }
     __syncthreads();  // the minima in part are read
-    part[4 * tid] = z;
-    part[4 * tid + 1] = qq;
-    part[4 * tid + 2] = na;
-    part[4 * tid + 3] = nd;
+    if ((tid & 63) < kSlots) {
+        double* pw = part + 4 * (wv * kSlots + slot);
+        pw[0] = z;
+        pw[1] = qq;
+        pw[2] = na;
+        pw[3] = nd;
+    }
     __syncthreads();
-    double zt = 0.0, qt = 0.0;
     if (tid < nst) {
-        double sa = 0.0, sd = 0.0;
-#pragma unroll 4
-        for (int c = 0; c < kChunks; ++c) {
-            const double* pc = part + 4 * (c * kSlots + tid);
+        double zt = 0.0, qt = 0.0, sa = 0.0, sd = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) {
+            const double* pc = part + 4 * (w * kSlots + tid);
             zt += pc[0];
             qt += pc[1];
             sa += pc[2];
