@@ -459,26 +459,24 @@ mppi_status mppi_server_submit(mppi_server_t* srv, int32_t vid, const double x0[
     if (s != MPPI_OK) return s;
     Req* r = new (std::nothrow) Req();
     if (!r) return fail(MPPI_E_NOMEM, "host allocation failed");
+    mppi_config c;
+    int lanes_req = 0;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         if (vid < 0 || vid >= (int)srv->veh.size()) {
             delete r;
             return fail(MPPI_E_INVALID, "unknown vehicle %d", vid);
         }
-        const mppi_config& c = srv->veh[vid].h->cfg;
-        if ((s = validate_scene(c, x0, scene)) != MPPI_OK) {
-            delete r;
-            return s;
-        }
-        if (srv->queued >= (size_t)srv->cfg.queue_cap) {
-            ++srv->rejected;
-            delete r;
-            return fail(MPPI_E_BUSY, "queue full (%d requests)", srv->cfg.queue_cap);
-        }
-        r->lanes = srv->veh[vid].h->lanes_req ? srv->veh[vid].h->lanes_req
-                                              : auto_lanes(c, scene->n_circles);
-        r->bytes = request_bytes(c, r->lanes);
+        c = srv->veh[vid].h->cfg;
+        lanes_req = srv->veh[vid].h->lanes_req;
     }
+    // the scene is checked outside the server lock
+    if ((s = validate_scene(c, x0, scene)) != MPPI_OK) {
+        delete r;
+        return s;
+    }
+    r->lanes = lanes_req ? lanes_req : auto_lanes(c, scene->n_circles);
+    r->bytes = request_bytes(c, r->lanes);
     r->vid = vid;
     memcpy(r->x0, x0, sizeof r->x0);
     r->wp.assign(scene->waypoints, scene->waypoints + 4 * scene->n_waypoints);
@@ -487,6 +485,11 @@ mppi_status mppi_server_submit(mppi_server_t* srv, int32_t vid, const double x0[
     r->keep = ticket != nullptr;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->queued >= (size_t)srv->cfg.queue_cap) {
+            ++srv->rejected;
+            delete r;
+            return fail(MPPI_E_BUSY, "queue full (%d requests)", srv->cfg.queue_cap);
+        }
         r->ticket = srv->next_ticket++;
         if (ticket) *ticket = r->ticket;
         srv->live[r->ticket] = r;
