@@ -724,14 +724,22 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     int seed = -1;                // closest chunk at this lane's previous step
     const int gbase = tid & ~(G - 1);  // first lane of this sample's group
     uint4 held = make_uint4(0u, 0u, 0u, 0u);  // Philox words kept for the next block
-    for (int t0 = 0; t0 < T; t0 += G) {
+    // A horizon that is not a whole number of blocks starts with the partial
+    // block (its leading lanes own no step), where the samples are still
+    // close together and the culled scans are short, rather than ending with
+    // it, where they have spread the most.  Kept even so that Philox step
+    // pairs stay within a lane pair.
+    const int rem = T % G;
+    int blk = 0;
+    for (int t0 = (rem != 0 && (rem & 1) == 0) ? rem - G : 0; t0 < T; t0 += G, ++blk) {
         const int tm = t0 + r;
+        const bool lead = tm < 0;  // before the horizon: no step, no increment
         // The lane's step within the block, opaque to the compiler so that the
         // per-step "own step" tests stay in the loop as vector compares
         // instead of G hoisted scalar masks (which exhaust the SGPRs).
         int rb = r;
         asm volatile("" : "+v"(rb));
-        const int tc = tm < T ? tm : T - 1;
+        const int tc = min(max(tm, 0), T - 1);
         // This lane's step: perturbation, the state-independent part of the
         // noise check (control bounds) and -- for the steering-angle control --
         // its tangent.  With the 5-state model the second control is the
@@ -740,13 +748,13 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         // G >= 2 lanes per sample the calls of two blocks are made together
         // in the first of them: lane 2i holds step pair i of that block and
         // lane 2i + 1 pair i of the next, and each lane takes its step's two
-        // words from itself or its neighbour (quad-permute DPP).  Lanes past
-        // the horizon draw the words of their own (unused) steps.
+        // words from itself or its neighbour (quad-permute DPP).  Lanes
+        // outside the horizon draw the words of their own (unused) steps.
         float2 em;
         if (G == 1) {
             em = draw_noise(d, kk, tc, n_iter);
         } else {
-            const bool second = ((t0 / G) & 1) != 0;
+            const bool second = (blk & 1) != 0;
             if (!second) held = noise_words(d, kk, t0 / 2 + ((r & 1) ? G / 2 : 0) + (r >> 1), n_iter);
             uint32_t ra, rb;
             if (!second) {  // odd lanes take the odd-step words of the even lane below
@@ -777,9 +785,11 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         // the recursion step by step (accelerations exchanged PF at a time),
         // each keeping the speed before its own step.  Steps past the horizon
         // (last block) are run too; the lanes that own them are inactive.
+        // Lanes before it (first block) add zero increments, which leave the
+        // closed form unchanged (their prefix sums equal v_0 <= v_max's).
         float vr = v;
         if (__ballot(v > d.v_max) == 0ull) {
-            const float sincl = seg_scan<G>(d.dt * a0m, r);
+            const float sincl = seg_scan<G>(lead ? 0.0f : d.dt * a0m, r);
             const float sr = seg_prev<G>(sincl, r);
             const float qr = seg_scan_max<G>(r >= 1 ? sr : -INFINITY, r);
             vr = fminf(v + sr, d.v_max + (sr - qr));
@@ -794,9 +804,11 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
                         apf[u] = G > 1 ? __shfl(a0m, gbase + i + u, 64) : a0m;
                 }
                 vr = i == rb ? v : vr;
-                float a = fminf(apf[i % PF], (d.v_max - v) * d.inv_dt);
-                a = fmaxf(a, d.a_min);
-                v = fmaf(d.dt, a, v);
+                if (t0 + i >= 0) {
+                    float a = fminf(apf[i % PF], (d.v_max - v) * d.inv_dt);
+                    a = fmaxf(a, d.a_min);
+                    v = fmaf(d.dt, a, v);
+                }
             }
         }
         // the own step's applied acceleration (noise check: speed cap,
@@ -811,11 +823,11 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         // of the group (each lane adds its own step's increment).  With the
         // 5-state model the heading turns with the steering angle before the
         // step, itself the sum of the applied rates.
-        const float vdt = vr * d.dt;
+        const float vdt = lead ? 0.0f : vr * d.dt;
         float tn = tnm;
         float ddel_blk = 0.0f;
         if (M5) {
-            const float dincl = seg_scan<G>(d.dt * tnm, r);
+            const float dincl = seg_scan<G>(lead ? 0.0f : d.dt * tnm, r);
             tn = __tanf(delta + seg_prev<G>(dincl, r));
             ddel_blk = group_last<G>(dincl, gbase);
         }
@@ -840,11 +852,11 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         const float mc = __cosf(mth), ms = __sinf(mth);
         const float mUa = Um.x, mUd = Um.y;
         const float mea = ma - Um.x, med = dlm - Um.y;
-        const bool act = tm < T;
+        const bool act = !lead && tm < T;
         float q = 0.0f;
         if (d.cull)
-            q = stage_cost_culled<NE>(d, s, lc, vref_uniform, act, seed, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm, t0,
-                                      min(t0 + G, T) - 1, mth, pxp, pyp);
+            q = stage_cost_culled<NE>(d, s, lc, vref_uniform, act, seed, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm,
+                                      max(t0, 0), min(t0 + G, T) - 1, mth, pxp, pyp);
         else if (act)
             q = stage_cost<NE>(d, s, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm, mth, pxp, pyp);
         if (act && d.per_step) {
