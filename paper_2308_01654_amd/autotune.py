@@ -1,7 +1,7 @@
 """Autotuner of the iteration kernel's launch shape (lanes per sample).
 
-For every shape bucket -- K in powers of two, T buckets (<=32, <=64, <=128,
-<=256, >256) and circle-count buckets (0, <=16, <=64, <=256, >256) -- it runs
+For every shape bucket -- K in powers of two, T buckets (<=16, <=32, <=64,
+<=128, <=256, >256) and circle-count buckets (0, <=16, <=64, <=256, >256) -- it runs
 a representative sine-lane instance with every lanes-per-sample shape
 (1, 2, 4, 8, 16), times whole iterations with HIP events, and writes the
 fastest shape as a line "k_log2 t_bucket c_bucket lanes" of ``tuning.txt``.
@@ -26,7 +26,7 @@ ROOT = os.path.dirname(HERE)
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-T_REPS = {0: 30, 1: 60, 2: 100, 3: 200, 4: 400}
+T_REPS = {0: 16, 1: 30, 2: 60, 3: 100, 4: 200, 5: 400}
 C_REPS = {0: 0, 1: 12, 2: 60, 3: 200, 4: 512}
 LANES = (1, 2, 4, 8, 16)
 
@@ -57,13 +57,13 @@ def main(argv=None):
     ap.add_argument("--out", default=os.path.join(HERE, "tuning.txt"))
     ap.add_argument("--k-min", type=int, default=10)
     ap.add_argument("--k-max", type=int, default=18)
-    ap.add_argument("--t-buckets", default="0,1,2,3")
+    ap.add_argument("--t-buckets", default="0,1,2,3,4")
     ap.add_argument("--c-buckets", default="0,1,2,3,4")
     args = ap.parse_args(argv)
     lines = ["# lanes-per-sample tuning table of the MPPI iteration kernel",
              "# written by: python -m paper_2308_01654_amd.autotune (HIP-event iteration time, "
              "fastest of lanes 1/2/4/8/16)",
-             "# columns: k_log2 t_bucket c_bucket lanes   (t: <=32,<=64,<=128,<=256,>256; "
+             "# columns: k_log2 t_bucket c_bucket lanes   (t: <=16,<=32,<=64,<=128,<=256,>256; "
              "c: 0,<=16,<=64,<=256,>256)"]
     t0 = time.time()
     for kb in range(args.k_min, args.k_max + 1):

@@ -197,7 +197,10 @@ static int k_bucket(int K)
     while ((1 << b) < K && b < 30) ++b;
     return b;
 }
-static int t_bucket(int T) { return T <= 32 ? 0 : T <= 64 ? 1 : T <= 128 ? 2 : T <= 256 ? 3 : 4; }
+static int t_bucket(int T)
+{
+    return T <= 16 ? 0 : T <= 32 ? 1 : T <= 64 ? 2 : T <= 128 ? 3 : T <= 256 ? 4 : 5;
+}
 static int c_bucket(int n) { return n == 0 ? 0 : n <= 16 ? 1 : n <= 64 ? 2 : n <= 256 ? 3 : 4; }
 
 static void load_tuning()
