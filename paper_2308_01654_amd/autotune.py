@@ -39,7 +39,9 @@ def shape_scene(K, T, n_c):
                 circles=scenes.sine_circles(rng, n_c))
 
 
-def time_shape(sc, lanes, reps):
+def time_shape(sc, lanes, reps, rounds=3):
+    """Best of `rounds` HIP-event timings of `reps` back-to-back iterations
+    (the best filters out the other work of a shared GPU)."""
     from paper_2308_01654_amd import mppi
     from paper_2308_01654_amd.hip_events import time_steps
     pl = mppi.Planner(sc["params"], lanes=lanes)
@@ -47,7 +49,7 @@ def time_shape(sc, lanes, reps):
         pl.set_scene(sc["x0"], sc["waypoints"], sc["circles"])
         pl.step_resident(sc["x0"])
         pl.sync()
-        return time_steps(pl, sc["x0"], reps)
+        return min(time_steps(pl, sc["x0"], reps) for _ in range(rounds))
     finally:
         pl.close()
 
@@ -62,7 +64,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     lines = ["# lanes-per-sample tuning table of the MPPI iteration kernel",
              "# written by: python -m paper_2308_01654_amd.autotune (HIP-event iteration time, "
-             "fastest of lanes 1/2/4/8/16)",
+             "best of 3 rounds, fastest of lanes 1/2/4/8/16)",
              "# columns: k_log2 t_bucket c_bucket lanes   (t: <=16,<=32,<=64,<=128,<=256,>256; "
              "c: 0,<=16,<=64,<=256,>256)"]
     t0 = time.time()
