@@ -1039,8 +1039,23 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             if (L.eps_staged) {
                 const float* e = s.eps + col * (SPB + 1);
                 double acc = 0.0;
-                for (int j = 0; j < n_valid; ++j)
-                    acc = fma((double)s.omega[j], (double)e[j], acc);
+                // whole tiles: every LDS read issued before the chain of FMAs
+                constexpr int NU = SPB < 32 ? SPB : 32;
+                if (n_valid == SPB) {
+                    for (int j0 = 0; j0 < SPB; j0 += NU) {
+                        float om[NU], ev[NU];
+#pragma unroll
+                        for (int u = 0; u < NU; ++u) {
+                            om[u] = s.omega[j0 + u];
+                            ev[u] = e[j0 + u];
+                        }
+#pragma unroll
+                        for (int u = 0; u < NU; ++u) acc = fma((double)om[u], (double)ev[u], acc);
+                    }
+                } else {
+                    for (int j = 0; j < n_valid; ++j)
+                        acc = fma((double)s.omega[j], (double)e[j], acc);
+                }
                 part[kPartialHead + col] = acc;
                 continue;
             }
