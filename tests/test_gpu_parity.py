@@ -124,6 +124,25 @@ def test_ragged_shapes(K, T, n_c, lanes):
             assert np.allclose(g["U"], U0 + g["eps"][:, 0, :], rtol=0, atol=1e-12)
 
 
+@pytest.mark.parametrize("lanes", [1, 16])
+def test_maximum_sizes(lanes):
+    """Horizon, waypoint and circle counts at their maxima (2048, 2048, 1024):
+    the workgroup's LDS then holds more than 64 KB; a ragged K; the costs of
+    every tenth sample against the oracle."""
+    mppi = _mppi()
+    rng = np.random.Generator(np.random.PCG64(5))
+    p = scenes.params(K=300, T=2048, dt=0.05, v_max=15.0, seed=3)
+    sc = dict(params=p, x0=scenes._sine_x0(), waypoints=scenes.sine_lane(-20.0, 2027.0, 15.0),
+              circles=scenes.sine_circles(rng, 1024, 10.0, 1500.0))
+    assert len(sc["waypoints"]) == 2048 and len(sc["circles"]) == 1024
+    _say("maximum sizes", lanes)
+    with mppi.Planner(p, max_waypoints=2048, max_circles=1024, lanes=lanes) as pl:
+        g = P.gpu_step(pl, sc)
+    rep = P.staged(p, sc, g, n_iter=0, ks=np.arange(0, 300, 10))
+    _say(" ", rep)
+    P.assert_staged(rep)
+
+
 def test_single_waypoint_and_unbounded_controls():
     mppi = _mppi()
     sc = scenes.tiny(K=512, T=20, n_c=4)
