@@ -158,7 +158,7 @@ struct LdsLayout {
 
 // Largest LDS copy of a tile's applied perturbations ([2T][spb + 1] floats)
 // and, with per-step weights, stage costs ([T][spb + 1] floats) and
-// cost-to-go ([T][spb] doubles).
+// cost-to-go ([T][spb + 1] doubles, rows padded by one).
 constexpr size_t kEpsStageMax = 48 << 10;
 // The copy is made when the workgroup's LDS stays within kLdsShared (five
 // workgroups per compute unit), or within kLdsAlone for an instance launched
@@ -198,7 +198,7 @@ inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int sp
     L.omega = o;   o += (size_t)spb * 4;
     const size_t eb = (size_t)2 * T * (spb + 1) * 4;
     const size_t qb = per_step ? align_up((size_t)T * (spb + 1) * 4, 8) : 0;
-    const size_t sb = per_step ? (size_t)T * spb * 8 : 0;
+    const size_t sb = per_step ? (size_t)T * (spb + 1) * 8 : 0;
     L.eps_staged = eps_stage && eb + qb + sb <= kEpsStageMax;
     L.eps = o;     o += L.eps_staged ? eb : 0;
     o = align_up(o, 8);

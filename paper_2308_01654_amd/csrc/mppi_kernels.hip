@@ -97,7 +97,7 @@ struct Lds {
     float* omega;
     float* eps;  // [2T][spb + 1]: column 2t + c, sample j at (2t + c)(spb + 1) + j
     float* qs;   // [T][spb + 1] stage costs (per-step weights)
-    double* ss;  // [T][spb] cost-to-go (per-step weights)
+    double* ss;  // [T][spb + 1] cost-to-go (per-step weights), rows padded by one
 };
 
 __device__ __forceinline__ Lds lds_bind(unsigned char* base, const LdsLayout& L)
@@ -906,10 +906,10 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             const int ta = min(p * len, T), tb = min(ta + len, T);
             const bool on = j < n_valid;
             auto st_ld = [&](int t) {
-                return lds ? s.ss[t * SPB + j] : d.Stk[(size_t)t * K + k_base + j];
+                return lds ? s.ss[t * (SPB + 1) + j] : d.Stk[(size_t)t * K + k_base + j];
             };
             auto st_st = [&](int t, double v) {
-                if (lds) s.ss[t * SPB + j] = v;
+                if (lds) s.ss[t * (SPB + 1) + j] = v;
                 else d.Stk[(size_t)t * K + k_base + j] = v;
             };
             if (on) {
@@ -944,7 +944,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
                 double m = INFINITY;
 #pragma unroll 4
                 for (int j = 0; j < n_valid; ++j) {
-                    const double v = s.ss[t * SPB + j];
+                    const double v = s.ss[t * (SPB + 1) + j];
                     if (isfinite(v) && v < m) m = v;
                 }
                 mt[t] = m;
@@ -953,15 +953,16 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             for (int i = tid; i < T * SPB; i += kBlock) {
                 const int t = i / SPB, j = i % SPB;
                 if (j >= n_valid) continue;
-                const double m = mt[t], v = s.ss[i];
-                s.ss[i] = isfinite(m) && isfinite(v) ? exp(-(v - m) / d.lambda) : 0.0;
+                double& sv = s.ss[t * (SPB + 1) + j];
+                const double m = mt[t], v = sv;
+                sv = isfinite(m) && isfinite(v) ? exp(-(v - m) / d.lambda) : 0.0;
             }
             __syncthreads();
             for (int t = tid; t < T; t += kBlock) {
                 double z = 0.0, qq = 0.0, na = 0.0, nd = 0.0;
 #pragma unroll 4
                 for (int j = 0; j < n_valid; ++j) {
-                    const double om = s.ss[t * SPB + j];
+                    const double om = s.ss[t * (SPB + 1) + j];
                     z += om;
                     qq += om * om;
                     na += om * (double)s.eps[(2 * t) * (SPB + 1) + j];
