@@ -649,17 +649,40 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
     return cost + ext;
 }
 
+// A float64 value of another lane by DPP (two 32-bit moves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
+// Butterfly reductions over the 64 lanes of a wave (every lane active; every
+// lane ends with the same value): lane pairs and quad halves by quad
+// permutes; then, each quad holding one value, the half-row mirror pairs
+// each quad with the other quad of its half-row, and the row mirror each
+// half-row with the other half; rows by LDS permutes.
 __device__ __forceinline__ double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_d<0x141>(v);  // row_half_mirror
+    v += dpp_d<0x140>(v);  // row_mirror
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
     return v;
 }
 
 __device__ __forceinline__ double wave_min(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    v = fmin(v, dpp_d<0xB1>(v));
+    v = fmin(v, dpp_d<0x4E>(v));
+    v = fmin(v, dpp_d<0x141>(v));
+    v = fmin(v, dpp_d<0x140>(v));
+    v = fmin(v, __shfl_xor(v, 16, 64));
+    v = fmin(v, __shfl_xor(v, 32, 64));
     return v;
 }
 
@@ -878,8 +901,10 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
 
     // per-sample total over the G lanes (float64)
     double Sd = (double)S - (double)comp;
-#pragma unroll
-    for (int o = 1; o < G; o <<= 1) Sd += __shfl_xor(Sd, o, 64);
+    if (G >= 2) Sd += dpp_d<0xB1>(Sd);
+    if (G >= 4) Sd += dpp_d<0x4E>(Sd);
+    if (G >= 8) Sd += dpp_d<0x141>(Sd);
+    if (G >= 16) Sd += dpp_d<0x140>(Sd);
     float Sk = (float)Sd;
     if (!valid || !isfinite(Sk)) Sk = INFINITY;
     if (valid && r == 0) d.S[k] = (float)Sd;
