@@ -195,7 +195,8 @@ inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int sp
     L.wp_vref = o; o += (size_t)n_wp * 4;
     L.wp_yaw = o;  o += (size_t)n_wp * 4;
     L.c_rr = o;    o += (size_t)n_c * 4;
-    L.omega = o;   o += (size_t)spb * 4;
+    o = align_up(o, 8);
+    L.omega = o;   o += (size_t)spb * 8;   // float64 weights
     const size_t eb = (size_t)2 * T * (spb + 1) * 4;
     const size_t qb = per_step ? align_up((size_t)T * (spb + 1) * 4, 8) : 0;
     const size_t sb = per_step ? (size_t)T * (spb + 1) * 8 : 0;

@@ -19,8 +19,8 @@
 //            time-major [T][K] as float2 (and kept in LDS for phase 2).
 //   phase 2  tile partials.  Tile minimum m_b, then (float64)
 //            omega_i = exp(-(S_i - m_b)/lambda), Z_b = sum omega_i and, for
-//            every (t, control) column, the float64 sum of the exact
-//            products omega_i * eps_eff[t][i] over the tile.
+//            every (t, control) column, the float64 sum of the products
+//            omega_i * eps_eff[t][i] over the tile.
 //   phase 3  (tiles above kDirect only) a fixed-shape tree merges tiles
 //            until kDirect nodes remain.
 //
@@ -94,7 +94,7 @@ struct Lds {
     float* wp_vref;
     float* wp_yaw;
     float* c_rr;
-    float* omega;
+    double* omega; // [spb] the tile's float64 exponential weights
     float* eps;  // [2T][spb + 1]: column 2t + c, sample j at (2t + c)(spb + 1) + j
     float* qs;   // [T][spb + 1] stage costs (per-step weights)
     double* ss;  // [T][spb + 1] cost-to-go (per-step weights), rows padded by one
@@ -111,7 +111,7 @@ __device__ __forceinline__ Lds lds_bind(unsigned char* base, const LdsLayout& L)
     s.wp_vref = reinterpret_cast<float*>(base + L.wp_vref);
     s.wp_yaw = reinterpret_cast<float*>(base + L.wp_yaw);
     s.c_rr = reinterpret_cast<float*>(base + L.c_rr);
-    s.omega = reinterpret_cast<float*>(base + L.omega);
+    s.omega = reinterpret_cast<double*>(base + L.omega);
     s.eps = reinterpret_cast<float*>(base + L.eps);
     s.qs = reinterpret_cast<float*>(base + L.qs);
     s.ss = reinterpret_cast<double*>(base + L.ss);
@@ -798,20 +798,23 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         const float dlm = fminf(fmaxf(Um.y + em.y, d.d_min), d.d_max);
         const float tnm = M5 ? dlm : __tanf(dlm);
         // Speed before the own step.  The noise check caps the acceleration
-        // so that v <= v_max and applies the braking bound last.  While the
-        // speed at the block start is within v_max the braking bound cannot
-        // bind (a >= a_min already), and the capped recursion
-        // v_{i+1} = min(v_i + dt a_i, v_max) has the closed form
+        // so that v <= v_max and applies the braking bound last.  With
+        // a_min <= 0 and the speed at the block start within v_max the
+        // braking bound cannot bind (the cap (v_max - v)/dt is >= 0 >= a_min),
+        // and the capped recursion v_{i+1} = min(v_i + dt a_i, v_max) has the
+        // closed form
         //   v_r = min(v_0 + S_r, v_max + S_r - max_{1<=k<=r} S_k),
         // S_k = sum_{j<k} dt a_j: a prefix sum and a prefix maximum over the G
-        // lanes.  Otherwise (a wave with a sample above v_max) the G lanes run
-        // the recursion step by step (accelerations exchanged PF at a time),
-        // each keeping the speed before its own step.  Steps past the horizon
-        // (last block) are run too; the lanes that own them are inactive.
-        // Lanes before it (first block) add zero increments, which leave the
-        // closed form unchanged (their prefix sums equal v_0 <= v_max's).
+        // lanes.  Otherwise (a_min > 0, where the braking bound lifts the speed
+        // above v_max whenever the cap falls below a_min, or a wave with a
+        // sample above v_max) the G lanes run the recursion step by step
+        // (accelerations exchanged PF at a time), each keeping the speed
+        // before its own step.  Steps past the horizon (last block) are run
+        // too; the lanes that own them are inactive.  Lanes before it (first
+        // block) add zero increments, which leave the closed form unchanged
+        // (their prefix sums equal v_0 <= v_max's).
         float vr = v;
-        if (__ballot(v > d.v_max) == 0ull) {
+        if (!(d.a_min > 0.0f) && __ballot(v > d.v_max) == 0ull) {
             const float sincl = seg_scan<G>(lead ? 0.0f : d.dt * a0m, r);
             const float sr = seg_prev<G>(sincl, r);
             const float qr = seg_scan_max<G>(r >= 1 ? sr : -INFINITY, r);
@@ -1041,7 +1044,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         for (int i = 1; i < kBlock / 64; ++i) m_b = fmin(m_b, s.red[i]);
         double om = 0.0;
         if (r == 0 && isfinite(m_b) && Sk < INFINITY) om = exp(-((double)Sk - m_b) / d.lambda);
-        if (r == 0) s.omega[grp] = (float)om;
+        if (r == 0) s.omega[grp] = om;
         const double wz = wave_sum(om);
         const double wq = wave_sum(om * om);
         if (lane0) {
@@ -1056,7 +1059,8 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             q_b += s.red[8 + i];
         }
         // Weighted perturbation sums, one column (step, control) per thread,
-        // the exact float products summed in float64 in sample order: from
+        // the float64 weights (the ones Z_b sums) times the float32
+        // perturbations, summed in float64 in sample order: from
         // the tile's LDS copy of its perturbations (rows padded by one so
         // that the lanes of a wave read distinct banks) or, when that copy
         // does not fit, from global memory, sixteen loads in flight.
@@ -1066,21 +1070,22 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
                 const float* e = s.eps + col * (SPB + 1);
                 double acc = 0.0;
                 // whole tiles: every LDS read issued before the chain of FMAs
-                constexpr int NU = SPB < 32 ? SPB : 32;
+                constexpr int NU = SPB < 16 ? SPB : 16;
                 if (n_valid == SPB) {
                     for (int j0 = 0; j0 < SPB; j0 += NU) {
-                        float om[NU], ev[NU];
+                        double om[NU];
+                        float ev[NU];
 #pragma unroll
                         for (int u = 0; u < NU; ++u) {
                             om[u] = s.omega[j0 + u];
                             ev[u] = e[j0 + u];
                         }
 #pragma unroll
-                        for (int u = 0; u < NU; ++u) acc = fma((double)om[u], (double)ev[u], acc);
+                        for (int u = 0; u < NU; ++u) acc = fma(om[u], (double)ev[u], acc);
                     }
                 } else {
                     for (int j = 0; j < n_valid; ++j)
-                        acc = fma((double)s.omega[j], (double)e[j], acc);
+                        acc = fma(s.omega[j], (double)e[j], acc);
                 }
                 part[kPartialHead + col] = acc;
                 continue;
@@ -1095,7 +1100,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
                 for (int u = 0; u < NB; ++u) ev[u] = (i0 + u < n_valid) ? e[2 * (i0 + u)] : 0.0f;
 #pragma unroll
                 for (int u = 0; u < NB; ++u)
-                    if (i0 + u < n_valid) acc = fma((double)s.omega[i0 + u], (double)ev[u], acc);
+                    if (i0 + u < n_valid) acc = fma(s.omega[i0 + u], (double)ev[u], acc);
             }
             part[kPartialHead + col] = acc;
         }
@@ -1564,12 +1569,14 @@ __device__ __forceinline__ double block_excl(double v, double* red)
 // x*_{t+1} = F(x*_t, u*_t) (eq. (5), explicit Euler from the old state), each
 // nominal control put through the noise check with zero noise (bounds, speed
 // cap, braking bound last).  One workgroup, each thread a run of consecutive
-// steps.  While the start is within v_max the braking bound cannot bind and
-// the capped speeds have the closed form of the iteration kernel's walk
-// (v_t = min(v_0 + S_t, v_max + S_t - max_{1<=k<=t} S_k), S_t the sum of the
-// first t commanded changes); heading, steering angle (5-state model) and
-// position are prefix sums of their increments.  A start above v_max is
-// walked step by step by one thread.
+// steps.  While the start is within v_max and a_min <= 0 the braking bound
+// cannot bind and the capped speeds have the closed form of the iteration
+// kernel's walk (v_t = min(v_0 + S_t, v_max + S_t - max_{1<=k<=t} S_k), S_t
+// the sum of the first t commanded changes); heading, steering angle
+// (5-state model) and position are prefix sums of their increments.  A start
+// above v_max, or a positive a_min (the braking bound then lifts the speed
+// above v_max whenever the cap falls below it), is walked step by step by one
+// thread.
 __global__ __launch_bounds__(kBlock) void k_trajectory(TrajArgs a, const double* __restrict__ U,
                                                        double* __restrict__ xs,
                                                        double* __restrict__ us)
@@ -1585,7 +1592,7 @@ __global__ __launch_bounds__(kBlock) void k_trajectory(TrajArgs a, const double*
         o[3] = v;
         if (a.model) o[4] = delta;
     };
-    if (!(a.x0[3] <= a.v_max)) {
+    if (!(a.x0[3] <= a.v_max) || a.a_min > 0.0) {
         if (threadIdx.x != 0) return;
         double x = a.x0[0], y = a.x0[1], th = a.x0[2], v = a.x0[3], delta = a.steer0;
         put(0, x, y, th, v, delta);

@@ -20,8 +20,19 @@ from oracle import oracle as O
 
 W_TOL = 1e-5
 U_REL = 1e-4
-S_REL = 1e-3     # bound on the relative cost error of the float32 rollout (D2)
+# Bound on the relative cost error of the float32 rollout (D2), fed the same
+# applied perturbations.  A stage cost is a sum of a few float32 terms of
+# squared distances whose positions carry the rounding of a float32 walk of
+# up to a few hundred steps (about 2^-24 per step, relative to the distance
+# travelled); the measured maximum on every workload of up to 300 steps is
+# 5.4e-5, and 2e-4 leaves a factor of about four.  Longer horizons state
+# their own bound.
+S_REL = 2e-4
 EPS_ABS = 2e-3   # bound on |delta eps_eff| / sigma of the float32 sampler (D1)
+# Samples whose oracle cost lies more than NEAR_LAMBDAS * lambda above the
+# minimum carry a weight below e^-40 relative to the best: the cost error on
+# the others (beta_near) is the one that moves the weights.
+NEAR_LAMBDAS = 40.0
 
 
 def u_tol(U_ref, sigma):
@@ -72,9 +83,9 @@ def staged(p, scene, g, n_iter, ks=None):
     return rep
 
 
-def assert_staged(rep):
+def assert_staged(rep, s_rel=S_REL):
     assert rep["D1_max_abs_over_sigma"] <= EPS_ABS, rep
-    assert rep["D2_max_rel"] <= S_REL, rep
+    assert rep["D2_max_rel"] <= s_rel, rep
     assert rep["G2_max_abs"] <= W_TOL, rep
     assert rep["G3_max_over_tol"] <= 1.0, rep
     assert abs(rep["s_min"][0] - rep["s_min"][1]) <= 1e-12 * max(1.0, abs(rep["s_min"][1])), rep
@@ -89,15 +100,38 @@ def end_to_end(p, scene, g, n_iter):
     r = O.iteration(p, scene["x0"], scene["waypoints"], scene["circles"], g["U_prev"],
                     n_iter=n_iter)
     sig = np.asarray(p["sigma"], dtype=np.float64)
-    beta = float(np.max(np.abs(g["S"] - r["S"])))
+    dS = np.abs(g["S"] - r["S"])
+    beta = float(np.max(dS))
     srt = np.sort(r["S"])
     gap = float(srt[1] - srt[0]) if srt.size > 1 else float("inf")
+    near = r["S"] - srt[0] <= NEAR_LAMBDAS * p["lam"]
+    beta_near = float(np.max(dS[near]))
     dw = float(np.max(np.abs(g["w"] - r["w"])))
     du = float(np.max(np.abs(g["U"] - r["U"]) / u_tol(r["U"], sig)))
-    # first-order prediction of the weight error from the cost error
-    pred = float(np.max(2.0 * np.maximum(g["w"], r["w"]) * beta / p["lam"]))
-    rep = dict(beta=beta, lam=p["lam"], top2_gap=gap, w_max_abs=dw, U_max_over_tol=du,
-               predicted_w_bound=pred, ess_gpu=g["stats"]["ess"],
+    # first-order prediction of the weight error from the cost error of the
+    # samples that carry weight
+    pred = float(np.max(2.0 * np.maximum(g["w"], r["w"]) * beta_near / p["lam"]))
+    rep = dict(beta=beta, beta_near=beta_near, n_near=int(np.sum(near)), lam=p["lam"],
+               top2_gap=gap, w_max_abs=dw, U_max_over_tol=du,
+               predicted_w_bound=pred, ess_gpu=g["stats"]["ess"], ess_oracle=r["ess"]
+               if "ess" in r else float(1.0 / np.sum(r["w"] ** 2)),
                argmin_same=bool(np.argmin(g["S"]) == np.argmin(r["S"])))
     ok = dw <= W_TOL and du <= 1.0
-    return rep, ok
+    return rep, ok, r
+
+
+def assert_end_to_end(rep, ok):
+    """End-to-end gate outside the metric's workloads.  The controls must
+    meet their tolerance.  The weights must meet theirs, or, where the
+    samples that carry weight are close in cost (spread weights), stay within
+    the first-order effect of the float32 cost error on those samples,
+    |dw_k| <= 2 w_k beta_near / lambda -- the one cause of a weight error
+    that a float32 rollout admits; the report names it."""
+    assert rep["U_max_over_tol"] <= 1.0, rep
+    if not ok:
+        assert rep["w_max_abs"] <= rep["predicted_w_bound"], rep
+        print("  end-to-end weights beyond 1e-5, attributed to the float32 cost error "
+              "(beta_near/lambda = %.3g, top-2 gap %.3g): %.3g <= %.3g"
+              % (rep["beta_near"] / rep["lam"], rep["top2_gap"], rep["w_max_abs"],
+                 rep["predicted_w_bound"]), flush=True)
+

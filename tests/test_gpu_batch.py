@@ -130,3 +130,51 @@ def test_batch_rejects_mixed_streams_and_duplicates():
             mppi.step_batch([p1, p1], np.array([a["x0"], a["x0"]]),
                             [(a["waypoints"], a["circles"])] * 2)
         assert p1.stats()["n_iter"] == 0
+
+
+def test_c2_full_draw_staged_parity():
+    """The 256 uneven instances of the batched workload (K in {1024..16384},
+    T in [30, 150], 0-64 circles, each its own seeded scene) stepped as one
+    batch: per instance the applied perturbations and costs of 32 sampled
+    samples (the cheapest and dearest four among them) against the oracle
+    fed the GPU's perturbations, the weights on every sample against the
+    oracle normaliser fed the GPU's costs and the controls against the
+    oracle update fed the GPU's weights and perturbations; four instances
+    (the largest K, the longest T, the most circles and one without circles)
+    end to end against fully independent oracle iterations."""
+    mppi = _mppi()
+    insts = scenes.c2()
+    _say("c2 full draw: %d instances" % len(insts))
+    lead = mppi.Planner(insts[0]["params"])
+    pls = [lead] + [mppi.Planner(sc["params"], hip_stream=lead.stream()) for sc in insts[1:]]
+    try:
+        prev = [pl.controls() for pl in pls]
+        mppi.step_batch(pls, np.array([sc["x0"] for sc in insts]),
+                        [(sc["waypoints"], sc["circles"]) for sc in insts])
+        shapes = [(sc["params"]["K"], sc["params"]["T"], len(sc["circles"])) for sc in insts]
+        e2e_ids = {int(np.argmax([s[0] * 1000 + s[1] for s in shapes])),
+                   int(np.argmax([s[1] * 100000 + s[0] for s in shapes])),
+                   int(np.argmax([s[2] for s in shapes])),
+                   int(np.argmin([s[2] for s in shapes]))}
+        worst = dict(D1=0.0, D2=0.0, G2=0.0, G3=0.0)
+        rng = np.random.Generator(np.random.PCG64(77))
+        for i, (pl, sc, U_prev) in enumerate(zip(pls, insts, prev)):
+            p = sc["params"]
+            g = dict(U_prev=U_prev, U=pl.controls(), S=pl.costs().astype(np.float64),
+                     w=pl.weights(), eps=pl.noise().astype(np.float64), stats=pl.stats())
+            order = np.argsort(g["S"])
+            ks = np.unique(np.concatenate([rng.integers(0, p["K"], size=24), order[:4], order[-4:]]))
+            rep = P.staged(p, sc, g, n_iter=0, ks=ks)
+            worst["D1"] = max(worst["D1"], rep["D1_max_abs_over_sigma"])
+            worst["D2"] = max(worst["D2"], rep["D2_max_rel"])
+            worst["G2"] = max(worst["G2"], rep["G2_max_abs"])
+            worst["G3"] = max(worst["G3"], rep["G3_max_over_tol"])
+            P.assert_staged(rep)
+            if i in e2e_ids:
+                e2e, ok, _ = P.end_to_end(p, sc, g, 0)
+                _say("  e2e instance", i, shapes[i], e2e)
+                assert ok, (i, e2e)
+        _say("c2 worst gates", worst)
+    finally:
+        for pl in reversed(pls):
+            pl.close()

@@ -65,10 +65,9 @@ def test_smoothing_end_to_end_and_ragged_horizons():
             g = P.gpu_step(pl, sc)
             rep = P.staged(p, sc, g, n_iter=0)
             P.assert_staged(rep)
-            rep, ok = P.end_to_end(p, sc, g, 0)
-            if not ok:
-                assert rep["w_max_abs"] <= max(P.W_TOL, 1.5 * rep["predicted_w_bound"]) or \
-                    rep["top2_gap"] <= 2 * rep["beta"], rep
+            rep, ok, _ = P.end_to_end(p, sc, g, 0)
+            _say("  e2e", rep)
+            P.assert_end_to_end(rep, ok)
 
 
 @pytest.mark.parametrize("smoothing", [0, 1])
@@ -118,6 +117,27 @@ def test_trajectory_long_horizon_and_start_above_cap(T, v0, model):
     assert np.max(np.abs(us - ref_u)) <= 1e-12
     assert np.max(np.abs(xs - ref_x)) <= TRAJ_ABS
     assert np.array_equal(xs[0, :4], x0)
+
+
+@pytest.mark.parametrize("T", [50, 700])
+def test_trajectory_positive_braking_bound(T):
+    """u_min = (0.3, -0.5) with the start just under v_max: the braking bound
+    applied last lifts the speed above v_max (the step-by-step branch); equal
+    to the oracle's optimal rollout."""
+    mppi = _mppi()
+    sc = scenes.tiny(K=256, T=T, n_c=4, seed=T + 1)
+    p = dict(sc["params"], v_max=12.0, u_min=(0.3, -0.5))
+    x0 = np.array(sc["x0"], dtype=np.float64)
+    x0[3] = 11.97
+    with mppi.Planner(p) as pl:
+        pl.set_controls(np.tile([0.8, 0.02], (T, 1)))
+        pl.step(x0, sc["waypoints"], sc["circles"])
+        xs, us = pl.trajectory()
+        ref_x, ref_u = O.optimal_trajectory(p, x0, pl.controls())
+    _say("trajectory a_min > 0", T, float(np.max(np.abs(xs - ref_x))), float(np.max(xs[:, 3])))
+    assert np.max(xs[:, 3]) > p["v_max"]
+    assert np.max(np.abs(us - ref_u)) <= 1e-12
+    assert np.max(np.abs(xs - ref_x)) <= TRAJ_ABS
 
 
 def test_trajectory_before_any_step_is_rejected():

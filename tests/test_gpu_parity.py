@@ -89,19 +89,18 @@ def test_c0_staged_parity_all_launch_shapes(lanes):
 
 
 def test_c0_end_to_end():
+    """Plain single iteration against a fully independent oracle iteration
+    (its own noise and rollouts): weights within 1e-5, controls within the
+    1e-4 relative tolerance."""
     mppi = _mppi()
     sc = scenes.c0()
     p = sc["params"]
     with mppi.Planner(p) as pl:
         g = P.gpu_step(pl, sc)
-    rep, ok = P.end_to_end(p, sc, g, 0)
+    rep, ok, _ = P.end_to_end(p, sc, g, 0)
     _dump("c0_e2e", rep)
     _say("c0 e2e", rep)
-    if not ok:
-        # the only admissible cause: a cost error that the weights amplify
-        # (beta/lambda) or a near-tie of the two best samples
-        assert rep["w_max_abs"] <= max(P.W_TOL, 1.5 * rep["predicted_w_bound"]) or \
-            rep["top2_gap"] <= 2 * rep["beta"], rep
+    assert ok, rep
 
 
 @pytest.mark.parametrize("K,T,n_c,lanes", [
@@ -140,7 +139,10 @@ def test_maximum_sizes(lanes):
         g = P.gpu_step(pl, sc)
     rep = P.staged(p, sc, g, n_iter=0, ks=np.arange(0, 300, 10))
     _say(" ", rep)
-    P.assert_staged(rep)
+    # one lane walks all 2048 steps sequentially in float32: the position
+    # rounding grows with the horizon (about seven times the 300-step bound;
+    # measured 2.8e-4), while 16 lanes sum 128 blocks of prefix sums
+    P.assert_staged(rep, s_rel=1.5e-3 if lanes == 1 else P.S_REL)
 
 
 def test_single_waypoint_and_unbounded_controls():
@@ -293,9 +295,13 @@ def test_shift_warm_start():
 
 
 def test_c1_ten_warm_iterations_staged():
-    """Sine-lane instance, K=8192, T=100: 10 warm-started iterations, every
-    gate checked per iteration with the oracle re-synced to the GPU's
-    previous controls; the free-running end-to-end result is reported."""
+    """Sine-lane instance, K=8192, T=100: 10 warm-started iterations.  Per
+    iteration, every staged gate with the oracle re-synced to the GPU's
+    previous controls, and the end-to-end tolerances (weights within 1e-5,
+    controls within 1e-4 relative) against a fully independent oracle
+    iteration from the same previous controls.  After the 10 iterations the
+    GPU's controls are within the control tolerance of 10 free-running
+    oracle iterations (which never see a GPU value)."""
     mppi = _mppi()
     sc = scenes.c1()
     p = sc["params"]
@@ -303,18 +309,21 @@ def test_c1_ten_warm_iterations_staged():
     U_free = np.zeros((p["T"], 2))
     with mppi.Planner(p) as pl:
         for i in range(sc["iterations"]):
-            _say("c1 iteration", i)
             g = P.gpu_step(pl, sc)
             rep = P.staged(p, sc, g, n_iter=i)
-            e2e, ok = P.end_to_end(p, sc, g, i)
+            e2e, ok, _ = P.end_to_end(p, sc, g, i)
             rep["e2e"] = e2e
             rep["e2e_ok"] = ok
             reps.append(rep)
+            _say("c1 iteration", i, "D2 %.2e" % rep["D2_max_rel"], "e2e", e2e)
             P.assert_staged(rep)
+            assert ok, (i, e2e)
             U_free = O.iteration(p, sc["x0"], sc["waypoints"], sc["circles"], U_free, n_iter=i)["U"]
         U_gpu = pl.controls()
     free = float(np.max(np.abs(U_gpu - U_free) / P.u_tol(U_free, p["sigma"])))
+    _say("c1 free-running controls, error / tolerance", free)
     _dump("c1", dict(iterations=reps, free_running_U_max_over_tol=free))
+    assert free <= 1.0, free
 
 
 def test_c4_stress_sampled():
@@ -332,6 +341,45 @@ def test_c4_stress_sampled():
     rep = P.staged(p, sc, g, n_iter=0, ks=ks)
     _dump("c4", rep)
     P.assert_staged(rep)
+
+
+def test_c4_stress_end_to_end():
+    """Stress instance at full size (K=262144, T=200, 512 circles) against a
+    fully independent oracle iteration (52.4 M float64 rollout steps on the
+    host cores): weights within 1e-5 on every sample and controls within the
+    1e-4 relative tolerance; the report carries the cost error of the
+    samples that carry weight (beta_near), the top-2 gap and the ESS."""
+    mppi = _mppi()
+    sc = scenes.c4()
+    p = sc["params"]
+    _say("c4 stress end to end: GPU iteration")
+    with mppi.Planner(p) as pl:
+        g = P.gpu_step(pl, sc)
+    _say("c4 stress end to end: oracle iteration on %d threads" % O.max_threads())
+    rep, ok, _ = P.end_to_end(p, sc, g, 0)
+    _say("c4 e2e", rep)
+    _dump("c4_e2e", rep)
+    assert ok, rep
+
+
+@pytest.mark.parametrize("lanes", [1, 4, 16])
+def test_positive_braking_bound(lanes):
+    """A positive lower acceleration bound (u_min = (0.3, -0.5)) with the
+    start just under v_max: the noise check applies a >= a_min last, so the
+    speed rises above v_max whenever the cap falls below a_min (the walk then
+    runs step by step); staged gates over two iterations."""
+    mppi = _mppi()
+    base = scenes.c0()
+    p = dict(base["params"], u_min=(0.3, -0.5))
+    x0 = np.array(base["x0"], dtype=np.float64)
+    x0[3] = p["v_max"] - 0.02
+    sc = dict(base, params=p, x0=x0)
+    _say("positive a_min", lanes)
+    with mppi.Planner(p, lanes=lanes) as pl:
+        pl.set_controls(np.tile([0.5, 0.0], (p["T"], 1)))
+        for it in range(2):
+            g = P.gpu_step(pl, sc)
+            P.assert_staged(P.staged(p, sc, g, n_iter=it))
 
 
 @pytest.mark.parametrize("name,lanes", [("c0", 16), ("c0", 1), ("c1", 8), ("c1", 2), ("paper_table1", 4),

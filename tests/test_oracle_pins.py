@@ -607,6 +607,25 @@ def test_optimal_trajectory_respects_bounds_and_speed_cap():
     assert np.all(ap == np.array(p["u_min"]))
 
 
+def test_positive_braking_bound_lifts_speed_above_cap():
+    """With a positive lower acceleration bound the noise check's last step
+    (a >= a_min) wins over the speed cap: from v0 = v_max - 0.02 at dt = 0.1
+    the first step's cap (0.2) falls below a_min = 0.3, so every applied
+    acceleration is a_min and v_t = v0 + 0.03 t exactly (in closed form),
+    crossing v_max at the first step."""
+    p = _p(T=40, dt=0.1, v_max=10.0, u_min=(0.3, -0.5))
+    Us = np.tile([0.5, 0.0], (40, 1))
+    v0 = 9.98
+    st_, ap = O.optimal_trajectory(p, np.array([0.0, 0.0, 0.0, v0]), Us)
+    assert np.all(ap[:, 0] == 0.3)
+    t = np.arange(41)
+    assert np.max(np.abs(st_[:, 3] - (v0 + 0.03 * t))) < 1e-12
+    assert st_[1, 3] > p["v_max"]
+    # the same rule in a sampled step: commanded 0.5 + 0.1 at v = 9.99 -> a_min
+    a, _ = O.apply_limits(p, [0.5, 0.0], [0.1, 0.0], 9.99)
+    assert a == 0.3
+
+
 # ---- the paper's full Sec. IV-C cost: c_target, c_yaw, collision-only mode
 
 def test_target_cost_counts_steps_away_from_the_last_waypoint():
