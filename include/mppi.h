@@ -333,6 +333,44 @@ mppi_status mppi_server_set_vehicle_state(mppi_server_t* srv, int32_t vid, const
 mppi_status mppi_server_replay(mppi_server_t* srv, const mppi_replay_plan* plan,
                                double* latency_ms);
 
+/* ---- allocation-free iteration ------------------------------------------- */
+
+/* Largest scratch of one mppi_step_static call, in bytes (the library's
+ * file-scope device array; every GPU it runs on holds one until the process
+ * ends). */
+#define MPPI_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
+
+/* For callers that cannot allocate device memory while they plan (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * one iteration with the work and the bits of mppi_step (scene staging, the
+ * iteration kernel and the combine kernel at the launch shape mppi_step
+ * picks), with no handle and no allocation.  Costs, applied perturbations,
+ * tile partials, the staged scene and the device state live in one
+ * file-scope device array of MPPI_STATIC_SCRATCH_BYTES per GPU, looked up
+ * once per device; the call calls no hipMalloc, hipFree or other allocating
+ * routine.
+ *   cfg        configuration, validated as by mppi_create; the 4-state model
+ *              only (model = 0)
+ *   x0, scene  host arrays as for mppi_step (copied before the call returns)
+ *   U          DEVICE pointer to the caller's [T][2] float64 controls, read
+ *              and updated in place on hip_stream (U_t += sum_k w_k eps_eff)
+ *   n_iter     iteration counter of the Philox stream; the caller keeps it
+ *              and passes n, n + 1, ... (mppi_step keeps it in the handle)
+ *   stats      optional DEVICE pointer, receives the iteration's statistics
+ *              on hip_stream (status MPPI_E_NONFINITE, U unchanged, when no
+ *              sample cost is finite)
+ *   hip_stream hipStream_t to enqueue on (NULL: the null stream)
+ * Asynchronous.  MPPI_E_INVALID (nothing enqueued) for a bad configuration,
+ * scene or pointer, or when K x T x 8 bytes of perturbations plus the rest
+ * exceed MPPI_STATIC_SCRATCH_BYTES (e.g. K = 8192, T = 100 needs 7.4 MB).
+ * All calls on one GPU share its array, which keeps the last call's
+ * contents: calls that overlap on one GPU (other streams, other threads)
+ * race and must be serialized by the caller; calls in order on one stream
+ * are safe. */
+mppi_status mppi_step_static(const mppi_config* cfg, const double x0[4], const mppi_scene* scene,
+                             double* U, uint64_t n_iter, mppi_iter_stats* stats,
+                             void* hip_stream);
+
 /* ---- Philox words as the rollout consumes them ---------------------------- */
 
 /* Philox4x32-10 (Salmon et al., SC'11) of counters (k, j, n_lo, n_hi) for

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmppi.so")
-SOURCES = ["mppi_kernels.hip", "mppi_api.hip", "mppi_server.hip"]
+SOURCES = ["mppi_kernels.hip", "mppi_api.hip", "mppi_server.hip", "mppi_static.hip"]
 ARCH = os.environ.get("MPPI_OFFLOAD_ARCH", "gfx950")
 
 

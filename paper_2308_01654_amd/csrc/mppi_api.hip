@@ -423,7 +423,7 @@ mppi_status handle_create(const mppi_config* cfg, void* hip_stream, bool with_sc
 // Descriptor of one iteration of handle h from state x0 on the scene at
 // `scene` (device), staged relative to `origin`.
 // Whether the tiles of d keep their perturbations in LDS (see kLdsShared).
-static void choose_eps_stage(InstDesc& d, bool alone)
+void choose_eps_stage(InstDesc& d, bool alone)
 {
     const LdsLayout L = lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes, 1, d.per_step);
     d.eps_stage = L.eps_staged && (L.total <= kLdsShared ||

@@ -141,6 +141,10 @@ mppi_status record_launch(mppi_t* h, int kind, hipEvent_t* a);
 mppi_status record_end(mppi_t* h, int kind, hipEvent_t a);
 void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double origin[2],
                const unsigned char* scene, const SceneLayout& L, int n_wp, int n_c, int shift);
+// Whether the tiles of d keep their perturbations in LDS: within kLdsShared,
+// or within kLdsAlone for an instance launched alone (alone = true) with at
+// most 512 tiles.
+void choose_eps_stage(InstDesc& d, bool alone);
 mppi_status ws_create(BatchWs** out);
 void ws_destroy(BatchWs* b);
 // Create a handle; with_scratch = false leaves S/eps/partials/scales/scene

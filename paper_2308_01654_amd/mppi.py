@@ -138,6 +138,8 @@ SIGNATURES = [
     ("mppi_get_stream", _i32, [_vp, ctypes.POINTER(_vp)]),
     ("mppi_set_profiling", _i32, [_vp, _i32]),
     ("mppi_get_profile", _i32, [_vp, ctypes.POINTER(Profile)]),
+    ("mppi_step_static", _i32, [ctypes.POINTER(Config), _dp, ctypes.POINTER(Scene), _vp,
+                                ctypes.c_uint64, _vp, _vp]),
     ("mppi_debug_philox", _i32, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                                  ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _u32p, _sz]),
     ("mppi_bench_copy", _i32, [_sz, _i32]),
@@ -269,6 +271,15 @@ def mppi_set_controls(h, U: np.ndarray):
 
 def mppi_shift(h, steps: int):
     return load().mppi_shift(h, int(steps))
+
+
+def mppi_step_static(cfg: Config, x0, scene: Scene, U_dev, n_iter, stats_dev=None,
+                     hip_stream=None):
+    """Allocation-free iteration; U_dev and stats_dev are device addresses
+    (int) owned by the caller."""
+    x = np.ascontiguousarray(np.asarray(x0, dtype=np.float64))
+    return load().mppi_step_static(ctypes.byref(cfg), x.ctypes.data_as(_dp), ctypes.byref(scene),
+                                   U_dev, int(n_iter), stats_dev, hip_stream)
 
 
 def mppi_debug_philox(seed, n_iter, k0, nk, j0, nj):
