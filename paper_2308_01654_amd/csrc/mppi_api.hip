@@ -425,7 +425,7 @@ mppi_status handle_create(const mppi_config* cfg, void* hip_stream, bool with_sc
 // Whether the tiles of d keep their perturbations in LDS (see kLdsShared).
 void choose_eps_stage(InstDesc& d, bool alone)
 {
-    const LdsLayout L = lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes, 1, d.per_step);
+    const LdsLayout L = lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes, 1, d.per_step, !d.cull);
     d.eps_stage = L.eps_staged && (L.total <= kLdsShared ||
                                    (alone && d.n_tiles <= 512 && L.total <= kLdsAlone));
 }
@@ -644,7 +644,7 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
         total += descs[j].n_tiles;
         smem = std::max(smem, lds_layout(descs[j].n_wp, descs[j].n_c, descs[j].T,
                                          kBlock / descs[j].lanes, descs[j].eps_stage,
-                                         descs[j].per_step).total);
+                                         descs[j].per_step, !descs[j].cull).total);
         any_shift |= sh;
         combine_g = std::max(combine_g, combine_groups(descs[j].T));
     }
@@ -815,7 +815,7 @@ mppi_status mppi_step_resident(mppi_t* h, const double x0[4])
     fill_desc(d, h, x0, h->origin, h->scene, h->lay, h->n_wp, h->n_c, 0);
     choose_eps_stage(d, true);
     const size_t smem =
-        lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes, d.eps_stage, d.per_step).total;
+        lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes, d.eps_stage, d.per_step, !d.cull).total;
     hipEvent_t a = nullptr;
     if ((s = record_launch(h, 0, &a)) != MPPI_OK) return s;
     hipEvent_t a2 = nullptr;

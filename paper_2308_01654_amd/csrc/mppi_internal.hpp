@@ -150,7 +150,7 @@ struct BatchHdr {
 
 // Dynamic LDS layout of the iteration kernel for a given scene size.
 struct LdsLayout {
-    size_t c_pv, wp_box, wp_xy, U, red, wp_vref, wp_yaw, c_rr, omega, eps, qs, ss, total;
+    size_t c_pv, wp_box, wp_xy, red, wp_vref, wp_yaw, c_rr, omega, eps, qs, ss, total;
     int eps_staged;  // the tile's applied perturbations are kept at eps, and
                      // with per-step weights its stage costs at qs and its
                      // cost-to-go at ss
@@ -182,19 +182,22 @@ constexpr int kSeedAhead = 4;
 
 inline __host__ __device__ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// scene_lds: the tile keeps a copy of the scene in LDS (the full scans of an
+// instance without culling read it there; the culled scans read the scene
+// from global memory, through the scalar cache for wave-uniform candidates).
 inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int spb, int eps_stage,
-                                                int per_step)
+                                                int per_step, int scene_lds)
 {
     LdsLayout L;
     size_t o = 0;
-    L.c_pv = o;    o += (size_t)n_c * 16;
-    L.wp_box = o;  o += (size_t)((n_wp + kChunk - 1) / kChunk) * 16;
-    L.wp_xy = o;   o += (size_t)((n_wp + kChunk - 1) / kChunk) * kChunk * 8;  // padded
-    L.U = o;       o += (size_t)T * 8;
+    const size_t sc = scene_lds ? 1 : 0;
+    L.c_pv = o;    o += sc * (size_t)n_c * 16;
+    L.wp_box = o;  o += sc * (size_t)((n_wp + kChunk - 1) / kChunk) * 16;
+    L.wp_xy = o;   o += sc * (size_t)((n_wp + kChunk - 1) / kChunk) * kChunk * 8;  // padded
     L.red = o;     o += 64 * 8;           // block reduction scratch (doubles)
-    L.wp_vref = o; o += (size_t)n_wp * 4;
-    L.wp_yaw = o;  o += (size_t)n_wp * 4;
-    L.c_rr = o;    o += (size_t)n_c * 4;
+    L.wp_vref = o; o += sc * (size_t)n_wp * 4;
+    L.wp_yaw = o;  o += sc * (size_t)n_wp * 4;
+    L.c_rr = o;    o += sc * (size_t)n_c * 4;
     o = align_up(o, 8);
     L.omega = o;   o += (size_t)spb * 8;   // float64 weights
     const size_t eb = (size_t)2 * T * (spb + 1) * 4;

@@ -89,7 +89,6 @@ struct Lds {
     float4* c_pv;
     float4* wp_box;
     float2* wp_xy;
-    float2* U;
     double* red;
     float* wp_vref;
     float* wp_yaw;
@@ -106,7 +105,6 @@ __device__ __forceinline__ Lds lds_bind(unsigned char* base, const LdsLayout& L)
     s.c_pv = reinterpret_cast<float4*>(base + L.c_pv);
     s.wp_box = reinterpret_cast<float4*>(base + L.wp_box);
     s.wp_xy = reinterpret_cast<float2*>(base + L.wp_xy);
-    s.U = reinterpret_cast<float2*>(base + L.U);
     s.red = reinterpret_cast<double*>(base + L.red);
     s.wp_vref = reinterpret_cast<float*>(base + L.wp_vref);
     s.wp_yaw = reinterpret_cast<float*>(base + L.wp_yaw);
@@ -168,18 +166,21 @@ __device__ __forceinline__ float circle_gap(const float (&ex)[NE > 0 ? NE : 1],
 // |P - T|^2 - |P_prev - T|^2 = (P - P_prev).(P + P_prev - 2 T) -- and c_yaw,
 // the heading th minus the yaw of closest waypoint bj, wrapped into
 // [-pi, pi), squared.
-__device__ __forceinline__ float extra_terms(const InstDesc& d, const Lds& s, int bj, float x,
-                                             float y, float th, float xp, float yp)
+// The waypoint arrays are read from wxy / wyaw (the tile's LDS copy or the
+// scene in global memory: the same values either way).
+__device__ __forceinline__ float extra_terms(const InstDesc& d, const float2* wxy,
+                                             const float* wyaw, int bj, float x, float y,
+                                             float th, float xp, float yp)
 {
     float e = 0.0f;
     if (d.w_target != 0.0f) {
-        const float2 tp = s.wp_xy[d.n_wp - 1];
+        const float2 tp = wxy[d.n_wp - 1];
         const float dx = x - xp, dy = y - yp;
         const float sx = (x - tp.x) + (xp - tp.x), sy = (y - tp.y) + (yp - tp.y);
         e = fmaf(d.w_target, fmaf(dx, sx, dy * sy) > 0.0f ? 1.0f : 0.0f, e);
     }
     if (d.w_yaw != 0.0f) {
-        float dyaw = th - s.wp_yaw[bj];
+        float dyaw = th - wyaw[bj];
         dyaw -= 6.28318530717958647692f *
                 floorf((dyaw + 3.14159265358979323846f) * 0.15915494309189533577f);
         e = fmaf(d.w_yaw, dyaw * dyaw, e);
@@ -208,7 +209,7 @@ __device__ __forceinline__ float stage_cost(const InstDesc& d, const Lds& s, flo
     float best = INFINITY;
     int bj = 0;
     for (int ch = 0; ch * kChunk < d.n_wp; ++ch) scan_chunk(s, ch, x, y, best, bj);
-    const float ext = extra_terms(d, s, bj, x, y, th, xp, yp);
+    const float ext = extra_terms(d, s.wp_xy, s.wp_yaw, bj, x, y, th, xp, yp);
     const float dv = v - s.wp_vref[bj];
     // q_u = w_effort (alpha eps.eps + U.eps + U.U / 2)
     const float q = d.w_effort * (d.alpha * fmaf(ea, ea, ed * ed) + fmaf(Ua, ea, Ud * ed) +
@@ -265,7 +266,10 @@ constexpr int kIntMin = (int)0x80000000u;
 // Prefix sums inside aligned groups of G lanes (G <= 16, so a group lies in
 // one DPP row): the inclusive sum (or maximum) up to lane r of the group,
 // the value of lane r - 1 (0 for the first lane), and the group's last
-// lane's value.
+// lane's value.  With G = 16 a group is a whole row, and a row shift by N
+// already gives lanes r < N nothing from another group (bound_ctrl reads 0;
+// without it the lane keeps the identity passed as the old value), so no
+// lane mask is needed.
 template <int N>
 __device__ __forceinline__ float dpp_shr(float v)
 {
@@ -275,19 +279,34 @@ __device__ __forceinline__ float dpp_shr(float v)
 template <int G>
 __device__ __forceinline__ float seg_scan(float v, int r)
 {
+    if (G == 16) {
+        v += dpp_shr<1>(v);
+        v += dpp_shr<2>(v);
+        v += dpp_shr<4>(v);
+        v += dpp_shr<8>(v);
+        return v;
+    }
     if (G >= 2) { const float u = dpp_shr<1>(v); v += r >= 1 ? u : 0.0f; }
     if (G >= 4) { const float u = dpp_shr<2>(v); v += r >= 2 ? u : 0.0f; }
     if (G >= 8) { const float u = dpp_shr<4>(v); v += r >= 4 ? u : 0.0f; }
-    if (G >= 16) { const float u = dpp_shr<8>(v); v += r >= 8 ? u : 0.0f; }
     return v;
 }
 template <int G>
 __device__ __forceinline__ float seg_scan_max(float v, int r)
 {
+    if (G == 16) {
+        // on order-preserving integer keys (non-NaN floats): one DPP max per
+        // stage; lanes r < N keep the identity
+        int k = fkey(v);
+        k = max(k, dpp_i<0x111>(kIntMin, k));
+        k = max(k, dpp_i<0x112>(kIntMin, k));
+        k = max(k, dpp_i<0x114>(kIntMin, k));
+        k = max(k, dpp_i<0x118>(kIntMin, k));
+        return fkey_inv(k);
+    }
     if (G >= 2) { const float u = dpp_shr<1>(v); v = r >= 1 ? fmaxf(v, u) : v; }
     if (G >= 4) { const float u = dpp_shr<2>(v); v = r >= 2 ? fmaxf(v, u) : v; }
     if (G >= 8) { const float u = dpp_shr<4>(v); v = r >= 4 ? fmaxf(v, u) : v; }
-    if (G >= 16) { const float u = dpp_shr<8>(v); v = r >= 8 ? fmaxf(v, u) : v; }
     return v;
 }
 template <int G>
@@ -295,6 +314,7 @@ __device__ __forceinline__ float seg_prev(float incl, int r)
 {
     if (G == 1) return 0.0f;
     const float u = dpp_shr<1>(incl);
+    if (G == 16) return u;
     return r >= 1 ? u : 0.0f;
 }
 template <int CTRL>
@@ -469,10 +489,11 @@ __device__ __forceinline__ void scan_chunks(const_ptr<float> wp4, int base, unsi
 // Index of the first point of chunk bch at squared distance best from
 // (x, y): together with scan_chunks this is the lowest index attaining the
 // minimum, as in the sequential scan (index 0 when no distance is finite).
-__device__ __forceinline__ int chunk_argmin(const Lds& s, int bch, float best, float x, float y)
+__device__ __forceinline__ int chunk_argmin(const float2* wxy, int bch, float best, float x,
+                                            float y)
 {
     if (!(best < INFINITY)) return 0;
-    const float4* p = reinterpret_cast<const float4*>(s.wp_xy) + bch * kChunkQ;
+    const float4* p = reinterpret_cast<const float4*>(wxy) + bch * kChunkQ;
     int bj = bch * kChunk;
 #pragma unroll
     for (int u = kChunkQ - 1; u >= 0; --u) {
@@ -489,7 +510,7 @@ __device__ __forceinline__ int chunk_argmin(const Lds& s, int bch, float best, f
 
 // Per-lane culling data that stays in registers through the rollout: the
 // bounding box of chunk `lane` and obstacle circle `lane` (the first 64 of
-// each; larger scenes read the rest from LDS).
+// each; larger scenes read the rest from global memory).
 struct LaneCull {
     float4 box;   // (x_lo, x_hi, y_lo, y_hi) of chunk lane; empty past the end
     float4 cpv;   // circle lane (x, y, vx, vy); at infinity past the end
@@ -512,10 +533,15 @@ struct LaneCull {
 //    farther than max(d_safe) + r_c + r_ego from the box of the wave's ego
 //    circles cannot make c_safe positive for any lane, so it is skipped.
 // Lanes whose position or safety distance is not finite are left out of the
-// wave box: their own cost is not finite under either scan.
+// wave box: their own cost is not finite under either scan.  The scene is
+// read from global memory (wave-uniform candidates through the scalar
+// cache); sw holds the lane's three waypoints ahead of its previous closest
+// chunk, fetched at the start of the block, and vref0 the reference speed
+// of waypoint 0.
 template <int NE>
-__device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds& s,
-                                                   const LaneCull& lc, bool vref_uniform, bool act,
+__device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const float2 (&sw)[3],
+                                                   float vref0, const LaneCull& lc,
+                                                   bool vref_uniform, bool act,
                                                    int& seed, float x, float y,
                                                    float c, float sn, float v, float Ua, float Ud,
                                                    float ea, float ed, int t, int t_lo, int t_hi,
@@ -550,9 +576,8 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
         if (seed >= 0) {
 #pragma unroll
             for (int u = 0; u < 3; ++u) {
-                const float2 w = s.wp_xy[min(seed * kChunk + (u + 1) * kSeedAhead, d.n_wp - 1)];
-                const float dx = x - w.x;
-                const float dy = y - w.y;
+                const float dx = x - sw[u].x;
+                const float dy = y - sw[u].y;
                 own = fminf(own, fmaf(dy, dy, dx * dx));
             }
         }
@@ -568,11 +593,11 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
         wave_minmax_nonneg(far2(lc.box), own, ub, ub_own);
         ub = fminf(ub, ub_own);
         for (int base = 64; base < n_ch; base += 64)
-            ub = fminf(ub, wave_min_nonneg(far2(base + lane < n_ch ? s.wp_box[base + lane] : empty)));
+            ub = fminf(ub, wave_min_nonneg(far2(base + lane < n_ch ? d.wp_box[base + lane] : empty)));
         const float thr = fmaf(ub, 1.0f + 1e-5f, 1e-6f);
         scan_chunks(wp4, 0, __ballot(near2(lc.box) <= thr), x, y, best, bch);
         for (int base = 64; base < n_ch; base += 64) {
-            const float4 b = base + lane < n_ch ? s.wp_box[base + lane] : empty;
+            const float4 b = base + lane < n_ch ? d.wp_box[base + lane] : empty;
             scan_chunks(wp4, base, __ballot(near2(b) <= thr), x, y, best, bch);
         }
     }
@@ -580,9 +605,9 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
     // the closest index, needed for its reference speed (unless every
     // waypoint has the same one) and for its yaw
     const bool need_idx = !vref_uniform || d.w_yaw != 0.0f;
-    const int bj = need_idx ? chunk_argmin(s, bch, best, x, y) : 0;
-    const float vref = s.wp_vref[vref_uniform ? 0 : bj];
-    const float ext = extra_terms(d, s, bj, x, y, th, xp, yp);
+    const int bj = need_idx ? chunk_argmin(d.wp_xy, bch, best, x, y) : 0;
+    const float vref = vref_uniform ? vref0 : d.wp_vref[bj];
+    const float ext = extra_terms(d, d.wp_xy, d.wp_yaw, bj, x, y, th, xp, yp);
     const float dv = v - vref;
     const float q = d.w_effort * (d.alpha * fmaf(ea, ea, ed * ed) + fmaf(Ua, ea, Ud * ed) +
                                   0.5f * fmaf(Ua, Ua, Ud * Ud));
@@ -618,7 +643,7 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const Lds&
             if (base == 0) {
                 need = close(lc.cpv, lc.crr);
             } else {
-                need = base + lane < d.n_c && close(s.c_pv[base + lane], s.c_rr[base + lane]);
+                need = base + lane < d.n_c && close(d.c_pv[base + lane], d.c_rr[base + lane]);
             }
             unsigned long long m = __ballot(need);
             while (m) {
@@ -695,26 +720,28 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     constexpr int SPB = kBlock / G;  // samples per tile
     const int T = d.T;
     const int K = d.K;
-    const LdsLayout L = lds_layout(d.n_wp, d.n_c, T, SPB, d.eps_stage, d.per_step);
+    const LdsLayout L = lds_layout(d.n_wp, d.n_c, T, SPB, d.eps_stage, d.per_step, !d.cull);
     const Lds s = lds_bind(smem, L);
 
-    for (int i = tid; i < d.n_c; i += kBlock) {
-        s.c_pv[i] = d.c_pv[i];
-        s.c_rr[i] = d.c_rr[i];
-    }
-    const int n_wp_pad = (d.n_wp + kChunk - 1) / kChunk * kChunk;
-    for (int i = tid; i < n_wp_pad; i += kBlock) {
-        // padding points at infinity are never the closest
-        s.wp_xy[i] = d.wp_xy[i];
-        if (i < d.n_wp) {
-            s.wp_vref[i] = d.wp_vref[i];
-            s.wp_yaw[i] = d.wp_yaw[i];
+    // The culled scans read the scene from global memory, so the rollout
+    // starts at once; the full scans (no culling) read a copy in LDS.
+    if (!d.cull) {
+        for (int i = tid; i < d.n_c; i += kBlock) {
+            s.c_pv[i] = d.c_pv[i];
+            s.c_rr[i] = d.c_rr[i];
         }
+        const int n_wp_pad = (d.n_wp + kChunk - 1) / kChunk * kChunk;
+        for (int i = tid; i < n_wp_pad; i += kBlock) {
+            // padding points at infinity are never the closest
+            s.wp_xy[i] = d.wp_xy[i];
+            if (i < d.n_wp) {
+                s.wp_vref[i] = d.wp_vref[i];
+                s.wp_yaw[i] = d.wp_yaw[i];
+            }
+        }
+        // (x_lo, x_hi, y_lo, y_hi) of every chunk, formed with the scene
+        for (int c = tid; c * kChunk < d.n_wp; c += kBlock) s.wp_box[c] = d.wp_box[c];
     }
-    // (x_lo, x_hi, y_lo, y_hi) of every chunk, formed with the scene
-    for (int c = tid; c * kChunk < d.n_wp; c += kBlock) s.wp_box[c] = d.wp_box[c];
-    for (int i = tid; i < T; i += kBlock)
-        s.U[i] = make_float2((float)d.U[2 * i], (float)d.U[2 * i + 1]);
     // the controls sampled around, kept for the smoothing combine
     if (d.smooth && tile == 0) {
         double* keep = d.partials + (size_t)d.n_tiles * partial_stride(T, d.per_step);
@@ -723,7 +750,8 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     const unsigned long long n_iter = d.st->n_iter;
     // one reference speed for every waypoint: the closest index is not needed
     const bool vref_uniform = d.scene_flags[0] != 0;
-    __syncthreads();
+    const float vref0 = as_const(d.wp_vref)[0];
+    if (!d.cull) __syncthreads();
 
     // ---------------------------------------------------------------- phase 1
     const int grp = tid / G;
@@ -737,9 +765,9 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     {
         const int lane = tid & 63;
         const int n_ch = (d.n_wp + kChunk - 1) / kChunk;
-        lc.box = lane < n_ch ? s.wp_box[lane] : make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
-        lc.cpv = lane < d.n_c ? s.c_pv[lane] : make_float4(INFINITY, INFINITY, 0.0f, 0.0f);
-        lc.crr = lane < d.n_c ? s.c_rr[lane] : 0.0f;
+        lc.box = lane < n_ch ? d.wp_box[lane] : make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+        lc.cpv = lane < d.n_c ? d.c_pv[lane] : make_float4(INFINITY, INFINITY, 0.0f, 0.0f);
+        lc.crr = lane < d.n_c ? d.c_rr[lane] : 0.0f;
     }
     float x = d.px0, y = d.py0, th = d.th0, v = d.v0;
     float delta = d.steer0;  // steering angle (5-state model only)
@@ -753,9 +781,28 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     // it, where they have spread the most.  Kept even so that Philox step
     // pairs stay within a lane pair.
     const int rem = T % G;
+    const int t_first = (rem != 0 && (rem & 1) == 0) ? rem - G : 0;
+    // the nominal control of the lane's step (float64 in global memory),
+    // fetched one block ahead
+    double ua_next = d.U[2 * min(max(t_first + r, 0), T - 1)];
+    double ud_next = d.U[2 * min(max(t_first + r, 0), T - 1) + 1];
     int blk = 0;
-    for (int t0 = (rem != 0 && (rem & 1) == 0) ? rem - G : 0; t0 < T; t0 += G, ++blk) {
+    for (int t0 = t_first; t0 < T; t0 += G, ++blk) {
         const int tm = t0 + r;
+        const float2 Um = make_float2((float)ua_next, (float)ud_next);
+        if (t0 + G < T) {
+            const int tn = min(max(t0 + G + r, 0), T - 1);
+            ua_next = d.U[2 * tn];
+            ud_next = d.U[2 * tn + 1];
+        }
+        // the lane's waypoints ahead of its previous closest chunk (the
+        // culling's own bound), fetched before they are needed
+        float2 sw[3];
+        if (d.cull) {
+            const int sb = max(seed, 0) * kChunk;
+#pragma unroll
+            for (int u = 0; u < 3; ++u) sw[u] = d.wp_xy[min(sb + (u + 1) * kSeedAhead, d.n_wp - 1)];
+        }
         const bool lead = tm < 0;  // before the horizon: no step, no increment
         // The lane's step within the block, opaque to the compiler so that the
         // per-step "own step" tests stay in the loop as vector compares
@@ -793,7 +840,6 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             }
             em = noise_from_words(d, ra, rb);
         }
-        const float2 Um = s.U[tc];
         const float a0m = fminf(fmaxf(Um.x + em.x, d.a_min), d.a_max);
         const float dlm = fminf(fmaxf(Um.y + em.y, d.d_min), d.d_max);
         const float tnm = M5 ? dlm : __tanf(dlm);
@@ -881,7 +927,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         const bool act = !lead && tm < T;
         float q = 0.0f;
         if (d.cull)
-            q = stage_cost_culled<NE>(d, s, lc, vref_uniform, act, seed, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm,
+            q = stage_cost_culled<NE>(d, sw, vref0, lc, vref_uniform, act, seed, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm,
                                       max(t0, 0), min(t0 + G, T) - 1, mth, pxp, pyp);
         else if (act)
             q = stage_cost<NE>(d, s, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm, mth, pxp, pyp);

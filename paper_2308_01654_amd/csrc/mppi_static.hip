@@ -183,7 +183,7 @@ extern "C" mppi_status mppi_step_static(const mppi_config* cfg, const double x0[
     fill_desc(d, &inst, x0, origin, inst.scene, lay, n_wp, n_c, 0);
     choose_eps_stage(d, true);  // launched alone, as mppi_step_resident launches it
     const size_t smem =
-        lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes, d.eps_stage, d.per_step).total;
+        lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes, d.eps_stage, d.per_step, !d.cull).total;
     unsigned int* tickets = reinterpret_cast<unsigned int*>(
         align_up(reinterpret_cast<uintptr_t>(inst.st + 1), 4 * kTicketStride));
     hipLaunchKernelGGL(k_static_begin, dim3(1), dim3(256), 0, stream, inst.st, tickets, n_tickets,
