@@ -28,25 +28,32 @@ struct DevState {
     double ess;                 // z^2 / sum_k exp(-2 (S_k - s_min)/lambda)
 };
 
-// Partial results of one tile of samples: tile minimum, shifted exponential
-// sums and the shifted weighted perturbation sums for every (t, control).
-//   [0] m_b  [1] Z_b  [2] Q_b (sum of squares)  [3] unused  [4 + 2t + d] N_b
-constexpr int kPartialHead = 4;
+// Partial results of one tile of samples: a row of the shifted weighted
+// perturbation sums N_b of every (t, control) at [2t + d], and a head
+//   [0] m_b (tile minimum)  [1] Z_b  [2] Q_b (sum of squares)  [3] unused
+// kept in a compact array of its own (heads of consecutive tiles are
+// consecutive), so that the combine reads all heads in a few lines.
+constexpr int kHeadDoubles = 4;
 
 // With per-step weights a partial row holds, for every step t, the tile
 // minimum of the cost-to-go, the shifted exponential sums and the two
-// weighted perturbation sums ([5t .. 5t+4]).
+// weighted perturbation sums ([5t .. 5t+4]); there is no head array.
 inline __host__ __device__ int partial_stride(int T, int per_step)
 {
-    return per_step ? 5 * T : kPartialHead + 2 * T;
+    return per_step ? 5 * T : 2 * T;
 }
 
-// Doubles of the partials buffer of an instance: the tile rows, then 2T
+// Layout of the partials buffer of an instance: the tile rows, then 2T
 // doubles where the iteration kernel keeps the controls it sampled around
-// (read by the combine kernel when it smooths).
-inline __host__ __device__ size_t partial_doubles(int T, int per_step, size_t tiles)
+// (read by the combine kernel when it smooths), then (total-cost weights)
+// the tile heads.
+inline __host__ __device__ size_t partial_heads_offset(int T, int per_step, size_t tiles)
 {
     return tiles * (size_t)partial_stride(T, per_step) + 2 * (size_t)T;
+}
+inline __host__ __device__ size_t partial_doubles(int T, int per_step, size_t tiles)
+{
+    return partial_heads_offset(T, per_step, tiles) + (per_step ? 0 : kHeadDoubles * tiles);
 }
 
 // Tile partials are merged by the combine kernel, which takes up to kDirect

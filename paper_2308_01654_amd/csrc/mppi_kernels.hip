@@ -38,6 +38,48 @@
 
 namespace mppi_impl {
 
+// Accesses to the instance's global arrays through pointers typed as global
+// memory: the descriptor's pointers are generic, and generic (flat)
+// accesses also count against the counter that scalar and LDS loads wait
+// on, so every wait for a scalar candidate load would also wait for the
+// rollout's in-flight global loads and stores.
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T* p)
+{
+    return (gptr<T>)p;
+}
+template <typename T>
+__device__ __forceinline__ T ld_g(const T* p, size_t i)
+{
+    return as_global(p)[i];
+}
+__device__ __forceinline__ float2 ld_g(const float2* p, size_t i)
+{
+    const f2v v = as_global(reinterpret_cast<const f2v*>(p))[i];
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ float4 ld_g(const float4* p, size_t i)
+{
+    const f4v v = as_global(reinterpret_cast<const f4v*>(p))[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+template <typename T>
+__device__ __forceinline__ void st_g(T* p, size_t i, T v)
+{
+    as_global(p)[i] = v;
+}
+__device__ __forceinline__ void st_g(float2* p, size_t i, float2 v)
+{
+    f2v w;
+    w.x = v.x;
+    w.y = v.y;
+    as_global(reinterpret_cast<f2v*>(p))[i] = w;
+}
+
 // ----------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
 // 4x32 S-box (two 32x32->64 multiplies, xor with the other half and the key)
@@ -166,21 +208,22 @@ __device__ __forceinline__ float circle_gap(const float (&ex)[NE > 0 ? NE : 1],
 // |P - T|^2 - |P_prev - T|^2 = (P - P_prev).(P + P_prev - 2 T) -- and c_yaw,
 // the heading th minus the yaw of closest waypoint bj, wrapped into
 // [-pi, pi), squared.
-// The waypoint arrays are read from wxy / wyaw (the tile's LDS copy or the
-// scene in global memory: the same values either way).
+// The waypoint arrays are read from wxy / wyaw: the tile's LDS copy, or
+// (GLOBAL) the scene in global memory -- the same values either way.
+template <bool GLOBAL>
 __device__ __forceinline__ float extra_terms(const InstDesc& d, const float2* wxy,
                                              const float* wyaw, int bj, float x, float y,
                                              float th, float xp, float yp)
 {
     float e = 0.0f;
     if (d.w_target != 0.0f) {
-        const float2 tp = wxy[d.n_wp - 1];
+        const float2 tp = GLOBAL ? ld_g(wxy, d.n_wp - 1) : wxy[d.n_wp - 1];
         const float dx = x - xp, dy = y - yp;
         const float sx = (x - tp.x) + (xp - tp.x), sy = (y - tp.y) + (yp - tp.y);
         e = fmaf(d.w_target, fmaf(dx, sx, dy * sy) > 0.0f ? 1.0f : 0.0f, e);
     }
     if (d.w_yaw != 0.0f) {
-        float dyaw = th - wyaw[bj];
+        float dyaw = th - (GLOBAL ? ld_g(wyaw, bj) : wyaw[bj]);
         dyaw -= 6.28318530717958647692f *
                 floorf((dyaw + 3.14159265358979323846f) * 0.15915494309189533577f);
         e = fmaf(d.w_yaw, dyaw * dyaw, e);
@@ -209,7 +252,7 @@ __device__ __forceinline__ float stage_cost(const InstDesc& d, const Lds& s, flo
     float best = INFINITY;
     int bj = 0;
     for (int ch = 0; ch * kChunk < d.n_wp; ++ch) scan_chunk(s, ch, x, y, best, bj);
-    const float ext = extra_terms(d, s.wp_xy, s.wp_yaw, bj, x, y, th, xp, yp);
+    const float ext = extra_terms<false>(d, s.wp_xy, s.wp_yaw, bj, x, y, th, xp, yp);
     const float dv = v - s.wp_vref[bj];
     // q_u = w_effort (alpha eps.eps + U.eps + U.U / 2)
     const float q = d.w_effort * (d.alpha * fmaf(ea, ea, ed * ed) + fmaf(Ua, ea, Ud * ed) +
@@ -497,7 +540,7 @@ __device__ __forceinline__ int chunk_argmin(const float2* wxy, int bch, float be
     int bj = bch * kChunk;
 #pragma unroll
     for (int u = kChunkQ - 1; u >= 0; --u) {
-        const float4 q = p[u];
+        const float4 q = ld_g(p, u);
 #pragma unroll
         for (int h = 1; h >= 0; --h) {
             const float dx = x - (h ? q.z : q.x);
@@ -593,11 +636,11 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const floa
         wave_minmax_nonneg(far2(lc.box), own, ub, ub_own);
         ub = fminf(ub, ub_own);
         for (int base = 64; base < n_ch; base += 64)
-            ub = fminf(ub, wave_min_nonneg(far2(base + lane < n_ch ? d.wp_box[base + lane] : empty)));
+            ub = fminf(ub, wave_min_nonneg(far2(base + lane < n_ch ? ld_g(d.wp_box, base + lane) : empty)));
         const float thr = fmaf(ub, 1.0f + 1e-5f, 1e-6f);
         scan_chunks(wp4, 0, __ballot(near2(lc.box) <= thr), x, y, best, bch);
         for (int base = 64; base < n_ch; base += 64) {
-            const float4 b = base + lane < n_ch ? d.wp_box[base + lane] : empty;
+            const float4 b = base + lane < n_ch ? ld_g(d.wp_box, base + lane) : empty;
             scan_chunks(wp4, base, __ballot(near2(b) <= thr), x, y, best, bch);
         }
     }
@@ -606,8 +649,8 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const floa
     // waypoint has the same one) and for its yaw
     const bool need_idx = !vref_uniform || d.w_yaw != 0.0f;
     const int bj = need_idx ? chunk_argmin(d.wp_xy, bch, best, x, y) : 0;
-    const float vref = vref_uniform ? vref0 : d.wp_vref[bj];
-    const float ext = extra_terms(d, d.wp_xy, d.wp_yaw, bj, x, y, th, xp, yp);
+    const float vref = vref_uniform ? vref0 : ld_g(d.wp_vref, bj);
+    const float ext = extra_terms<true>(d, d.wp_xy, d.wp_yaw, bj, x, y, th, xp, yp);
     const float dv = v - vref;
     const float q = d.w_effort * (d.alpha * fmaf(ea, ea, ed * ed) + fmaf(Ua, ea, Ud * ed) +
                                   0.5f * fmaf(Ua, Ua, Ud * Ud));
@@ -643,7 +686,7 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const floa
             if (base == 0) {
                 need = close(lc.cpv, lc.crr);
             } else {
-                need = base + lane < d.n_c && close(d.c_pv[base + lane], d.c_rr[base + lane]);
+                need = base + lane < d.n_c && close(ld_g(d.c_pv, base + lane), ld_g(d.c_rr, base + lane));
             }
             unsigned long long m = __ballot(need);
             while (m) {
@@ -727,29 +770,29 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     // starts at once; the full scans (no culling) read a copy in LDS.
     if (!d.cull) {
         for (int i = tid; i < d.n_c; i += kBlock) {
-            s.c_pv[i] = d.c_pv[i];
-            s.c_rr[i] = d.c_rr[i];
+            s.c_pv[i] = ld_g(d.c_pv, i);
+            s.c_rr[i] = ld_g(d.c_rr, i);
         }
         const int n_wp_pad = (d.n_wp + kChunk - 1) / kChunk * kChunk;
         for (int i = tid; i < n_wp_pad; i += kBlock) {
             // padding points at infinity are never the closest
-            s.wp_xy[i] = d.wp_xy[i];
+            s.wp_xy[i] = ld_g(d.wp_xy, i);
             if (i < d.n_wp) {
-                s.wp_vref[i] = d.wp_vref[i];
-                s.wp_yaw[i] = d.wp_yaw[i];
+                s.wp_vref[i] = ld_g(d.wp_vref, i);
+                s.wp_yaw[i] = ld_g(d.wp_yaw, i);
             }
         }
         // (x_lo, x_hi, y_lo, y_hi) of every chunk, formed with the scene
-        for (int c = tid; c * kChunk < d.n_wp; c += kBlock) s.wp_box[c] = d.wp_box[c];
+        for (int c = tid; c * kChunk < d.n_wp; c += kBlock) s.wp_box[c] = ld_g(d.wp_box, c);
     }
     // the controls sampled around, kept for the smoothing combine
     if (d.smooth && tile == 0) {
         double* keep = d.partials + (size_t)d.n_tiles * partial_stride(T, d.per_step);
-        for (int i = tid; i < 2 * T; i += kBlock) keep[i] = d.U[i];
+        for (int i = tid; i < 2 * T; i += kBlock) st_g(keep, i, ld_g(d.U, i));
     }
-    const unsigned long long n_iter = d.st->n_iter;
+    const unsigned long long n_iter = ld_g(&d.st->n_iter, 0);
     // one reference speed for every waypoint: the closest index is not needed
-    const bool vref_uniform = d.scene_flags[0] != 0;
+    const bool vref_uniform = ld_g(d.scene_flags, 0) != 0;
     const float vref0 = as_const(d.wp_vref)[0];
     if (!d.cull) __syncthreads();
 
@@ -765,9 +808,9 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     {
         const int lane = tid & 63;
         const int n_ch = (d.n_wp + kChunk - 1) / kChunk;
-        lc.box = lane < n_ch ? d.wp_box[lane] : make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
-        lc.cpv = lane < d.n_c ? d.c_pv[lane] : make_float4(INFINITY, INFINITY, 0.0f, 0.0f);
-        lc.crr = lane < d.n_c ? d.c_rr[lane] : 0.0f;
+        lc.box = lane < n_ch ? ld_g(d.wp_box, lane) : make_float4(INFINITY, -INFINITY, INFINITY, -INFINITY);
+        lc.cpv = lane < d.n_c ? ld_g(d.c_pv, lane) : make_float4(INFINITY, INFINITY, 0.0f, 0.0f);
+        lc.crr = lane < d.n_c ? ld_g(d.c_rr, lane) : 0.0f;
     }
     float x = d.px0, y = d.py0, th = d.th0, v = d.v0;
     float delta = d.steer0;  // steering angle (5-state model only)
@@ -784,16 +827,16 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     const int t_first = (rem != 0 && (rem & 1) == 0) ? rem - G : 0;
     // the nominal control of the lane's step (float64 in global memory),
     // fetched one block ahead
-    double ua_next = d.U[2 * min(max(t_first + r, 0), T - 1)];
-    double ud_next = d.U[2 * min(max(t_first + r, 0), T - 1) + 1];
+    double ua_next = ld_g(d.U, 2 * min(max(t_first + r, 0), T - 1));
+    double ud_next = ld_g(d.U, 2 * min(max(t_first + r, 0), T - 1) + 1);
     int blk = 0;
     for (int t0 = t_first; t0 < T; t0 += G, ++blk) {
         const int tm = t0 + r;
         const float2 Um = make_float2((float)ua_next, (float)ud_next);
         if (t0 + G < T) {
             const int tn = min(max(t0 + G + r, 0), T - 1);
-            ua_next = d.U[2 * tn];
-            ud_next = d.U[2 * tn + 1];
+            ua_next = ld_g(d.U, 2 * tn);
+            ud_next = ld_g(d.U, 2 * tn + 1);
         }
         // the lane's waypoints ahead of its previous closest chunk (the
         // culling's own bound), fetched before they are needed
@@ -801,7 +844,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         if (d.cull) {
             const int sb = max(seed, 0) * kChunk;
 #pragma unroll
-            for (int u = 0; u < 3; ++u) sw[u] = d.wp_xy[min(sb + (u + 1) * kSeedAhead, d.n_wp - 1)];
+            for (int u = 0; u < 3; ++u) sw[u] = ld_g(d.wp_xy, min(sb + (u + 1) * kSeedAhead, d.n_wp - 1));
         }
         const bool lead = tm < 0;  // before the horizon: no step, no increment
         // The lane's step within the block, opaque to the compiler so that the
@@ -932,7 +975,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         else if (act)
             q = stage_cost<NE>(d, s, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm, mth, pxp, pyp);
         if (act && d.per_step) {
-            if (valid) d.q[(size_t)tm * K + k] = q;
+            if (valid) st_g(d.q, (size_t)tm * K + k, q);
             if (L.eps_staged) s.qs[tm * (SPB + 1) + grp] = q;
         }
         if (act) {
@@ -940,7 +983,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             const float tk = S + yk;
             comp = (tk - S) - yk;
             S = tk;
-            if (valid) d.eps[(size_t)tm * K + k] = make_float2(mea, med);
+            if (valid) st_g(d.eps, (size_t)tm * K + k, make_float2(mea, med));
             if (L.eps_staged) {
                 s.eps[(2 * tm) * (SPB + 1) + grp] = mea;
                 s.eps[(2 * tm + 1) * (SPB + 1) + grp] = med;
@@ -956,7 +999,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     if (G >= 16) Sd += dpp_d<0x140>(Sd);
     float Sk = (float)Sd;
     if (!valid || !isfinite(Sk)) Sk = INFINITY;
-    if (valid && r == 0) d.S[k] = (float)Sd;
+    if (valid && r == 0) st_g(d.S, k, (float)Sd);
 
     // ---------------------------------------------------------------- phase 2
     const int stride = partial_stride(T, d.per_step);
@@ -980,16 +1023,16 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             const int ta = min(p * len, T), tb = min(ta + len, T);
             const bool on = j < n_valid;
             auto st_ld = [&](int t) {
-                return lds ? s.ss[t * (SPB + 1) + j] : d.Stk[(size_t)t * K + k_base + j];
+                return lds ? s.ss[t * (SPB + 1) + j] : ld_g(d.Stk, (size_t)t * K + k_base + j);
             };
             auto st_st = [&](int t, double v) {
                 if (lds) s.ss[t * (SPB + 1) + j] = v;
-                else d.Stk[(size_t)t * K + k_base + j] = v;
+                else st_g(d.Stk, (size_t)t * K + k_base + j, v);
             };
             if (on) {
                 double acc = 0.0;
                 for (int t = tb - 1; t >= ta; --t) {
-                    acc += lds ? (double)s.qs[t * (SPB + 1) + j] : (double)d.q[(size_t)t * K + k_base + j];
+                    acc += lds ? (double)s.qs[t * (SPB + 1) + j] : (double)ld_g(d.q, (size_t)t * K + k_base + j);
                     st_st(t, acc);
                 }
             }
@@ -1001,9 +1044,9 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             __syncthreads();  // segment totals are read before they change
             if (on && p < G - 1 && ta < T) {
                 for (int t = ta; t < tb; ++t) st_st(t, st_ld(t) + off);
-                if (lds && p == 0) d.Stk[k_base + j] = st_ld(0);
+                if (lds && p == 0) st_g(d.Stk, k_base + j, st_ld(0));
             } else if (on && lds && p == 0) {
-                d.Stk[k_base + j] = st_ld(0);
+                st_g(d.Stk, k_base + j, st_ld(0));
             }
         }
         __syncthreads();
@@ -1043,15 +1086,15 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
                     nd += om * (double)s.eps[(2 * t + 1) * (SPB + 1) + j];
                 }
                 double* o = part + 5 * t;
-                o[0] = mt[t];
-                o[1] = z;
-                o[2] = qq;
-                o[3] = na;
-                o[4] = nd;
+                st_g(o, 0, mt[t]);
+                st_g(o, 1, z);
+                st_g(o, 2, qq);
+                st_g(o, 3, na);
+                st_g(o, 4, nd);
             }
         }
         for (int t = tid; t < T && !lds; t += kBlock) {
-            auto st_at = [&](int j) { return d.Stk[(size_t)t * K + k_base + j]; };
+            auto st_at = [&](int j) { return ld_g(d.Stk, (size_t)t * K + k_base + j); };
             double m = INFINITY;
             for (int j = 0; j < n_valid; ++j) {
                 const double v = st_at(j);
@@ -1063,7 +1106,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
                 for (int j = 0; j < n_valid; ++j) {
                     const double v = st_at(j);
                     const double om = isfinite(v) ? exp(-(v - m) / d.lambda) : 0.0;
-                    const float2 ev = d.eps[(size_t)t * K + k_base + j];
+                    const float2 ev = ld_g(d.eps, (size_t)t * K + k_base + j);
                     z += om;
                     qq += om * om;
                     na += om * (double)ev.x;
@@ -1071,11 +1114,11 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
                 }
             }
             double* o = part + 5 * t;
-            o[0] = m;
-            o[1] = z;
-            o[2] = qq;
-            o[3] = na;
-            o[4] = nd;
+            st_g(o, 0, m);
+            st_g(o, 1, z);
+            st_g(o, 2, qq);
+            st_g(o, 3, na);
+            st_g(o, 4, nd);
         }
     } else {
         // Tile minimum, then the tile's exponential sums: wave results through
@@ -1133,7 +1176,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
                     for (int j = 0; j < n_valid; ++j)
                         acc = fma(s.omega[j], (double)e[j], acc);
                 }
-                part[kPartialHead + col] = acc;
+                st_g(part, col, acc);
                 continue;
             }
             const int t = col >> 1;
@@ -1143,18 +1186,19 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             for (int i0 = 0; i0 < n_valid; i0 += NB) {
                 float ev[NB];
 #pragma unroll
-                for (int u = 0; u < NB; ++u) ev[u] = (i0 + u < n_valid) ? e[2 * (i0 + u)] : 0.0f;
+                for (int u = 0; u < NB; ++u) ev[u] = (i0 + u < n_valid) ? ld_g(e, 2 * (i0 + u)) : 0.0f;
 #pragma unroll
                 for (int u = 0; u < NB; ++u)
                     if (i0 + u < n_valid) acc = fma(s.omega[i0 + u], (double)ev[u], acc);
             }
-            part[kPartialHead + col] = acc;
+            st_g(part, col, acc);
         }
         if (tid == 0) {
-            part[0] = m_b;
-            part[1] = z_b;
-            part[2] = q_b;
-            part[3] = 0.0;
+            double* hd = d.partials + partial_heads_offset(T, 0, d.n_tiles) + kHeadDoubles * tile;
+            st_g(hd, 0, m_b);
+            st_g(hd, 1, z_b);
+            st_g(hd, 2, q_b);
+            st_g(hd, 3, 0.0);
         }
     }
 
@@ -1163,8 +1207,9 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     // one.  More than kDirect tiles
     // are first merged here, kFanIn at a time in tile order with the
     // log-sum-exp shift to their common minimum, until at most kDirect nodes
-    // remain; a node's row is the row of its first tile.
+    // remain; a node's row and head are those of its first tile.
     if (d.per_step || d.n_tiles <= kDirect) return;
+    double* heads = d.partials + partial_heads_offset(T, 0, d.n_tiles);
     // first ticket on the 128-byte line after the state
     unsigned int* tickets = reinterpret_cast<unsigned int*>(
         (reinterpret_cast<uintptr_t>(d.st + 1) + 4 * kTicketStride - 1) & ~(uintptr_t)(4 * kTicketStride - 1));
@@ -1197,11 +1242,12 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
 
         double* rows = d.partials + (size_t)first * span * stride;
         const size_t cstride = span * stride;  // between consecutive children
+        double* head = heads + kHeadDoubles * (size_t)first * span;
         if (tid < 64) {
-            const double* h = rows + (size_t)min(tid, nc - 1) * cstride;
-            const double mi = tid < nc ? h[0] : INFINITY;
-            const double zi = tid < nc ? h[1] : 0.0;
-            const double qi = tid < nc ? h[2] : 0.0;
+            const double* h = head + kHeadDoubles * (size_t)min(tid, nc - 1) * span;
+            const double mi = tid < nc ? ld_g(h, 0) : INFINITY;
+            const double zi = tid < nc ? ld_g(h, 1) : 0.0;
+            const double qi = tid < nc ? ld_g(h, 2) : 0.0;
             const double mm = wave_min(mi);
             // a child whose samples are all non-finite has m = +inf and weight 0
             const double sc = (tid < nc && isfinite(mi)) ? exp(-(mi - mm) / d.lambda) : 0.0;
@@ -1216,21 +1262,21 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         }
         __syncthreads();
         for (int col = tid; col < 2 * T; col += kBlock) {
-            const double* src = rows + kPartialHead + col;
+            const double* src = rows + col;
             // every child in flight at once, merged in child order
             double pv[kFanIn];
 #pragma unroll
-            for (int u = 0; u < kFanIn; ++u) pv[u] = u < nc ? src[(size_t)u * cstride] : 0.0;
+            for (int u = 0; u < kFanIn; ++u) pv[u] = u < nc ? ld_g(src, (size_t)u * cstride) : 0.0;
             double acc = 0.0;
 #pragma unroll
             for (int u = 0; u < kFanIn; ++u)
                 if (u < nc) acc += pv[u] * sc_lds[u];
-            rows[kPartialHead + col] = acc;
+            st_g(rows, col, acc);
         }
         if (tid == 0) {
-            rows[0] = s.red[0];
-            rows[1] = s.red[1];
-            rows[2] = s.red[2];
+            st_g(head, 0, s.red[0]);
+            st_g(head, 1, s.red[1]);
+            st_g(head, 2, s.red[2]);
         }
         toff += (n_l + kFanIn - 1) / kFanIn;
         n_l = (n_l + kFanIn - 1) / kFanIn;
@@ -1272,32 +1318,34 @@ __device__ void combine(const InstDesc& d, int cg)
     const int n = combine_nodes(d.n_tiles, &span);
     const size_t nstride = span * stride;    // between nodes
     const double* rows = d.partials;
+    const double* heads = d.partials + partial_heads_offset(T, 0, d.n_tiles);
 
-    // One round trip: the node heads (kDirect / kBlock per thread) and the
-    // first sixteen nodes of this thread's chunk of its worked column.
+    // One round trip: the node heads (kDirect / kBlock per thread, from the
+    // compact head array) and the first sixteen nodes of this thread's chunk
+    // of its worked column.
     constexpr int kH = kDirect / kBlock;
     double mh[kH], zh[kH], qh[kH];
 #pragma unroll
     for (int r = 0; r < kH; ++r) {
         const int i = tid + r * kBlock;
-        const double* h = rows + (size_t)min(i, n - 1) * nstride;
-        mh[r] = i < n ? h[0] : INFINITY;
-        zh[r] = i < n ? h[1] : 0.0;
-        qh[r] = i < n ? h[2] : 0.0;
+        const double* h = heads + kHeadDoubles * (size_t)min(i, n - 1) * span;
+        mh[r] = i < n ? ld_g(h, 0) : INFINITY;
+        zh[r] = i < n ? ld_g(h, 1) : 0.0;
+        qh[r] = i < n ? ld_g(h, 2) : 0.0;
     }
     const int slot = tid % slots, chunk = tid / slots;
     const int per = (n + chunks - 1) / chunks;
     const int i0 = min(chunk * per, n), i1 = min(i0 + per, n);
     const bool worked = slot < ncol;
-    const double* src = rows + kPartialHead + 2 * w0 + slot;
+    const double* src = rows + 2 * w0 + slot;
     // the controls the iteration sampled around (kept after the tile rows when
     // smoothing, since other workgroups rewrite U), loaded with the rest
     const double* u_old = d.smooth ? d.partials + (size_t)d.n_tiles * stride : d.U;
-    const double u_prev = tid < ncol ? u_old[2 * w0 + tid] : 0.0;
+    const double u_prev = tid < ncol ? ld_g(u_old, 2 * w0 + tid) : 0.0;
     double pv[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u)
-        pv[u] = (worked && i0 + u < i1) ? src[(size_t)(i0 + u) * nstride] : 0.0;
+        pv[u] = (worked && i0 + u < i1) ? ld_g(src, (size_t)(i0 + u) * nstride) : 0.0;
 
     // global minimum
     double mloc = mh[0];
@@ -1347,7 +1395,7 @@ __device__ void combine(const InstDesc& d, int cg)
             if (i0 + u < i1) acc += pv[u] * sc[i0 + u];
         for (int b = i0 + 16; b < i1; b += 16) {
 #pragma unroll
-            for (int u = 0; u < 16; ++u) pv[u] = b + u < i1 ? src[(size_t)(b + u) * nstride] : 0.0;
+            for (int u = 0; u < 16; ++u) pv[u] = b + u < i1 ? ld_g(src, (size_t)(b + u) * nstride) : 0.0;
 #pragma unroll
             for (int u = 0; u < 16; ++u)
                 if (b + u < i1) acc += pv[u] * sc[b + u];
