@@ -578,11 +578,11 @@ struct LaneCull {
 // Lanes whose position or safety distance is not finite are left out of the
 // wave box: their own cost is not finite under either scan.  The scene is
 // read from global memory (wave-uniform candidates through the scalar
-// cache); sw holds the lane's three waypoints ahead of its previous closest
-// chunk, fetched at the start of the block, and vref0 the reference speed
-// of waypoint 0.
+// cache); own_d2 is the lane's squared distance to the nearest of three
+// waypoints ahead of its previous closest chunk (+inf without one), formed
+// by the caller, and vref0 the reference speed of waypoint 0.
 template <int NE>
-__device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const float2 (&sw)[3],
+__device__ __forceinline__ float stage_cost_culled(const InstDesc& d, float own_d2,
                                                    float vref0, const LaneCull& lc,
                                                    bool vref_uniform, bool act,
                                                    int& seed, float x, float y,
@@ -613,18 +613,7 @@ __device__ __forceinline__ float stage_cost_culled(const InstDesc& d, const floa
     // A second bound from the lane itself: its distance^2 to three waypoints
     // ahead of the chunk it was closest to at its previous step (seed), the
     // largest over the lanes of the wave; lanes without a seed give +inf.
-    float own = 0.0f;
-    if (inc) {
-        own = INFINITY;
-        if (seed >= 0) {
-#pragma unroll
-            for (int u = 0; u < 3; ++u) {
-                const float dx = x - sw[u].x;
-                const float dy = y - sw[u].y;
-                own = fminf(own, fmaf(dy, dy, dx * dx));
-            }
-        }
-    }
+    const float own = inc ? own_d2 : 0.0f;
     if (n_ch <= 64) {
         float ub_box, ub_own;
         wave_minmax_nonneg(far2(lc.box), own, ub_box, ub_own);
@@ -968,9 +957,31 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         const float mUa = Um.x, mUd = Um.y;
         const float mea = ma - Um.x, med = dlm - Um.y;
         const bool act = !lead && tm < T;
+        // the culling's own bound (consumes the waypoint loads of the block
+        // start before the store below enters the vector-memory counter)
+        float own_d2 = INFINITY;
+        if (d.cull && seed >= 0) {
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const float dx = mx - sw[u].x;
+                const float dy = my - sw[u].y;
+                own_d2 = fminf(own_d2, fmaf(dy, dy, dx * dx));
+            }
+        }
+        // The applied perturbation is stored now, before the stage cost: the
+        // store then retires during the scans instead of holding up the next
+        // block's first wait on the vector-memory counter (loads and stores
+        // share it and complete in order).
+        if (act) {
+            if (valid) st_g(d.eps, (size_t)tm * K + k, make_float2(mea, med));
+            if (L.eps_staged) {
+                s.eps[(2 * tm) * (SPB + 1) + grp] = mea;
+                s.eps[(2 * tm + 1) * (SPB + 1) + grp] = med;
+            }
+        }
         float q = 0.0f;
         if (d.cull)
-            q = stage_cost_culled<NE>(d, sw, vref0, lc, vref_uniform, act, seed, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm,
+            q = stage_cost_culled<NE>(d, own_d2, vref0, lc, vref_uniform, act, seed, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm,
                                       max(t0, 0), min(t0 + G, T) - 1, mth, pxp, pyp);
         else if (act)
             q = stage_cost<NE>(d, s, mx, my, mc, ms, mv, mUa, mUd, mea, med, tm, mth, pxp, pyp);
@@ -983,11 +994,6 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
             const float tk = S + yk;
             comp = (tk - S) - yk;
             S = tk;
-            if (valid) st_g(d.eps, (size_t)tm * K + k, make_float2(mea, med));
-            if (L.eps_staged) {
-                s.eps[(2 * tm) * (SPB + 1) + grp] = mea;
-                s.eps[(2 * tm + 1) * (SPB + 1) + grp] = med;
-            }
         }
     }
 
