@@ -67,6 +67,13 @@ __device__ __forceinline__ float4 ld_g(const float4* p, size_t i)
     const f4v v = as_global(reinterpret_cast<const f4v*>(p))[i];
     return make_float4(v.x, v.y, v.z, v.w);
 }
+// Element i (below 2^32 bytes from p) of a small array: a 32-bit offset from
+// a uniform base, without 64-bit address arithmetic per lane.
+__device__ __forceinline__ float2 ld_g32(const float2* p, unsigned i)
+{
+    const f2v v = *(gptr<const f2v>)((gptr<const char>)(const char*)p + i * 8u);
+    return make_float2(v.x, v.y);
+}
 template <typename T>
 __device__ __forceinline__ void st_g(T* p, size_t i, T v)
 {
@@ -85,14 +92,17 @@ __device__ __forceinline__ void st_g(float2* p, size_t i, float2 v)
 // 4x32 S-box (two 32x32->64 multiplies, xor with the other half and the key)
 // with a Weyl-sequence key schedule.
 // ----------------------------------------------------------------------------
+// (v_bitop3 with truth table 0x96 is the three-input exclusive or of gfx950)
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
-                       (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
+        c = make_uint4(__builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.y, k0, 0x96),
+                       (uint32_t)p1,
+                       __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.w, k1, 0x96),
+                       (uint32_t)p0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -192,12 +202,13 @@ __device__ __forceinline__ float circle_gap(const float (&ex)[NE > 0 ? NE : 1],
 {
     const float ox = fmaf(tau, p.z, p.x);
     const float oy = fmaf(tau, p.w, p.y);
-    float m2 = INFINITY;
+    float m2 = 0.0f;
 #pragma unroll
     for (int e = 0; e < NE; ++e) {
         const float dx = ex[e] - ox;
         const float dy = ey[e] - oy;
-        m2 = fminf(m2, fmaf(dy, dy, dx * dx));
+        const float d2 = fmaf(dy, dy, dx * dx);
+        m2 = e == 0 ? d2 : fminf(m2, d2);
     }
     return __builtin_amdgcn_sqrtf(m2) - rr;
 }
@@ -833,7 +844,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
         if (d.cull) {
             const int sb = max(seed, 0) * kChunk;
 #pragma unroll
-            for (int u = 0; u < 3; ++u) sw[u] = ld_g(d.wp_xy, min(sb + (u + 1) * kSeedAhead, d.n_wp - 1));
+            for (int u = 0; u < 3; ++u) sw[u] = ld_g32(d.wp_xy, (unsigned)min(sb + (u + 1) * kSeedAhead, d.n_wp - 1));
         }
         const bool lead = tm < 0;  // before the horizon: no step, no increment
         // The lane's step within the block, opaque to the compiler so that the
