@@ -10,12 +10,16 @@ every timed step is ``mppi_step_resident``.
 
 Prints one JSON line: throughput in rollout-steps/s (K*T per iteration over
 the HIP-event time of the timed region), the roofline of the fused iteration
-kernel (algorithmic FP32 flops per launch over its HIP-event duration), the
-plain one-at-a-time replan latency percentiles, the host-buffer (PCIe
-inclusive) rate, and the FP64 CPU oracle timed on the host on a bounded
-sample of the same workload.
+kernel (algorithmic FP32 flops per launch over its HIP-event duration, and
+the FP32 work it executes from committed hardware counters), the plain
+one-at-a-time replan latency percentiles, the host-buffer (PCIe inclusive)
+rate, the served and plain paths under the 20 Hz fleet load, the other
+workloads' iteration times, and the FP64 CPU oracle timed on the host on
+bounded samples of the same workloads (all cores and one core).
 
 Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 20]
+       python bench.py --serve-sweep [--sweep-seconds 60]   (served and plain
+       paths at several offered loads; one JSON line per run)
 """
 from __future__ import annotations
 
@@ -67,10 +71,36 @@ def load_traffic(n_launch_units):
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(sc, seconds):
-    """The FP64 oracle, unchanged, on the host cores: full iterations of the
-    same workload, repeated until `seconds` have passed (at least one)."""
-    from oracle import oracle as O
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_iteration_c1.json")
+
+
+def load_counters():
+    """SQ counters of the iteration kernel (one dispatch at the benchmark
+    workload) from the committed rocprofv3 summary, if it was taken on the
+    current kernel source."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_iterations(O, sc, seconds):
+    """Warm-started full oracle iterations until `seconds` have passed."""
     p = sc["params"]
     U = np.zeros((p["T"], 2))
     n = 0
@@ -81,10 +111,78 @@ def cpu_baseline(sc, seconds):
         el = time.perf_counter() - t0
         if el >= seconds:
             break
-    return dict(value=p["K"] * p["T"] * n / el, unit="rollout-steps/s", cores=O.max_threads(),
-                kind="oracle",
-                sample="%d warm-started FP64 oracle iteration(s) of the K=%d, T=%d sine-lane "
-                       "instance in %.1f s" % (n, p["K"], p["T"], el))
+    return p["K"] * p["T"] * n / el, "%d full iteration(s) in %.2f s" % (n, el)
+
+
+def _oracle_rollouts(O, sc, n_samples):
+    """Rollouts (noise, dynamics, stage costs) of the first n_samples samples
+    of the instance: the bulk of an iteration's work."""
+    p = sc["params"]
+    ks = np.arange(min(n_samples, p["K"]))
+    t0 = time.perf_counter()
+    O.rollout_samples(p, sc["x0"], sc["waypoints"], sc["circles"], np.zeros((p["T"], 2)), ks)
+    el = time.perf_counter() - t0
+    return ks.size * p["T"] / el, "rollouts of %d of the %d samples in %.2f s" % (ks.size, p["K"], el)
+
+
+def cpu_baseline(sc, seconds, mean_request_steps):
+    """The FP64 oracle, unchanged, on the host cores.  Headline: full
+    warm-started iterations of the benchmark workload for `seconds` on every
+    core.  Rows: the plain, stress and paper-shaped workloads on every core
+    and on one (bounded samples: full iterations where they take a fraction
+    of a second, else the rollouts of a subset of the samples), and the
+    request rate of the served fleet's mix that the all-core rate implies."""
+    from oracle import oracle as O
+    from paper_2308_01654_amd import scenes
+    p = sc["params"]
+    n_all = O.max_threads()
+    value, what = _oracle_iterations(O, sc, seconds)
+    out = dict(value=value, unit="rollout-steps/s", cores=n_all, kind="oracle",
+               sample="%s of the K=%d, T=%d sine-lane instance (warm-started FP64 oracle)"
+                      % (what, p["K"], p["T"]),
+               cpu_model=cpu_model(), rows=[])
+    cases = [("plain K=1024 T=50", scenes.c0(), "iter", 1.0, 1.0),
+             ("sine lane K=8192 T=100", sc, "roll", None, 2048),
+             ("stress K=262144 T=200", scenes.c4(), "roll", 16384, 512),
+             ("paper Table I shape K=2560 T=16", scenes.paper_table1(), "iter", 1.0, 1.0)]
+    try:
+        for threads in (n_all, 1):
+            O.set_threads(threads)
+            for name, c, kind, a_all, a_one in cases:
+                arg = a_all if threads == n_all else a_one
+                if arg is None:
+                    rate, what = value, "the headline sample"
+                elif kind == "iter":
+                    rate, what = _oracle_iterations(O, c, arg)
+                else:
+                    rate, what = _oracle_rollouts(O, c, arg)
+                out["rows"].append(dict(workload=name, threads=threads,
+                                        rollout_steps_per_s=round(rate, 1), sample=what))
+    finally:
+        O.set_threads(n_all)
+    out["served_mix_requests_per_s"] = round(value / mean_request_steps, 1)
+    out["served_mix_mean_steps_per_request"] = mean_request_steps
+    return out
+
+
+def workload_rows(steps=20):
+    """Iteration time of the other workloads on the GPU (library's launch
+    shape, HIP events, resident scenes): the plain single iteration, the
+    stress instance, the paper's Table I shape, and the share of one GPU in
+    an eight-GPU split of a stress-sized instance (K = 32768 of 262144)."""
+    from paper_2308_01654_amd import scenes
+    rows = []
+    cases = [("plain K=1024 T=50", scenes.c0()), ("stress K=262144 T=200", scenes.c4()),
+             ("paper Table I shape K=2560 T=16", scenes.paper_table1()),
+             ("one GPU's share of the stress instance, K=32768 T=200", scenes.c4(K=32768))]
+    for name, sc in cases:
+        p = sc["params"]
+        F = flops_per_rollout_step(len(sc["waypoints"]), len(sc["circles"]), len(p["ego_off"]))
+        ms = _iteration_ms(p, sc["x0"], sc["waypoints"], sc["circles"], 3, steps)
+        rate = p["K"] * p["T"] / (ms * 1e-3)
+        rows.append(dict(workload=name, iteration_ms=ms, rollout_steps_per_s=round(rate, 1),
+                         full_scan_equivalent_tflops=round(F * rate / 1e12, 2)))
+    return rows
 
 
 def probe(steps):
@@ -259,39 +357,63 @@ def c3_load(n_vehicles, duration_s, pool_size=512, seed=33):
     return vehicles, pool, vid, x0, sidx, arr, steps
 
 
-def served(n_vehicles=1000, duration_s=5.0, plain_duration_s=1.0, warmup_s=1.0):
-    """p50/p99/p99.9 replan latency of the continuous-batching server and of
-    the plain one-at-a-time path under the same open-loop load.  The load
-    runs warmup_s + duration seconds without a break; requests arriving in
-    the first warmup_s seconds (first launches of every kernel variant,
-    arena growth) are left out of the statistics."""
+def _replay(mode, n_vehicles, duration_s, warmup_s, deadline_ms=50.0):
+    """One open-loop run of the fleet load on the served (continuous
+    batching) or plain (one request at a time) path; statistics over the
+    requests that arrive after the first warmup_s seconds."""
     from paper_2308_01654_amd import mppi
+    vehicles, pool, vid, x0, sidx, arr, steps = c3_load(n_vehicles, warmup_s + duration_s)
+    srv = mppi.Server(hbm_budget_bytes=8 << 30, n_streams=3, max_batch=512,
+                      plain=(mode == "plain"), deadline_ms=deadline_ms)
+    try:
+        vids = [srv.add_vehicle(p) for p in vehicles]
+        t0 = time.perf_counter()
+        lat = srv.replay([vids[v] for v in vid], x0, sidx, pool, arr)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    finally:
+        srv.close()
+    meas = arr >= np.uint64(int(warmup_s * 1e9))
+    ok = np.isfinite(lat) & meas
+    done = np.isfinite(lat)
+    return dict(
+        path=mode, vehicles=n_vehicles, requests=int(meas.sum()), warmup_s=warmup_s,
+        measured_s=duration_s, offered_rps=round(int(meas.sum()) / duration_s, 1),
+        completed_rps=round(int(done.sum()) / wall, 1), wall_s=round(wall, 3),
+        p50=round(float(np.percentile(lat[ok], 50)), 3),
+        p99=round(float(np.percentile(lat[ok], 99)), 3),
+        p999=round(float(np.percentile(lat[ok], 99.9)), 3), max=round(float(lat[ok].max()), 3),
+        deadline_ms=deadline_ms, deadline_misses=int(np.sum(lat[ok] > deadline_ms)),
+        rollout_steps_per_s=round(float(steps[done].sum()) / wall, 1),
+        mean_batch=round(st["mean_batch"], 2), hbm_peak_bytes=int(st["hbm_peak_bytes"]),
+        rejected=int(st["rejected"]))
+
+
+def served(n_vehicles=1000, duration_s=10.0, plain_duration_s=3.0, warmup_s=2.0):
+    """p50/p99/p99.9 replan latency of the continuous-batching server and of
+    the plain one-at-a-time path under the same open-loop 20 Hz fleet load
+    (1000 vehicles, ~20k requests/s).  The load runs warmup_s + duration
+    seconds without a break; requests arriving in the first warmup_s
+    seconds (first launches of every kernel variant, arena growth) are left
+    out of the statistics.  The plain path cannot keep up with this load:
+    its queue grows for as long as the run lasts, and its completed rate is
+    its capacity."""
     out = {}
     for mode, dur in (("served", duration_s), ("plain", plain_duration_s)):
-        vehicles, pool, vid, x0, sidx, arr, steps = c3_load(n_vehicles, warmup_s + dur)
-        srv = mppi.Server(hbm_budget_bytes=8 << 30, n_streams=3, max_batch=512,
-                          plain=(mode == "plain"))
-        try:
-            vids = [srv.add_vehicle(p) for p in vehicles]
-            t0 = time.perf_counter()
-            lat = srv.replay([vids[v] for v in vid], x0, sidx, pool, arr)
-            wall = time.perf_counter() - t0
-            st = srv.stats()
-        finally:
-            srv.close()
-        meas = arr >= np.uint64(int(warmup_s * 1e9))
-        ok = np.isfinite(lat) & meas
-        out[mode] = dict(
-            vehicles=n_vehicles, requests=int(meas.sum()), warmup_s=warmup_s,
-            offered_rps=round(int(meas.sum()) / dur, 1),
-            completed_rps=round(int(np.isfinite(lat).sum()) / wall, 1), wall_s=round(wall, 3),
-            p50=round(float(np.percentile(lat[ok], 50)), 3),
-            p99=round(float(np.percentile(lat[ok], 99)), 3),
-            p999=round(float(np.percentile(lat[ok], 99.9)), 3), max=round(float(lat[ok].max()), 3),
-            rollout_steps_per_s=round(float(steps[np.isfinite(lat)].sum()) / wall, 1),
-            mean_batch=round(st["mean_batch"], 2), hbm_peak_bytes=int(st["hbm_peak_bytes"]),
-            rejected=int(st["rejected"]))
+        r = _replay(mode, n_vehicles, dur, warmup_s)
+        r.pop("path")
+        out[mode] = r
     return out
+
+
+def serve_sweep(seconds, warmup_s=5.0):
+    """Served path at 1000, 2000 and 4000 vehicles (offered ~20k, 40k and
+    80k requests/s) and the plain path at 250, 500, 750 and 1000 vehicles
+    (~5k to 20k requests/s): one JSON line per run."""
+    for mode, fleets in (("served", (1000, 2000, 4000)), ("plain", (250, 500, 750, 1000))):
+        for n in fleets:
+            r = _replay(mode, n, seconds, warmup_s)
+            print(json.dumps(r), flush=True)
 
 
 def main(argv=None):
@@ -306,9 +428,12 @@ def main(argv=None):
     ap.add_argument("--probe", type=int, default=0, metavar="N",
                     help="only dispatch the counter-calibration copy and N iterations")
     ap.add_argument("--sweep", action="store_true", help="only run the lanes-per-sample sweep")
-    ap.add_argument("--served-seconds", type=float, default=5.0,
+    ap.add_argument("--served-seconds", type=float, default=10.0,
                     help="duration of the served load (0 skips the served comparison)")
-    ap.add_argument("--plain-seconds", type=float, default=1.0)
+    ap.add_argument("--plain-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-sweep", action="store_true",
+                    help="only run the served and plain paths at several offered loads")
+    ap.add_argument("--sweep-seconds", type=float, default=60.0)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the smoothing, trajectory, per-step, paper-scenario and batched timings")
     args = ap.parse_args(argv)
@@ -322,6 +447,9 @@ def main(argv=None):
         return 0
     if args.sweep:
         sweep()
+        return 0
+    if args.serve_sweep:
+        serve_sweep(args.sweep_seconds)
         return 0
 
     from paper_2308_01654_amd import mppi, scenes
@@ -367,9 +495,25 @@ def main(argv=None):
     iter_ms = ms_per_step
     F = flops_per_rollout_step(n_wp, n_c, n_ego)
     achieved = F * K * T / (kern_ms * 1e-3) / 1e12
+    counters = load_counters()
+    executed = None
+    if counters:
+        ef = counters.get("executed_fp32_flop_per_dispatch")
+        pw = counters.get("per_wave", {})
+        executed = dict(
+            source="profiles/counters_iteration_c1.json (rocprofv3 SQ counters, one dispatch)",
+            fp32_tflops=round(ef / (kern_ms * 1e-3) / 1e12, 3) if ef else None,
+            fp32_frac_of_157_3=round(ef / (kern_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4) if ef else None,
+            algorithmic_over_executed_flops=round(F * K * T / ef, 2) if ef else None,
+            valu_instructions_per_wave=round(pw.get("SQ_INSTS_VALU", 0.0), 1),
+            salu_instructions_per_wave=round(pw.get("SQ_INSTS_SALU", 0.0), 1),
+            wave_quad_cycles=round(pw.get("SQ_WAVE_CYCLES", 0.0), 1),
+            waiting_quad_cycles=round(pw.get("SQ_WAIT_INST_ANY", 0.0), 1))
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS,
                     unit="TFLOP/s", frac=round(achieved / PEAK_FP32_TFLOPS, 4),
-                    traffic=load_traffic(K * T),
+                    traffic=load_traffic(K * T), executed=executed,
+                    achieved_counts="algorithmic flops of full scans (the kernel culls them "
+                                    "exactly; executed holds what the hardware counted)",
                     kernel="k_batch<G,NE,M5> (sampling, rollouts, costs, tile partials)",
                     kernel_ms=round(kern_ms, 5), iteration_ms=round(iter_ms, 5),
                     combine_ms=round(iter_ms - kern_ms, 5), flops_per_rollout_step=F,
@@ -391,11 +535,12 @@ def main(argv=None):
     pl.sync()
     pcie_value = K * T * 50 / (time.perf_counter() - a)
     pl.close()
-    smooth = bat = None
+    smooth = bat = rows = None
     if not args.no_extras:
         smooth = alg1_output(p, x0, wp, circ, args.warmup, args.steps)
         smooth.update(paper_cost_kernels())
         bat = batched()
+        rows = workload_rows()
 
     out = {
         "metric": METRIC,
@@ -421,6 +566,7 @@ def main(argv=None):
         "host_staged_value": round(pcie_value, 1),
         "alg1_output": smooth,
         "batched": bat,
+        "workloads": rows,
     }
     if args.served_seconds > 0:
         sv = served(duration_s=args.served_seconds, plain_duration_s=args.plain_seconds)
@@ -430,7 +576,7 @@ def main(argv=None):
                                   "plain_p999": sv["plain"]["p999"]})
         out["served"] = sv
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds, 358400)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -276,6 +276,8 @@ typedef struct mppi_server_config {
     int32_t max_batch;         /* requests per launch, 1..4096                        */
     int32_t queue_cap;         /* queued + in-flight requests before MPPI_E_BUSY      */
     int32_t plain;             /* 1: one request at a time, no batching, no overlap   */
+    double deadline_ms;        /* replanning period for the miss count (50 ms at the
+                                  20 Hz of Sec. IV-D); 0: no count                    */
 } mppi_server_config;
 
 typedef struct mppi_server_stats {
@@ -285,6 +287,8 @@ typedef struct mppi_server_stats {
     double mean_ms, p50_ms, p99_ms, p999_ms, max_ms; /* completion - arrival          */
     uint64_t hbm_peak_bytes;   /* peak scratch in use                                 */
     int32_t max_queue;         /* peak queued + in-flight requests                    */
+    uint64_t deadline_misses;  /* completed requests whose latency exceeded
+                                  deadline_ms                                         */
 } mppi_server_stats;
 
 /* Open-loop load: request i of vehicle vid[i] from state x0[i] in scene

@@ -116,6 +116,12 @@ enum { ORC_OK = 0, ORC_E_INVALID = -1, ORC_E_NONFINITE = -4 };
 
 /* Threads the parallel loops of this oracle use. */
 int orc_max_threads(void) { return omp_get_max_threads(); }
+/* Thread count of the parallel loops over samples (the host baseline times
+ * the oracle on all cores and on one); n < 1 leaves it unchanged. */
+void orc_set_threads(int n)
+{
+    if (n >= 1) omp_set_num_threads(n);
+}
 
 /* ------------------------------------------------------------------------
  * Philox4x32-10 (Salmon et al., SC'11, Section 4.2 / Table 2 constants).

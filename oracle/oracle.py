@@ -72,6 +72,7 @@ def lib():
             u32p = ctypes.POINTER(ctypes.c_uint32)
             L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
             L.orc_max_threads.restype = ctypes.c_int
+            L.orc_set_threads.argtypes = [ctypes.c_int]
             L.orc_philox_batch.argtypes = [u32p, ctypes.c_int64, u32p, u32p]
             L.orc_uniform.argtypes = [ctypes.c_uint32]
             L.orc_uniform.restype = ctypes.c_double
@@ -163,6 +164,11 @@ def philox_batch(ctrs, key):
 
 def max_threads() -> int:
     return int(lib().orc_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops over samples."""
+    lib().orc_set_threads(int(n))
 
 
 def uniform(r: int) -> float:

@@ -384,9 +384,11 @@ mppi_status mppi_server_create(const mppi_server_config* cfg, mppi_server_t** ou
     if (!cfg || !out) return fail(MPPI_E_INVALID, "config and out must not be NULL");
     *out = nullptr;
     if (cfg->hbm_budget_bytes < 4096 || cfg->n_streams < 1 || cfg->n_streams > 8 ||
-        cfg->max_batch < 1 || cfg->max_batch > 4096 || cfg->queue_cap < 1)
+        cfg->max_batch < 1 || cfg->max_batch > 4096 || cfg->queue_cap < 1 ||
+        !(cfg->deadline_ms >= 0.0) || !isfinite(cfg->deadline_ms))
         return fail(MPPI_E_INVALID,
-                    "budget >= 4096, 1 <= n_streams <= 8, 1 <= max_batch <= 4096, queue_cap >= 1");
+                    "budget >= 4096, 1 <= n_streams <= 8, 1 <= max_batch <= 4096, queue_cap >= 1, "
+                    "finite deadline_ms >= 0");
     mppi_server* srv = new (std::nothrow) mppi_server();
     if (!srv) return fail(MPPI_E_NOMEM, "host allocation failed");
     srv->cfg = *cfg;
@@ -562,6 +564,9 @@ mppi_status mppi_server_get_stats(mppi_server_t* srv, mppi_server_stats* out)
         out->p99_ms = pct(0.99);
         out->p999_ms = pct(0.999);
         out->max_ms = lat.back();
+        if (srv->cfg.deadline_ms > 0.0)
+            out->deadline_misses = (uint64_t)(lat.end() - std::upper_bound(lat.begin(), lat.end(),
+                                                                            srv->cfg.deadline_ms));
     }
     return MPPI_OK;
 }

@@ -82,6 +82,7 @@ class ServerConfig(ctypes.Structure):
     _fields_ = [
         ("hbm_budget_bytes", ctypes.c_uint64), ("n_streams", ctypes.c_int32),
         ("max_batch", ctypes.c_int32), ("queue_cap", ctypes.c_int32), ("plain", ctypes.c_int32),
+        ("deadline_ms", ctypes.c_double),
     ]
 
 
@@ -93,6 +94,7 @@ class ServerStats(ctypes.Structure):
         ("mean_ms", ctypes.c_double), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
         ("p999_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
         ("hbm_peak_bytes", ctypes.c_uint64), ("max_queue", ctypes.c_int32),
+        ("deadline_misses", ctypes.c_uint64),
     ]
 
 
@@ -451,9 +453,9 @@ class Server:
     """Continuous-batching replanning server (mppi_server_* of the C ABI)."""
 
     def __init__(self, hbm_budget_bytes=2 << 30, n_streams=3, max_batch=256, queue_cap=1 << 20,
-                 plain=False):
+                 plain=False, deadline_ms=50.0):
         c = ServerConfig(int(hbm_budget_bytes), int(n_streams), int(max_batch), int(queue_cap),
-                         1 if plain else 0)
+                         1 if plain else 0, float(deadline_ms))
         h = _vp()
         check(load().mppi_server_create(ctypes.byref(c), ctypes.byref(h)))
         self.h = h

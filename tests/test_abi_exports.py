@@ -72,7 +72,9 @@ def test_invalid_server_config_rejected_without_device():
     L = mppi.load()
     import ctypes
     h = ctypes.c_void_p()
-    for cfg in (mppi.ServerConfig(0, 1, 1, 1, 0), mppi.ServerConfig(1 << 20, 0, 1, 1, 0),
-                mppi.ServerConfig(1 << 20, 1, 0, 1, 0), mppi.ServerConfig(1 << 20, 9, 1, 1, 0)):
+    for cfg in (mppi.ServerConfig(0, 1, 1, 1, 0, 50.0), mppi.ServerConfig(1 << 20, 0, 1, 1, 0, 50.0),
+                mppi.ServerConfig(1 << 20, 1, 0, 1, 0, 50.0), mppi.ServerConfig(1 << 20, 9, 1, 1, 0, 50.0),
+                mppi.ServerConfig(1 << 20, 1, 1, 1, 0, -1.0),
+                mppi.ServerConfig(1 << 20, 1, 1, 1, 0, float("nan"))):
         assert L.mppi_server_create(ctypes.byref(cfg), ctypes.byref(h)) == mppi.E_INVALID
         assert not h.value

@@ -179,3 +179,16 @@ def test_open_loop_replay_small():
     _say("replay", len(lat), "p50 %.3f p99 %.3f ms" % (np.percentile(lat, 50), np.percentile(lat, 99)), st)
     assert np.all(np.isfinite(lat)) and np.all(lat > 0)
     assert st["completed"] == len(lat) and st["failed"] == 0
+
+
+def test_deadline_miss_count():
+    """The stats count the completed requests whose latency exceeded the
+    configured replanning period: every request with a 1 ns period, none
+    with a period of an hour, and no count with 0."""
+    mppi = _mppi()
+    vehs = _fleet(4, 2, seed=3)
+    for deadline, expect in ((1e-6, "all"), (3.6e6, 0), (0.0, 0)):
+        _, st = _serve(mppi, vehs, n_streams=2, max_batch=8, deadline_ms=deadline)
+        _say("deadline", deadline, st["completed"], st["deadline_misses"])
+        assert st["completed"] == 8
+        assert st["deadline_misses"] == (st["completed"] if expect == "all" else expect)
