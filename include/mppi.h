@@ -242,6 +242,12 @@ mppi_status mppi_get_iter_stats(mppi_t* h, mppi_iter_stats* out);
  * let the library pick from its tuning table. */
 mppi_status mppi_set_lanes_per_sample(mppi_t* h, int32_t lanes);
 
+/* LDS copy of each tile's applied perturbations for its weighted sums:
+ * -1 (default) the tuning table's choice for the instance's shape, 0 never
+ * (the sums read them back from L2), 1 whenever the copy fits the LDS.
+ * Results are identical bit for bit. */
+mppi_status mppi_set_staging(mppi_t* h, int32_t mode);
+
 /* Wave-level culling of the two scans of the stage cost (on by default):
  * waypoint chunks and obstacle circles that provably cannot change any
  * lane's tracking minimum or obstacle cost are skipped.  Results are

@@ -1,10 +1,12 @@
-"""Autotuner of the iteration kernel's launch shape (lanes per sample).
+"""Autotuner of the iteration kernel's launch shape.
 
 For every shape bucket -- K in powers of two, T buckets (<=16, <=32, <=64,
 <=128, <=256, >256) and circle-count buckets (0, <=16, <=64, <=256, >256) -- it runs
 a representative sine-lane instance with every lanes-per-sample shape
-(1, 2, 4, 8, 16), times whole iterations with HIP events, and writes the
-fastest shape as a line "k_log2 t_bucket c_bucket lanes" of ``tuning.txt``.
+(1, 2, 4, 8, 16) and, for the fastest of them, with and without the tiles'
+LDS copy of their perturbations, times whole iterations with HIP events, and
+writes the fastest pair as a line "k_log2 t_bucket c_bucket lanes stage" of
+``tuning.txt``.
 The library reads that file at its first launch (next to libmppi.so, or the
 file named by MPPI_TUNING_FILE).  A bucket's choice depends only on the
 instance's own shape, so an instance computes the same bits alone and inside
@@ -39,13 +41,14 @@ def shape_scene(K, T, n_c):
                 circles=scenes.sine_circles(rng, n_c))
 
 
-def time_shape(sc, lanes, reps, rounds=3):
+def time_shape(sc, lanes, reps, rounds=3, stage=1):
     """Best of `rounds` HIP-event timings of `reps` back-to-back iterations
     (the best filters out the other work of a shared GPU)."""
     from paper_2308_01654_amd import mppi
     from paper_2308_01654_amd.hip_events import time_steps
     pl = mppi.Planner(sc["params"], lanes=lanes)
     try:
+        pl.set_staging(stage)
         pl.set_scene(sc["x0"], sc["waypoints"], sc["circles"])
         pl.step_resident(sc["x0"])
         pl.sync()
@@ -59,13 +62,14 @@ def main(argv=None):
     ap.add_argument("--out", default=os.path.join(HERE, "tuning.txt"))
     ap.add_argument("--k-min", type=int, default=10)
     ap.add_argument("--k-max", type=int, default=18)
-    ap.add_argument("--t-buckets", default="0,1,2,3,4")
+    ap.add_argument("--t-buckets", default="0,1,2,3,4,5")
     ap.add_argument("--c-buckets", default="0,1,2,3,4")
     args = ap.parse_args(argv)
-    lines = ["# lanes-per-sample tuning table of the MPPI iteration kernel",
+    lines = ["# launch-shape tuning table of the MPPI iteration kernel",
              "# written by: python -m paper_2308_01654_amd.autotune (HIP-event iteration time, "
-             "best of 3 rounds, fastest of lanes 1/2/4/8/16)",
-             "# columns: k_log2 t_bucket c_bucket lanes   (t: <=16,<=32,<=64,<=128,<=256,>256; "
+             "best of 3 rounds, fastest of lanes 1/2/4/8/16, then LDS staging of the "
+             "perturbations on (1) or off (0) at that shape)",
+             "# columns: k_log2 t_bucket c_bucket lanes stage   (t: <=16,<=32,<=64,<=128,<=256,>256; "
              "c: 0,<=16,<=64,<=256,>256)"]
     t0 = time.time()
     for kb in range(args.k_min, args.k_max + 1):
@@ -77,10 +81,13 @@ def main(argv=None):
                 reps = 20 if K * T < 2_000_000 else 3
                 times = {g: time_shape(sc, g, reps) for g in LANES if g <= T}
                 best = min(times, key=times.get)
-                lines.append("%d %d %d %d" % (kb, tb, cb, best))
+                off = time_shape(sc, best, reps, stage=0)
+                stage = 0 if off < times[best] else 1
+                lines.append("%d %d %d %d %d" % (kb, tb, cb, best, stage))
                 print("K=%-7d T=%-4d circles=%-4d " % (K, T, C_REPS[cb]) +
                       " ".join("g%d=%.4fms" % (g, ms) for g, ms in times.items()) +
-                      "  -> %d  (%.0fs)" % (best, time.time() - t0), flush=True)
+                      " g%d-unstaged=%.4fms" % (best, off) +
+                      "  -> %d %d  (%.0fs)" % (best, stage, time.time() - t0), flush=True)
     with open(args.out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("wrote", args.out, flush=True)

@@ -187,6 +187,7 @@ void write_scene(unsigned char* dst, const SceneLayout& L, const mppi_config& c,
 
 struct TuneEntry {
     int k, t, c, lanes;
+    int stage;  // 1: the tiles may keep their perturbations in LDS; 0: read back from L2
 };
 static std::vector<TuneEntry> g_tune;
 static std::once_flag g_tune_once;
@@ -223,7 +224,9 @@ static void load_tuning()
     while (fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
         TuneEntry t;
-        if (sscanf(line, "%d %d %d %d", &t.k, &t.t, &t.c, &t.lanes) == 4 &&
+        t.stage = 1;  // the optional fifth column
+        const int n = sscanf(line, "%d %d %d %d %d", &t.k, &t.t, &t.c, &t.lanes, &t.stage);
+        if (n >= 4 && (t.stage == 0 || t.stage == 1) &&
             (t.lanes == 1 || t.lanes == 2 || t.lanes == 4 || t.lanes == 8 || t.lanes == 16))
             g_tune.push_back(t);
     }
@@ -249,6 +252,18 @@ int auto_lanes(const mppi_config& c, int n_c)
     int g = best ? best->lanes : heuristic_lanes(c);
     while (g > 1 && g > c.T) g >>= 1;
     return g;
+}
+
+// The tuning table's staging choice for the bucket auto_lanes uses (1 when
+// the table has no such column or no bucket).
+int auto_stage(const mppi_config& c, int n_c)
+{
+    std::call_once(g_tune_once, load_tuning);
+    const int kb = k_bucket(c.K), tb = t_bucket(c.T), cb = c_bucket(n_c);
+    const TuneEntry* best = nullptr;
+    for (const TuneEntry& e : g_tune)
+        if (e.t == tb && e.c == cb && (!best || abs(e.k - kb) < abs(best->k - kb))) best = &e;
+    return best ? best->stage : 1;
 }
 
 // ---- profiling --------------------------------------------------------------------
@@ -423,11 +438,16 @@ mppi_status handle_create(const mppi_config* cfg, void* hip_stream, bool with_sc
 // Descriptor of one iteration of handle h from state x0 on the scene at
 // `scene` (device), staged relative to `origin`.
 // Whether the tiles of d keep their perturbations in LDS (see kLdsShared).
-void choose_eps_stage(InstDesc& d, bool alone)
+int stage_allowed(const mppi_t* h, int n_c)
+{
+    return h->stage_req >= 0 ? h->stage_req : auto_stage(h->cfg, n_c);
+}
+
+void choose_eps_stage(InstDesc& d, bool alone, int allowed)
 {
     const LdsLayout L = lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes, 1, d.per_step, !d.cull);
-    d.eps_stage = L.eps_staged && (L.total <= kLdsShared ||
-                                   (alone && d.n_tiles <= 512 && L.total <= kLdsAlone));
+    d.eps_stage = allowed && L.eps_staged &&
+                  (L.total <= kLdsShared || (alone && d.n_tiles <= 512 && L.total <= kLdsAlone));
 }
 
 void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double origin[2],
@@ -493,7 +513,7 @@ void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double or
     d.q = h->q;
     d.Stk = h->Stk;
     d.st = h->st;
-    choose_eps_stage(d, false);
+    choose_eps_stage(d, false, stage_allowed(h, n_c));
 }
 
 // ---- batched launches ---------------------------------------------------------------
@@ -813,7 +833,7 @@ mppi_status mppi_step_resident(mppi_t* h, const double x0[4])
         if (!isfinite(x0[i])) return fail(MPPI_E_INVALID, "x0[%d] is not finite", i);
     InstDesc d;
     fill_desc(d, h, x0, h->origin, h->scene, h->lay, h->n_wp, h->n_c, 0);
-    choose_eps_stage(d, true);
+    choose_eps_stage(d, true, stage_allowed(h, h->n_c));
     const size_t smem =
         lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes, d.eps_stage, d.per_step, !d.cull).total;
     hipEvent_t a = nullptr;
@@ -1062,6 +1082,15 @@ mppi_status mppi_set_lanes_per_sample(mppi_t* h, int32_t lanes)
     if (!(lanes == 0 || lanes == 1 || lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16))
         return fail(MPPI_E_INVALID, "lanes per sample must be 0, 1, 2, 4, 8 or 16");
     h->lanes_req = lanes;
+    return MPPI_OK;
+}
+
+mppi_status mppi_set_staging(mppi_t* h, int32_t mode)
+{
+    mppi_status s = usable(h);
+    if (s != MPPI_OK) return s;
+    if (mode < -1 || mode > 1) return fail(MPPI_E_INVALID, "staging mode must be -1, 0 or 1");
+    h->stage_req = mode;
     return MPPI_OK;
 }
 

@@ -69,6 +69,7 @@ struct mppi {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int lanes_req = 0;  // 0 = tuning table
+    int stage_req = -1; // -1 = tuning table, 0 = no LDS copy of the perturbations, 1 = when it fits
     int no_cull = 0;    // 1: full waypoint and circle scans
     int last_lanes = 0;
     mppi_status sticky = MPPI_OK;
@@ -144,7 +145,11 @@ void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double or
 // Whether the tiles of d keep their perturbations in LDS: within kLdsShared,
 // or within kLdsAlone for an instance launched alone (alone = true) with at
 // most 512 tiles.
-void choose_eps_stage(InstDesc& d, bool alone);
+void choose_eps_stage(InstDesc& d, bool alone, int allowed);
+// Whether h's tiles may keep their perturbations in LDS (its own setting or
+// the tuning table's choice for its shape).
+int stage_allowed(const mppi_t* h, int n_c);
+int auto_stage(const mppi_config& c, int n_c);
 mppi_status ws_create(BatchWs** out);
 void ws_destroy(BatchWs* b);
 // Create a handle; with_scratch = false leaves S/eps/partials/scales/scene

@@ -181,7 +181,7 @@ extern "C" mppi_status mppi_step_static(const mppi_config* cfg, const double x0[
 
     InstDesc d;
     fill_desc(d, &inst, x0, origin, inst.scene, lay, n_wp, n_c, 0);
-    choose_eps_stage(d, true);  // launched alone, as mppi_step_resident launches it
+    choose_eps_stage(d, true, stage_allowed(&inst, n_c));  // launched alone, as mppi_step_resident
     const size_t smem =
         lds_layout(d.n_wp, d.n_c, d.T, kBlock / d.lanes, d.eps_stage, d.per_step, !d.cull).total;
     unsigned int* tickets = reinterpret_cast<unsigned int*>(

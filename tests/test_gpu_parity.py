@@ -430,3 +430,22 @@ def test_varying_reference_speed_and_repeated_waypoints(lanes, n_c):
             outs.append((g["S"], g["eps"], g["U"]))
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name,lanes", [("c1", 16), ("c0", 4), ("tiny", 1)])
+def test_staging_choice_bit_identical(name, lanes):
+    """The tiles' LDS copy of their perturbations (tuned per shape) and the
+    read-back from L2 give the same bits: the weighted sums run in the same
+    order over the same values."""
+    mppi = _mppi()
+    sc = scenes.tiny(K=3000, T=45, n_c=40, seed=5) if name == "tiny" else scenes.by_name(name)
+    p = sc["params"]
+    outs = []
+    for stage in (1, 0):
+        with mppi.Planner(p, lanes=lanes) as pl:
+            pl.set_staging(stage)
+            for _ in range(2):
+                pl.step(sc["x0"], sc["waypoints"], sc["circles"])
+            outs.append((pl.costs(), pl.noise(), pl.controls(), pl.weights()))
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
