@@ -18,8 +18,9 @@ workloads' iteration times, and the FP64 CPU oracle timed on the host on
 bounded samples of the same workloads (all cores and one core).
 
 Usage: python bench.py [--gpus 1] [--steps 200] [--warmup 20]
-       python bench.py --serve-sweep [--sweep-seconds 60]   (served and plain
-       paths at several offered loads; one JSON line per run)
+       python bench.py --serve-sweep [--sweep-seconds 60] [--served-fleets
+           1000,2000,4000] [--plain-fleets 250,500,750,1000]   (served and
+           plain paths at several offered loads; one JSON line per run)
 """
 from __future__ import annotations
 
@@ -406,11 +407,12 @@ def served(n_vehicles=1000, duration_s=10.0, plain_duration_s=3.0, warmup_s=2.0)
     return out
 
 
-def serve_sweep(seconds, warmup_s=5.0):
+def serve_sweep(seconds, warmup_s=5.0, served_fleets=(1000, 2000, 4000),
+                plain_fleets=(250, 500, 750, 1000)):
     """Served path at 1000, 2000 and 4000 vehicles (offered ~20k, 40k and
     80k requests/s) and the plain path at 250, 500, 750 and 1000 vehicles
-    (~5k to 20k requests/s): one JSON line per run."""
-    for mode, fleets in (("served", (1000, 2000, 4000)), ("plain", (250, 500, 750, 1000))):
+    (~5k to 20k requests/s) by default: one JSON line per run."""
+    for mode, fleets in (("served", served_fleets), ("plain", plain_fleets)):
         for n in fleets:
             r = _replay(mode, n, seconds, warmup_s)
             print(json.dumps(r), flush=True)
@@ -434,6 +436,10 @@ def main(argv=None):
     ap.add_argument("--serve-sweep", action="store_true",
                     help="only run the served and plain paths at several offered loads")
     ap.add_argument("--sweep-seconds", type=float, default=60.0)
+    ap.add_argument("--served-fleets", default="1000,2000,4000",
+                    help="vehicle counts of the served runs of --serve-sweep (20 requests/s each)")
+    ap.add_argument("--plain-fleets", default="250,500,750,1000",
+                    help="vehicle counts of the plain runs of --serve-sweep")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the smoothing, trajectory, per-step, paper-scenario and batched timings")
     args = ap.parse_args(argv)
@@ -449,7 +455,9 @@ def main(argv=None):
         sweep()
         return 0
     if args.serve_sweep:
-        serve_sweep(args.sweep_seconds)
+        fl = lambda v: tuple(int(x) for x in v.split(",") if x)
+        serve_sweep(args.sweep_seconds, served_fleets=fl(args.served_fleets),
+                    plain_fleets=fl(args.plain_fleets))
         return 0
 
     from paper_2308_01654_amd import mppi, scenes

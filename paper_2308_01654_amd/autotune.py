@@ -72,6 +72,9 @@ def main(argv=None):
              "# columns: k_log2 t_bucket c_bucket lanes stage   (t: <=16,<=32,<=64,<=128,<=256,>256; "
              "c: 0,<=16,<=64,<=256,>256)"]
     t0 = time.time()
+    tmp = args.out + ".partial"
+    with open(tmp, "w") as f:  # rows are appended as they are measured
+        f.write("\n".join(lines) + "\n")
     for kb in range(args.k_min, args.k_max + 1):
         K = 1 << kb
         for tb in [int(v) for v in args.t_buckets.split(",")]:
@@ -84,12 +87,13 @@ def main(argv=None):
                 off = time_shape(sc, best, reps, stage=0)
                 stage = 0 if off < times[best] else 1
                 lines.append("%d %d %d %d %d" % (kb, tb, cb, best, stage))
+                with open(tmp, "a") as f:
+                    f.write(lines[-1] + "\n")
                 print("K=%-7d T=%-4d circles=%-4d " % (K, T, C_REPS[cb]) +
                       " ".join("g%d=%.4fms" % (g, ms) for g, ms in times.items()) +
                       " g%d-unstaged=%.4fms" % (best, off) +
                       "  -> %d %d  (%.0fs)" % (best, stage, time.time() - t0), flush=True)
-    with open(args.out, "w") as f:
-        f.write("\n".join(lines) + "\n")
+    os.replace(tmp, args.out)
     print("wrote", args.out, flush=True)
     return 0
 
