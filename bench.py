@@ -186,20 +186,36 @@ def workload_rows(steps=20):
     return rows
 
 
-def probe(steps):
-    """Dispatches for hardware-counter runs: a 256 MiB streaming copy (the
-    calibration reference, 3 dispatches), then `steps` warm-started
-    iterations of the benchmark workload."""
+def probe(steps, workload="c1"):
+    """Dispatches for hardware-counter and kernel-trace runs: a 256 MiB
+    streaming copy (the calibration reference, 3 dispatches), then `steps`
+    warm-started iterations of one workload: "c1" the sine-lane benchmark
+    instance, "c4" the stress instance, "c2" the 256 uneven instances of the
+    batched workload stepped by mppi_step_batch."""
     from paper_2308_01654_amd import mppi, scenes
     mppi.check(mppi.load().mppi_bench_copy(256 << 20, 3))
-    sc = scenes.c1()
-    pl = mppi.Planner(sc["params"])
-    pl.set_scene(sc["x0"], sc["waypoints"], sc["circles"])
-    for _ in range(steps):
-        pl.step_resident(sc["x0"])
-    pl.sync()
-    pl.close()
-    print("probe: copy calibration + %d iterations done" % steps, flush=True)
+    if workload == "c2":
+        insts = scenes.c2(256)
+        pls = [mppi.Planner(insts[0]["params"])]
+        st = pls[0].stream()
+        pls += [mppi.Planner(sc["params"], hip_stream=st) for sc in insts[1:]]
+        for pl, sc in zip(pls, insts):
+            pl.set_scene(sc["x0"], sc["waypoints"], sc["circles"])
+        x0s = [sc["x0"] for sc in insts]
+        for _ in range(steps):
+            mppi.step_batch(pls, x0s)
+        pls[0].sync()
+        for pl in reversed(pls):
+            pl.close()
+    else:
+        sc = scenes.c1() if workload == "c1" else scenes.by_name(workload)
+        pl = mppi.Planner(sc["params"])
+        pl.set_scene(sc["x0"], sc["waypoints"], sc["circles"])
+        for _ in range(steps):
+            pl.step_resident(sc["x0"])
+        pl.sync()
+        pl.close()
+    print("probe: copy calibration + %d iterations of %s done" % (steps, workload), flush=True)
 
 
 def sweep():
@@ -429,6 +445,8 @@ def main(argv=None):
     ap.add_argument("--latency-iters", type=int, default=200)
     ap.add_argument("--probe", type=int, default=0, metavar="N",
                     help="only dispatch the counter-calibration copy and N iterations")
+    ap.add_argument("--probe-workload", default="c1", choices=("c1", "c4", "c2", "paper_table1"),
+                    help="workload of --probe (sine lane, stress, batched, Table I shape)")
     ap.add_argument("--sweep", action="store_true", help="only run the lanes-per-sample sweep")
     ap.add_argument("--served-seconds", type=float, default=10.0,
                     help="duration of the served load (0 skips the served comparison)")
@@ -449,7 +467,7 @@ def main(argv=None):
         return 2
 
     if args.probe:
-        probe(args.probe)
+        probe(args.probe, args.probe_workload)
         return 0
     if args.sweep:
         sweep()

@@ -636,7 +636,7 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
     InstDesc* descs = reinterpret_cast<InstDesc*>(host + off_descs);
     long total = 0;
     size_t smem = 0;
-    int any_shift = 0, any_out = 0, combine_g = 0;
+    int any_shift = 0, any_out = 0, combine_g = 0, max_nodes = 0;
     for (int j = 0; j < n; ++j) {
         const int i = order[j];
         mppi_t* hi = hs[i];
@@ -667,6 +667,7 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
                                          descs[j].per_step, !descs[j].cull).total);
         any_shift |= sh;
         combine_g = std::max(combine_g, combine_groups(descs[j].T));
+        max_nodes = std::max(max_nodes, combine_nodes(descs[j].n_tiles, nullptr));
     }
     if (total > (1L << 30)) return fail(MPPI_E_INVALID, "batch too large");
     prefix[n] = (int)total;
@@ -686,6 +687,7 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
         hdr->cls_begin[kLaneClasses] = n;
     }
     const size_t smem_b = align_up(smem, 4096);
+    const int node_limit = max_nodes <= kDirectSmall ? kDirectSmall : kDirect;
     const int n_blocks = (int)pow2_at_least((size_t)n, 1);
     const int shift_blocks = any_shift ? n_blocks : 0;
     const int gather_blocks = (gather_dev && any_out) ? n_blocks : 0;
@@ -698,7 +700,7 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
                 e = launch_batch(kClassLanes[(c % 25) / 5], c % 5, c / 25, nullptr, hdr_dev, c,
                                  grids[c], smem_b, stream);
         if (e == hipSuccess && combine_g)
-            e = launch_combine(nullptr, hdr_dev, combine_g, n_blocks, stream);
+            e = launch_combine(nullptr, hdr_dev, combine_g, n_blocks, max_nodes, stream);
         if (e == hipSuccess && gather_blocks)
             e = launch_gather(hdr_dev, gather_blocks, gather_dev, slot_doubles, stream);
         return e;
@@ -713,7 +715,7 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
             if (g.bytes == bucket && g.smem == smem_b && g.buf == b &&
                 g.shift_blocks == shift_blocks && g.gather_blocks == gather_blocks &&
                 g.combine_g == combine_g && g.combine_y == (combine_g ? n_blocks : 0) &&
-                memcmp(g.grids, grids, sizeof grids) == 0)
+                g.combine_nodes == node_limit && memcmp(g.grids, grids, sizeof grids) == 0)
                 ge = &g;
         if (!ge) {
             if (ws->graphs.size() >= 64) {
@@ -730,6 +732,7 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
             g.gather_blocks = gather_blocks;
             g.combine_g = combine_g;
             g.combine_y = combine_g ? n_blocks : 0;
+            g.combine_nodes = node_limit;
             g.graph = nullptr;
             g.exec = nullptr;
             HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
@@ -843,7 +846,8 @@ mppi_status mppi_step_resident(mppi_t* h, const double x0[4])
     HIP_TRY(launch_batch(d.lanes, active_ego(d.n_ego, d.n_c), d.model, &d, nullptr, 0, d.n_tiles,
                          smem, h->stream));
     if ((s = record_end(h, 2, a2)) != MPPI_OK) return s;
-    HIP_TRY(launch_combine(&d, nullptr, combine_groups(d.T), 1, h->stream));
+    HIP_TRY(launch_combine(&d, nullptr, combine_groups(d.T), 1, combine_nodes(d.n_tiles, nullptr),
+                           h->stream));
     if ((s = record_end(h, 0, a)) != MPPI_OK) return s;
     h->last_lanes = d.lanes;
     h->stepped = true;

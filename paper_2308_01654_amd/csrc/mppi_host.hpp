@@ -21,6 +21,7 @@ struct GraphEntry {
     size_t bytes, smem;
     int grids[kLaneClasses];
     int buf, shift_blocks, gather_blocks, combine_g, combine_y;
+    int combine_nodes;  // the combine width's node limit (kDirectSmall or kDirect)
     hipGraph_t graph;
     hipGraphExec_t exec;
 };

@@ -63,7 +63,11 @@ inline __host__ __device__ size_t partial_doubles(int T, int per_step, size_t ti
 // remain.  Each group has a ticket; the member that completes it merges the
 // group into the row of its first tile.  The shape depends on the tile count
 // only.
-constexpr int kDirect = 512;
+constexpr int kDirect = 2048;
+// The combine kernel comes in two widths: up to kDirectSmall nodes (two heads
+// per thread) and up to kDirect (eight per thread); a launch takes the
+// narrowest that holds its largest instance.
+constexpr int kDirectSmall = 512;
 constexpr int kFanIn = 16;
 // Tickets sit on separate 128-byte lines so that groups finishing at the same
 // time do not contend for one line.
@@ -231,8 +235,9 @@ hipError_t launch_batch(int lanes, int ne, int model, const InstDesc* d0,
 // Combine of the tile rows of one instance (d0, hdr_dev == nullptr) or of
 // every instance of a batch (n_inst rows of the grid, groups = largest
 // combine_groups(T) among them).
+// max_nodes: the largest combine_nodes() among the instances.
 hipError_t launch_combine(const InstDesc* d0, const BatchHdr* hdr_dev, int groups, int n_inst,
-                          hipStream_t stream);
+                          int max_nodes, hipStream_t stream);
 
 // Ego circles that take part in the obstacle term of an instance.
 inline int active_ego(int n_ego, int n_c) { return n_c > 0 ? n_ego : 0; }

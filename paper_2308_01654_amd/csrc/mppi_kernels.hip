@@ -727,20 +727,30 @@ __device__ __forceinline__ double dpp_d(double v)
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
 }
 
+// A float64 value of one lane, wave-uniform (two lane reads into scalar
+// registers).
+__device__ __forceinline__ double lane_d(double v, int lane)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
 // Butterfly reductions over the 64 lanes of a wave (every lane active; every
 // lane ends with the same value): lane pairs and quad halves by quad
 // permutes; then, each quad holding one value, the half-row mirror pairs
 // each quad with the other quad of its half-row, and the row mirror each
-// half-row with the other half; rows by LDS permutes.
+// half-row with the other half; the four row values, read into scalar
+// registers, are combined as (row 0 with row 1) with (row 2 with row 3) --
+// the value the cross-row butterfly gives in every lane.
 __device__ __forceinline__ double wave_sum(double v)
 {
     v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
     v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
     v += dpp_d<0x141>(v);  // row_half_mirror
     v += dpp_d<0x140>(v);  // row_mirror
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    return v;
+    return (lane_d(v, 0) + lane_d(v, 16)) + (lane_d(v, 32) + lane_d(v, 48));
 }
 
 __device__ __forceinline__ double wave_min(double v)
@@ -749,9 +759,7 @@ __device__ __forceinline__ double wave_min(double v)
     v = fmin(v, dpp_d<0x4E>(v));
     v = fmin(v, dpp_d<0x141>(v));
     v = fmin(v, dpp_d<0x140>(v));
-    v = fmin(v, __shfl_xor(v, 16, 64));
-    v = fmin(v, __shfl_xor(v, 32, 64));
-    return v;
+    return fmin(fmin(lane_d(v, 0), lane_d(v, 16)), fmin(lane_d(v, 32), lane_d(v, 48)));
 }
 
 // M5: the 5-state model of eq. (5) -- the steering angle is part of the state
@@ -1304,7 +1312,7 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
 }
 
 // Combine (Alg. 1, the normaliser and the input update of eq.
-// (update-input)): merges the kDirect or fewer remaining node rows of one
+// (update-input)): merges the KH * kBlock (<= kDirect) or fewer remaining node rows of one
 // instance.  Every workgroup forms the global minimum m and the node scales
 // exp(-(m_b - m)/lambda), Z and Q itself (node order, fixed trees), then
 // updates kCombineSteps steps of U: U_t += N_t / Z with N_t summed over the
@@ -1313,11 +1321,12 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
 // (from the controls the iteration kernel kept) and writes its own steps
 // after eq. (sg).  Workgroup 0 records the statistics and bumps the
 // iteration counter.  Nothing is written if no sample cost is finite.
+template <int KH>
 __device__ void combine(const InstDesc& d, int cg)
 {
     extern __shared__ __align__(16) unsigned char csm[];
-    double* sc = reinterpret_cast<double*>(csm);   // [kDirect] node scales
-    double* red = sc + kDirect;                    // [64] reductions
+    double* sc = reinterpret_cast<double*>(csm);   // [KH * kBlock] node scales
+    double* red = sc + KH * kBlock;                // [64] reductions
     double* part = red + 64;                       // [kBlock] column partials
     double* un = part + kBlock;                    // [16] updated worked columns
     const int tid = threadIdx.x;
@@ -1337,10 +1346,10 @@ __device__ void combine(const InstDesc& d, int cg)
     const double* rows = d.partials;
     const double* heads = d.partials + partial_heads_offset(T, 0, d.n_tiles);
 
-    // One round trip: the node heads (kDirect / kBlock per thread, from the
+    // One round trip: the node heads (KH per thread, from the
     // compact head array) and the first sixteen nodes of this thread's chunk
     // of its worked column.
-    constexpr int kH = kDirect / kBlock;
+    constexpr int kH = KH;
     double mh[kH], zh[kH], qh[kH];
 #pragma unroll
     for (int r = 0; r < kH; ++r) {
@@ -1625,29 +1634,39 @@ __device__ void combine_per_step(const InstDesc& d, int cg)
     }
 }
 
-// One instance (d0, hdr == nullptr) or instance blockIdx.y of a batch.
+// One instance (d0, hdr == nullptr) or instance blockIdx.y of a batch; KH
+// node heads per thread.
+template <int KH>
 __global__ __launch_bounds__(kBlock) void k_combine(InstDesc d0, const BatchHdr* __restrict__ hdr)
 {
     if (!hdr) {
         if (d0.per_step) combine_per_step(d0, blockIdx.x);
-        else combine(d0, blockIdx.x);
+        else combine<KH>(d0, blockIdx.x);
         return;
     }
     if ((int)blockIdx.y >= hdr->n_inst) return;
     const InstDesc& d = reinterpret_cast<const InstDesc*>(
         reinterpret_cast<const unsigned char*>(hdr) + hdr->off_descs)[blockIdx.y];
     if (d.per_step) combine_per_step(d, blockIdx.x);
-    else combine(d, blockIdx.x);
+    else combine<KH>(d, blockIdx.x);
 }
 
 hipError_t launch_combine(const InstDesc* d0, const BatchHdr* hdr_dev, int groups, int n_inst,
-                          hipStream_t stream)
+                          int max_nodes, hipStream_t stream)
 {
     InstDesc zero;
     memset(&zero, 0, sizeof zero);
-    const size_t smem = sizeof(double) * (kDirect + 64 + 4 * kBlock + 8 + 16);
-    hipLaunchKernelGGL(k_combine, dim3(groups, n_inst), dim3(kBlock), smem, stream,
-                       d0 ? *d0 : zero, hdr_dev);
+    if (max_nodes <= kDirectSmall) {
+        constexpr int KH = kDirectSmall / kBlock;
+        const size_t smem = sizeof(double) * (KH * kBlock + 64 + 4 * kBlock + 8 + 16);
+        hipLaunchKernelGGL(k_combine<KH>, dim3(groups, n_inst), dim3(kBlock), smem, stream,
+                           d0 ? *d0 : zero, hdr_dev);
+    } else {
+        constexpr int KH = kDirect / kBlock;
+        const size_t smem = sizeof(double) * (KH * kBlock + 64 + 4 * kBlock + 8 + 16);
+        hipLaunchKernelGGL(k_combine<KH>, dim3(groups, n_inst), dim3(kBlock), smem, stream,
+                           d0 ? *d0 : zero, hdr_dev);
+    }
     return hipGetLastError();
 }
 

@@ -191,7 +191,8 @@ extern "C" mppi_status mppi_step_static(const mppi_config* cfg, const double x0[
     HIP_TRY(hipGetLastError());
     HIP_TRY(launch_batch(d.lanes, active_ego(d.n_ego, d.n_c), d.model, &d, nullptr, 0, d.n_tiles,
                          smem, stream));
-    HIP_TRY(launch_combine(&d, nullptr, combine_groups(d.T), 1, stream));
+    HIP_TRY(launch_combine(&d, nullptr, combine_groups(d.T), 1, combine_nodes(d.n_tiles, nullptr),
+                           stream));
     if (stats) {
         hipLaunchKernelGGL(k_static_end, dim3(1), dim3(64), 0, stream, inst.st, stats, d.lanes);
         HIP_TRY(hipGetLastError());

@@ -177,18 +177,20 @@ def test_initial_speed_above_cap_and_binding_cap(lanes):
                 P.assert_staged(P.staged(p, sc, g, n_iter=it))
 
 
-@pytest.mark.parametrize("K,smoothing", [(8192, 0), (8208, 0), (16 * 8193, 0), (8208, 1)])
+@pytest.mark.parametrize("K,smoothing", [(8192, 0), (8208, 0), (32768, 0), (32784, 0),
+                                         (16 * 32769, 0), (8208, 1), (32784, 1)])
 def test_combine_at_the_direct_limit_and_above(K, smoothing):
-    """512 tiles of 16 samples go to the combine kernel directly; 513 tiles
-    and 8193 tiles are first merged by one and two levels of the in-kernel
-    tree (down to 33 and 513 -> 33 nodes); with smoothing the combine reads
-    the controls the first tile kept."""
+    """Up to 512 tiles of 16 samples go to the narrow combine kernel, up to
+    2048 to the wide one (513 and 2048 tiles); 2049 tiles and 32769 tiles
+    are first merged by one and two levels of the in-kernel tree (down to
+    129 and 2049 -> 129 nodes); with smoothing the combine reads the
+    controls the first tile kept."""
     mppi = _mppi()
     sc = scenes.tiny(K=K, T=12, n_c=6, seed=K % 1000)
     p = dict(sc["params"], smoothing=smoothing)
     sc = dict(sc, params=p)
     _say("combine limit", K, smoothing)
-    ks = None if K <= 8208 else np.arange(0, K, 257)
+    ks = None if K <= 32784 else np.arange(0, K, 257)
     with mppi.Planner(p, lanes=16) as pl:
         pl.set_controls(np.tile([0.1, -0.02], (12, 1)))
         for it in range(2):
