@@ -461,6 +461,9 @@ void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double or
     d.n_c = n_c;
     d.lanes = h->lanes_req ? h->lanes_req : auto_lanes(c, n_c);
     d.n_tiles = (c.K + (kBlock / d.lanes) - 1) / (kBlock / d.lanes);
+    // two or more waves per SIMD (256 compute units x 4): the block-ordered
+    // wave priority pays; with fewer it only costs its instructions
+    d.wave_prio = (long)c.K * d.lanes >= 2L * 1024 * 64 ? 1 : 0;
     d.dt = (float)c.dt;
     d.inv_dt = (float)(1.0 / c.dt);
     d.inv_L = (float)(1.0 / c.wheelbase);

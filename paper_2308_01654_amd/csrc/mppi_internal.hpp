@@ -121,6 +121,7 @@ struct InstDesc {
     int coll_only;        // c_safe_dist only when d_obj <= 0
     int per_step;         // 1: weights from the cost-to-go per step
     int eps_stage;        // 1: tiles keep their perturbations in LDS (lds_layout)
+    int wave_prio;        // 1: wave priority falls with the block index (see iteration_tile)
     int model;            // 1: 5-state model of eq. (5), steering-rate control
     float steer0;         // its initial steering angle
     float ego_ext;        // max |ego_off|

@@ -839,6 +839,18 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     double ud_next = ld_g(d.U, 2 * min(max(t_first + r, 0), T - 1) + 1);
     int blk = 0;
     for (int t0 = t_first; t0 < T; t0 += G, ++blk) {
+        // Where two waves share a SIMD, the one in the earlier block issues
+        // first (wave priority 3 in blocks 0-1, 2 in 2-3, 1 in 4-5, then 0),
+        // so that the pair tends to finish together instead of leaving the
+        // later one to run alone at the end.
+        if (d.wave_prio) {
+            switch (min(blk >> 1, 3)) {
+            case 0: __builtin_amdgcn_s_setprio(3); break;
+            case 1: __builtin_amdgcn_s_setprio(2); break;
+            case 2: __builtin_amdgcn_s_setprio(1); break;
+            default: __builtin_amdgcn_s_setprio(0); break;
+            }
+        }
         const int tm = t0 + r;
         const float2 Um = make_float2((float)ua_next, (float)ud_next);
         if (t0 + G < T) {
@@ -1027,6 +1039,8 @@ __device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
     if (valid && r == 0) st_g(d.S, k, (float)Sd);
 
     // ---------------------------------------------------------------- phase 2
+    // the tile's last steps go first
+    if (d.wave_prio) __builtin_amdgcn_s_setprio(3);
     const int stride = partial_stride(T, d.per_step);
     double* part = d.partials + (size_t)tile * stride;
     const int n_valid = min(SPB, K - k_base);
