@@ -36,8 +36,8 @@ def _instances():
     return out
 
 
-def _run_alone(mppi, sc, iters, U0=None):
-    with mppi.Planner(sc["params"]) as pl:
+def _run_alone(mppi, sc, iters, U0=None, lanes=0):
+    with mppi.Planner(sc["params"], lanes=lanes) as pl:
         if U0 is not None:
             pl.set_controls(U0)
         res = []
@@ -177,4 +177,32 @@ def test_c2_full_draw_staged_parity():
         _say("c2 worst gates", worst)
     finally:
         for pl in reversed(pls):
+            pl.close()
+
+
+@pytest.mark.parametrize("K", [32784, 16 * 2049 + 5])
+def test_batched_tile_tree_equals_alone_tile_tree(K):
+    """Above 2048 tiles an instance stepped alone merges its tiles with one
+    k_merge launch per tree level, and inside a batch with the iteration
+    kernel's ticket tree: the same group merges in the same order, so the
+    same bits.  A small instance rides along in the batch."""
+    mppi = _mppi()
+    big = scenes.tiny(K=K, T=20, n_c=9, seed=K % 997)
+    small = scenes.c2_instance(0, SHAPES[0])
+    insts = [big, small]
+    alone = [_run_alone(mppi, big, 2, lanes=16), _run_alone(mppi, small, 2)]
+    lead = mppi.Planner(insts[0]["params"], lanes=16)
+    pls = [lead, mppi.Planner(small["params"], hip_stream=lead.stream())]
+    try:
+        x0s = np.array([sc["x0"] for sc in insts])
+        arrays = [(sc["waypoints"], sc["circles"]) for sc in insts]
+        for it in range(2):
+            mppi.step_batch(pls, x0s, arrays)
+            for k, pl in enumerate(pls):
+                U, S, w = alone[k][it]
+                assert np.array_equal(pl.costs(), S), (it, k)
+                assert np.array_equal(pl.weights(), w), (it, k)
+                assert np.array_equal(pl.controls(), U), (it, k)
+    finally:
+        for pl in pls:
             pl.close()
