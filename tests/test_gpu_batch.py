@@ -182,10 +182,10 @@ def test_c2_full_draw_staged_parity():
 
 @pytest.mark.parametrize("K", [32784, 16 * 2049 + 5])
 def test_batched_tile_tree_equals_alone_tile_tree(K):
-    """Above 2048 tiles an instance stepped alone merges its tiles with one
-    k_merge launch per tree level, and inside a batch with the iteration
-    kernel's ticket tree: the same group merges in the same order, so the
-    same bits.  A small instance rides along in the batch."""
+    """Above 2048 tiles the iteration kernel first merges an instance's
+    tiles by its ticket tree (one and two levels here), alone and inside a
+    batch: the groups depend on the instance only, so a batch with a small
+    instance alongside gives the big instance its alone bits."""
     mppi = _mppi()
     big = scenes.tiny(K=K, T=20, n_c=9, seed=K % 997)
     small = scenes.c2_instance(0, SHAPES[0])
