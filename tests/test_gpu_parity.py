@@ -88,6 +88,28 @@ def test_c0_staged_parity_all_launch_shapes(lanes):
         P.assert_staged(rep)
 
 
+@pytest.mark.parametrize("ego_off", [(0.0,), (0.0, 2.0), (0.0, 1.0, 2.7), (-0.5, 0.5, 1.5, 2.5),
+                                     (0.0, 1.35, 2.7)])
+@pytest.mark.parametrize("lanes", [4, 16])
+def test_ego_circle_sets(ego_off, lanes):
+    """One to four ego circles, equally spaced or not, on a scene where many
+    samples come close to the obstacles: staged gates and culled == full."""
+    mppi = _mppi()
+    sc = scenes.tiny(K=2048, T=40, n_c=48, seed=11)
+    p = dict(sc["params"], ego_off=ego_off)
+    sc = dict(sc, params=p)
+    _say("ego circles", ego_off, lanes)
+    outs = []
+    for cull in (1, 0):
+        with mppi.Planner(p, lanes=lanes) as pl:
+            pl.set_culling(cull)
+            g = P.gpu_step(pl, sc)
+            outs.append(g)
+    P.assert_staged(P.staged(p, sc, outs[0], n_iter=0))
+    for key in ("S", "w", "U"):
+        assert np.array_equal(outs[0][key], outs[1][key]), key
+
+
 def test_c0_end_to_end():
     """Plain single iteration against a fully independent oracle iteration
     (its own noise and rollouts): weights within 1e-5, controls within the
