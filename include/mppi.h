@@ -248,6 +248,14 @@ mppi_status mppi_set_lanes_per_sample(mppi_t* h, int32_t lanes);
  * Results are identical bit for bit. */
 mppi_status mppi_set_staging(mppi_t* h, int32_t mode);
 
+/* Compilation of the iteration kernel (the parallel rollout of Alg. 1,
+ * Sec. III-A): -1 (default) the tuning table's choice for the instance's
+ * shape, 0 the default register budget, 1 the variant compiled for five
+ * waves per SIMD (instances with far more waves than the GPU holds at
+ * once; at 8 and 16 lanes per sample, other shapes use 0).  Results are
+ * identical bit for bit.  MPPI_E_INVALID for other values. */
+mppi_status mppi_set_occupancy(mppi_t* h, int32_t mode);
+
 /* Wave-level culling of the two scans of the stage cost (on by default):
  * waypoint chunks and obstacle circles that provably cannot change any
  * lane's tracking minimum or obstacle cost are skipped.  Results are

@@ -3,10 +3,12 @@
 For every shape bucket -- K in powers of two, T buckets (<=16, <=32, <=64,
 <=128, <=256, >256) and circle-count buckets (0, <=16, <=64, <=256, >256) -- it runs
 a representative sine-lane instance with every lanes-per-sample shape
-(1, 2, 4, 8, 16) and, for the fastest of them, with and without the tiles'
-LDS copy of their perturbations, times whole iterations with HIP events, and
-writes the fastest pair as a line "k_log2 t_bucket c_bucket lanes stage" of
-``tuning.txt``.
+(1, 2, 4, 8, 16), then, for the fastest of them, with and without the tiles'
+LDS copy of their perturbations and -- at 8 or 16 lanes -- with the
+iteration kernel compiled for five waves per SIMD, times whole iterations
+with HIP events, and
+writes the fastest choice as a line "k_log2 t_bucket c_bucket lanes stage
+occupancy" of ``tuning.txt``.
 The library reads that file at its first launch (next to libmppi.so, or the
 file named by MPPI_TUNING_FILE).  A bucket's choice depends only on the
 instance's own shape, so an instance computes the same bits alone and inside
@@ -41,7 +43,7 @@ def shape_scene(K, T, n_c):
                 circles=scenes.sine_circles(rng, n_c))
 
 
-def time_shape(sc, lanes, reps, rounds=3, stage=1):
+def time_shape(sc, lanes, reps, rounds=3, stage=1, occ=0):
     """Best of `rounds` HIP-event timings of `reps` back-to-back iterations
     (the best filters out the other work of a shared GPU)."""
     from paper_2308_01654_amd import mppi
@@ -49,6 +51,7 @@ def time_shape(sc, lanes, reps, rounds=3, stage=1):
     pl = mppi.Planner(sc["params"], lanes=lanes)
     try:
         pl.set_staging(stage)
+        pl.set_occupancy(occ)
         pl.set_scene(sc["x0"], sc["waypoints"], sc["circles"])
         pl.step_resident(sc["x0"])
         pl.sync()
@@ -68,9 +71,10 @@ def main(argv=None):
     lines = ["# launch-shape tuning table of the MPPI iteration kernel",
              "# written by: python -m paper_2308_01654_amd.autotune (HIP-event iteration time, "
              "best of 3 rounds, fastest of lanes 1/2/4/8/16, then LDS staging of the "
-             "perturbations on (1) or off (0) at that shape)",
-             "# columns: k_log2 t_bucket c_bucket lanes stage   (t: <=16,<=32,<=64,<=128,<=256,>256; "
-             "c: 0,<=16,<=64,<=256,>256)"]
+             "perturbations on (1) or off (0) at that shape, then at 8 or 16 lanes the "
+             "compilation: default (0) or five waves per SIMD (1))",
+             "# columns: k_log2 t_bucket c_bucket lanes stage occupancy   (t: <=16,<=32,<=64,"
+             "<=128,<=256,>256; c: 0,<=16,<=64,<=256,>256)"]
     t0 = time.time()
     tmp = args.out + ".partial"
     with open(tmp, "w") as f:  # rows are appended as they are measured
@@ -86,13 +90,19 @@ def main(argv=None):
                 best = min(times, key=times.get)
                 off = time_shape(sc, best, reps, stage=0)
                 stage = 0 if off < times[best] else 1
-                lines.append("%d %d %d %d %d" % (kb, tb, cb, best, stage))
+                occ_t = {0: min(off, times[best])}
+                if best >= 8:
+                    for o in (1,):
+                        occ_t[o] = time_shape(sc, best, reps, stage=stage, occ=o)
+                occ = min(occ_t, key=occ_t.get)
+                lines.append("%d %d %d %d %d %d" % (kb, tb, cb, best, stage, occ))
                 with open(tmp, "a") as f:
                     f.write(lines[-1] + "\n")
                 print("K=%-7d T=%-4d circles=%-4d " % (K, T, C_REPS[cb]) +
                       " ".join("g%d=%.4fms" % (g, ms) for g, ms in times.items()) +
                       " g%d-unstaged=%.4fms" % (best, off) +
-                      "  -> %d %d  (%.0fs)" % (best, stage, time.time() - t0), flush=True)
+                      "".join(" g%d-occ%d=%.4fms" % (best, o, ms) for o, ms in occ_t.items() if o) +
+                      "  -> %d %d %d  (%.0fs)" % (best, stage, occ, time.time() - t0), flush=True)
     os.replace(tmp, args.out)
     print("wrote", args.out, flush=True)
     return 0

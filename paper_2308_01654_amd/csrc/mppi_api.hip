@@ -188,6 +188,7 @@ void write_scene(unsigned char* dst, const SceneLayout& L, const mppi_config& c,
 struct TuneEntry {
     int k, t, c, lanes;
     int stage;  // 1: the tiles may keep their perturbations in LDS; 0: read back from L2
+    int occ;    // 1: the high-occupancy compilation of the iteration kernel
 };
 static std::vector<TuneEntry> g_tune;
 static std::once_flag g_tune_once;
@@ -224,9 +225,11 @@ static void load_tuning()
     while (fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
         TuneEntry t;
-        t.stage = 1;  // the optional fifth column
-        const int n = sscanf(line, "%d %d %d %d %d", &t.k, &t.t, &t.c, &t.lanes, &t.stage);
-        if (n >= 4 && (t.stage == 0 || t.stage == 1) &&
+        t.stage = 1;  // the optional fifth and sixth columns
+        t.occ = 0;
+        const int n = sscanf(line, "%d %d %d %d %d %d", &t.k, &t.t, &t.c, &t.lanes, &t.stage,
+                             &t.occ);
+        if (n >= 4 && (t.stage == 0 || t.stage == 1) && t.occ >= 0 && t.occ < kOccModes &&
             (t.lanes == 1 || t.lanes == 2 || t.lanes == 4 || t.lanes == 8 || t.lanes == 16))
             g_tune.push_back(t);
     }
@@ -254,16 +257,35 @@ int auto_lanes(const mppi_config& c, int n_c)
     return g;
 }
 
-// The tuning table's staging choice for the bucket auto_lanes uses (1 when
-// the table has no such column or no bucket).
-int auto_stage(const mppi_config& c, int n_c)
+static const TuneEntry* tune_entry(const mppi_config& c, int n_c)
 {
     std::call_once(g_tune_once, load_tuning);
     const int kb = k_bucket(c.K), tb = t_bucket(c.T), cb = c_bucket(n_c);
     const TuneEntry* best = nullptr;
     for (const TuneEntry& e : g_tune)
         if (e.t == tb && e.c == cb && (!best || abs(e.k - kb) < abs(best->k - kb))) best = &e;
-    return best ? best->stage : 1;
+    return best;
+}
+
+// The tuning table's staging choice for the bucket auto_lanes uses (1 when
+// the table has no such column or no bucket).
+int auto_stage(const mppi_config& c, int n_c)
+{
+    const TuneEntry* e = tune_entry(c, n_c);
+    return e ? e->stage : 1;
+}
+
+int auto_occ(const mppi_config& c, int n_c)
+{
+    const TuneEntry* e = tune_entry(c, n_c);
+    return e ? e->occ : 0;
+}
+
+int occ_choice(const mppi_t* h, int n_c, int lanes)
+{
+    // the other compilations exist for 8 and 16 lanes per sample
+    if (lanes < 8) return kOccDefault;
+    return h->occ_req >= 0 ? h->occ_req : auto_occ(h->cfg, n_c);
 }
 
 // ---- profiling --------------------------------------------------------------------
@@ -464,6 +486,7 @@ void fill_desc(InstDesc& d, const mppi_t* h, const double x0[4], const double or
     // two or more waves per SIMD (256 compute units x 4): the block-ordered
     // wave priority pays; with fewer it only costs its instructions
     d.wave_prio = (long)c.K * d.lanes >= 2L * 1024 * 64 ? 1 : 0;
+    d.occ = occ_choice(h, n_c, d.lanes);
     d.dt = (float)c.dt;
     d.inv_dt = (float)(1.0 / c.dt);
     d.inv_L = (float)(1.0 / c.wheelbase);
@@ -628,7 +651,8 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
         const int g = hs[i]->lanes_req ? hs[i]->lanes_req : auto_lanes(c, nc);
         const int gi = g == 1 ? 0 : g == 2 ? 1 : g == 4 ? 2 : g == 8 ? 3 : 4;
         order[i] = i;
-        cls[i] = 25 * (c.model ? 1 : 0) + 5 * gi + active_ego(c.n_ego, nc);
+        cls[i] = 50 * occ_choice(hs[i], nc, g) + 25 * (c.model ? 1 : 0) + 5 * gi +
+                 active_ego(c.n_ego, nc);
         work[i] = (double)c.T * (73.0 + 6.0 * nw + 7.0 * c.n_ego * nc);
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
@@ -700,7 +724,8 @@ mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, co
         if (e == hipSuccess && shift_blocks) e = launch_shift_batch(hdr_dev, shift_blocks, stream);
         for (int c = 0; c < kLaneClasses && e == hipSuccess; ++c)
             if (grids[c] > 0)
-                e = launch_batch(kClassLanes[(c % 25) / 5], c % 5, c / 25, nullptr, hdr_dev, c,
+                e = launch_batch(kClassLanes[(c % 25) / 5], c % 5, (c % 50) / 25, c / 50, nullptr,
+                                 hdr_dev, c,
                                  grids[c], smem_b, stream);
         if (e == hipSuccess && combine_g)
             e = launch_combine(nullptr, hdr_dev, combine_g, n_blocks, max_nodes, stream);
@@ -846,7 +871,8 @@ mppi_status mppi_step_resident(mppi_t* h, const double x0[4])
     if ((s = record_launch(h, 0, &a)) != MPPI_OK) return s;
     hipEvent_t a2 = nullptr;
     if ((s = record_launch(h, 2, &a2)) != MPPI_OK) return s;
-    HIP_TRY(launch_batch(d.lanes, active_ego(d.n_ego, d.n_c), d.model, &d, nullptr, 0, d.n_tiles,
+    HIP_TRY(launch_batch(d.lanes, active_ego(d.n_ego, d.n_c), d.model, d.occ, &d, nullptr, 0,
+                         d.n_tiles,
                          smem, h->stream));
     if ((s = record_end(h, 2, a2)) != MPPI_OK) return s;
     HIP_TRY(launch_combine(&d, nullptr, combine_groups(d.T), 1, combine_nodes(d.n_tiles, nullptr),
@@ -1089,6 +1115,16 @@ mppi_status mppi_set_lanes_per_sample(mppi_t* h, int32_t lanes)
     if (!(lanes == 0 || lanes == 1 || lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16))
         return fail(MPPI_E_INVALID, "lanes per sample must be 0, 1, 2, 4, 8 or 16");
     h->lanes_req = lanes;
+    return MPPI_OK;
+}
+
+mppi_status mppi_set_occupancy(mppi_t* h, int32_t mode)
+{
+    mppi_status s = usable(h);
+    if (s != MPPI_OK) return s;
+    if (mode < -1 || mode >= kOccModes)
+        return fail(MPPI_E_INVALID, "occupancy mode must be -1, 0 or 1");
+    h->occ_req = mode;
     return MPPI_OK;
 }
 

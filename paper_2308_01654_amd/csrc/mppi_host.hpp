@@ -71,6 +71,7 @@ struct mppi {
     bool own_stream = false;
     int lanes_req = 0;  // 0 = tuning table
     int stage_req = -1; // -1 = tuning table, 0 = no LDS copy of the perturbations, 1 = when it fits
+    int occ_req = -1;   // -1 = tuning table, else kOccDefault or kOccHigh
     int no_cull = 0;    // 1: full waypoint and circle scans
     int last_lanes = 0;
     mppi_status sticky = MPPI_OK;
@@ -151,6 +152,11 @@ void choose_eps_stage(InstDesc& d, bool alone, int allowed);
 // the tuning table's choice for its shape).
 int stage_allowed(const mppi_t* h, int n_c);
 int auto_stage(const mppi_config& c, int n_c);
+// The compilation of the iteration kernel an instance is launched with: the
+// tuning table's choice (kOccDefault when it has no such column) unless the
+// handle requests one; kOccDefault below 8 lanes per sample.
+int auto_occ(const mppi_config& c, int n_c);
+int occ_choice(const mppi_t* h, int n_c, int lanes);
 mppi_status ws_create(BatchWs** out);
 void ws_destroy(BatchWs* b);
 // Create a handle; with_scratch = false leaves S/eps/partials/scales/scene

@@ -122,6 +122,7 @@ struct InstDesc {
     int per_step;         // 1: weights from the cost-to-go per step
     int eps_stage;        // 1: tiles keep their perturbations in LDS (lds_layout)
     int wave_prio;        // 1: wave priority falls with the block index (see iteration_tile)
+    int occ;              // compilation it is launched with, kOccDefault or kOccHigh (host-side)
     int model;            // 1: 5-state model of eq. (5), steering-rate control
     float steer0;         // its initial steering angle
     float ego_ext;        // max |ego_off|
@@ -144,13 +145,22 @@ struct InstDesc {
     DevState* st;         // followed by the partial-tree tickets
 };
 
+// Compilations of the iteration kernel (the "occupancy" launch choice): the
+// default one, and one for kHiOccWaves waves per SIMD (8 and 16 lanes per
+// sample only).
+constexpr int kOccDefault = 0;
+constexpr int kOccHigh = 1;
+constexpr int kOccModes = 2;
+constexpr int kHiOccWaves = 5;
+
 // Header of a batch arena in device memory: followed by the tile prefix
 // (n_inst + 1 ints) at off_prefix and the descriptors at off_descs.
-// Instances are grouped by kernel variant: class c = 25 * model +
-// 5 * lane_index + ne (model 0 or 1 (5-state); lane_index 0..4 for 1, 2, 4,
-// 8, 16 lanes per sample; ne = ego circles that meet obstacle circles, 0..4)
-// owns instances [cls_begin[c], cls_begin[c+1]).
-constexpr int kLaneClasses = 50;
+// Instances are grouped by kernel variant: class c = 50 * occ + 25 * model +
+// 5 * lane_index + ne (occ the compilation, kOccDefault or kOccHigh; model 0
+// or 1 (5-state); lane_index 0..4 for 1, 2, 4, 8, 16 lanes per sample; ne =
+// ego circles that meet obstacle circles, 0..4) owns instances
+// [cls_begin[c], cls_begin[c+1]).
+constexpr int kLaneClasses = 50 * kOccModes;
 struct BatchHdr {
     int n_inst;
     int total_tiles;
@@ -229,7 +239,7 @@ inline __host__ __device__ LdsLayout lds_layout(int n_wp, int n_c, int T, int sp
 // Iteration kernel, one workgroup per tile: one instance (d0, hdr_dev ==
 // nullptr) or lanes class `cls` of the batch described by the arena at
 // hdr_dev (lanes is the launch shape of every instance it processes).
-hipError_t launch_batch(int lanes, int ne, int model, const InstDesc* d0,
+hipError_t launch_batch(int lanes, int ne, int model, int occ, const InstDesc* d0,
                         const BatchHdr* hdr_dev, int cls, int grid, size_t smem,
                         hipStream_t stream);
 

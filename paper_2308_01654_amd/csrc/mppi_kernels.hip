@@ -765,7 +765,7 @@ __device__ __forceinline__ double wave_min(double v)
 // M5: the 5-state model of eq. (5) -- the steering angle is part of the state
 // and the second control is the steering rate.
 template <int G, int NE, bool M5>
-__device__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
+__device__ __forceinline__ void iteration_tile(const InstDesc& d, int tile, unsigned char* smem)
 {
     const int tid = threadIdx.x;
     constexpr int SPB = kBlock / G;  // samples per tile
@@ -1851,10 +1851,9 @@ __global__ __launch_bounds__(kBlock) void k_trajectory(TrajArgs a, const double*
 // Workgroups past the last tile of the class (the grid is rounded up so that
 // captured graphs can be replayed for other batches) return at once.
 template <int G, int NE, bool M5>
-__global__ __launch_bounds__(kBlock) void k_batch(InstDesc d0, const BatchHdr* __restrict__ hdr,
-                                                  int cls)
+__device__ __forceinline__ void batch_tile(const InstDesc& d0, const BatchHdr* __restrict__ hdr,
+                                           int cls, unsigned char* smem)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
     const int w = blockIdx.x;
     if (!hdr) {
         if (w < d0.n_tiles) iteration_tile<G, NE, M5>(d0, w, smem);
@@ -1875,31 +1874,71 @@ __global__ __launch_bounds__(kBlock) void k_batch(InstDesc d0, const BatchHdr* _
     iteration_tile<G, NE, M5>(descs[lo], gw - prefix[lo], smem);
 }
 
-template <int G, bool M5>
+template <int G, int NE, bool M5>
+__global__ __launch_bounds__(kBlock) void k_batch(InstDesc d0, const BatchHdr* __restrict__ hdr,
+                                                  int cls)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    batch_tile<G, NE, M5>(d0, hdr, cls, smem);
+}
+
+// The same kernel compiled for five waves per SIMD (at most 96 VGPRs, a few
+// spilled in some variants): the shape for instances with many more waves
+// than the GPU holds at once, where the extra wave hides more latency than
+// the spills cost.
+template <int G, int NE, bool M5>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kHiOccWaves)))
+void k_batch_hi(InstDesc d0, const BatchHdr* __restrict__ hdr, int cls)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    batch_tile<G, NE, M5>(d0, hdr, cls, smem);
+}
+
+// occ: kOccDefault or kOccHigh (the latter for 8 and 16 lanes per sample
+// only; other shapes take the default compilation).
+template <int G, bool M5, int OCC>
 static hipError_t launch_gm(int ne, const InstDesc& a, const BatchHdr* hdr_dev, int cls, int grid,
                             size_t smem, hipStream_t stream)
 {
     const dim3 g(grid), b(kBlock);
+#define MPPI_LAUNCH_NE(N)                                                                        \
+    case N:                                                                                       \
+        if constexpr (OCC == kOccHigh)                                                            \
+            hipLaunchKernelGGL((k_batch_hi<G, N, M5>), g, b, smem, stream, a, hdr_dev, cls);     \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_batch<G, N, M5>), g, b, smem, stream, a, hdr_dev, cls);        \
+        break;
     switch (ne) {
-    case 0: hipLaunchKernelGGL((k_batch<G, 0, M5>), g, b, smem, stream, a, hdr_dev, cls); break;
-    case 1: hipLaunchKernelGGL((k_batch<G, 1, M5>), g, b, smem, stream, a, hdr_dev, cls); break;
-    case 2: hipLaunchKernelGGL((k_batch<G, 2, M5>), g, b, smem, stream, a, hdr_dev, cls); break;
-    case 3: hipLaunchKernelGGL((k_batch<G, 3, M5>), g, b, smem, stream, a, hdr_dev, cls); break;
-    case 4: hipLaunchKernelGGL((k_batch<G, 4, M5>), g, b, smem, stream, a, hdr_dev, cls); break;
+    MPPI_LAUNCH_NE(0)
+    MPPI_LAUNCH_NE(1)
+    MPPI_LAUNCH_NE(2)
+    MPPI_LAUNCH_NE(3)
+    MPPI_LAUNCH_NE(4)
     default: return hipErrorInvalidValue;
     }
+#undef MPPI_LAUNCH_NE
     return hipGetLastError();
 }
 
-template <int G>
-static hipError_t launch_g(int ne, int model, const InstDesc& a, const BatchHdr* hdr_dev, int cls,
-                           int grid, size_t smem, hipStream_t stream)
+template <int G, int OCC>
+static hipError_t launch_go(int ne, int model, const InstDesc& a, const BatchHdr* hdr_dev,
+                            int cls, int grid, size_t smem, hipStream_t stream)
 {
-    return model ? launch_gm<G, true>(ne, a, hdr_dev, cls, grid, smem, stream)
-                 : launch_gm<G, false>(ne, a, hdr_dev, cls, grid, smem, stream);
+    return model ? launch_gm<G, true, OCC>(ne, a, hdr_dev, cls, grid, smem, stream)
+                 : launch_gm<G, false, OCC>(ne, a, hdr_dev, cls, grid, smem, stream);
 }
 
-hipError_t launch_batch(int lanes, int ne, int model, const InstDesc* d0,
+template <int G>
+static hipError_t launch_g(int ne, int model, int occ, const InstDesc& a, const BatchHdr* hdr_dev,
+                           int cls, int grid, size_t smem, hipStream_t stream)
+{
+    if constexpr (G >= 8) {
+        if (occ == kOccHigh) return launch_go<G, kOccHigh>(ne, model, a, hdr_dev, cls, grid, smem, stream);
+    }
+    return launch_go<G, kOccDefault>(ne, model, a, hdr_dev, cls, grid, smem, stream);
+}
+
+hipError_t launch_batch(int lanes, int ne, int model, int occ, const InstDesc* d0,
                         const BatchHdr* hdr_dev, int cls, int grid, size_t smem,
                         hipStream_t stream)
 {
@@ -1907,11 +1946,11 @@ hipError_t launch_batch(int lanes, int ne, int model, const InstDesc* d0,
     memset(&zero, 0, sizeof zero);
     const InstDesc& a = d0 ? *d0 : zero;
     switch (lanes) {
-    case 1: return launch_g<1>(ne, model, a, hdr_dev, cls, grid, smem, stream);
-    case 2: return launch_g<2>(ne, model, a, hdr_dev, cls, grid, smem, stream);
-    case 4: return launch_g<4>(ne, model, a, hdr_dev, cls, grid, smem, stream);
-    case 8: return launch_g<8>(ne, model, a, hdr_dev, cls, grid, smem, stream);
-    case 16: return launch_g<16>(ne, model, a, hdr_dev, cls, grid, smem, stream);
+    case 1: return launch_g<1>(ne, model, occ, a, hdr_dev, cls, grid, smem, stream);
+    case 2: return launch_g<2>(ne, model, occ, a, hdr_dev, cls, grid, smem, stream);
+    case 4: return launch_g<4>(ne, model, occ, a, hdr_dev, cls, grid, smem, stream);
+    case 8: return launch_g<8>(ne, model, occ, a, hdr_dev, cls, grid, smem, stream);
+    case 16: return launch_g<16>(ne, model, occ, a, hdr_dev, cls, grid, smem, stream);
     default: return hipErrorInvalidValue;
     }
 }

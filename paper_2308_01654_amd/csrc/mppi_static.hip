@@ -189,7 +189,8 @@ extern "C" mppi_status mppi_step_static(const mppi_config* cfg, const double x0[
     hipLaunchKernelGGL(k_static_begin, dim3(1), dim3(256), 0, stream, inst.st, tickets, n_tickets,
                        (unsigned long long)n_iter);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(launch_batch(d.lanes, active_ego(d.n_ego, d.n_c), d.model, &d, nullptr, 0, d.n_tiles,
+    HIP_TRY(launch_batch(d.lanes, active_ego(d.n_ego, d.n_c), d.model, d.occ, &d, nullptr, 0,
+                         d.n_tiles,
                          smem, stream));
     HIP_TRY(launch_combine(&d, nullptr, combine_groups(d.T), 1, combine_nodes(d.n_tiles, nullptr),
                            stream));

@@ -137,6 +137,7 @@ SIGNATURES = [
     ("mppi_get_iter_stats", _i32, [_vp, ctypes.POINTER(IterStats)]),
     ("mppi_set_lanes_per_sample", _i32, [_vp, _i32]),
     ("mppi_set_staging", _i32, [_vp, _i32]),
+    ("mppi_set_occupancy", _i32, [_vp, _i32]),
     ("mppi_set_culling", _i32, [_vp, _i32]),
     ("mppi_get_stream", _i32, [_vp, ctypes.POINTER(_vp)]),
     ("mppi_set_profiling", _i32, [_vp, _i32]),
@@ -358,6 +359,10 @@ class Planner:
     def set_staging(self, mode):
         """-1: tuning table, 0: no LDS copy of the perturbations, 1: when it fits."""
         check(load().mppi_set_staging(self.h, int(mode)))
+
+    def set_occupancy(self, mode):
+        """-1: tuning table, 0: default kernel, 1: the five-waves-per-SIMD kernel."""
+        check(load().mppi_set_occupancy(self.h, int(mode)))
 
     def step(self, x0, waypoints, circles):
         scene, keep = make_scene(waypoints, circles)

@@ -206,3 +206,31 @@ def test_batched_tile_tree_equals_alone_tile_tree(K):
     finally:
         for pl in pls:
             pl.close()
+
+
+def test_batch_with_high_occupancy_instances():
+    """Instances set to the other compilations of the iteration kernel form
+    launch classes of their own in a batch; every instance keeps its alone
+    bits."""
+    mppi = _mppi()
+    insts = _instances()[:5]
+    occ = [1, 0, 1, 1, 0]
+    alone = []
+    for sc, o in zip(insts, occ):
+        with mppi.Planner(sc["params"]) as pl:
+            pl.set_occupancy(o)
+            pl.step(sc["x0"], sc["waypoints"], sc["circles"])
+            alone.append((pl.costs(), pl.controls()))
+    lead = mppi.Planner(insts[0]["params"])
+    pls = [lead] + [mppi.Planner(sc["params"], hip_stream=lead.stream()) for sc in insts[1:]]
+    try:
+        for pl, o in zip(pls, occ):
+            pl.set_occupancy(o)
+        mppi.step_batch(pls, np.array([sc["x0"] for sc in insts]),
+                        [(sc["waypoints"], sc["circles"]) for sc in insts])
+        for k, pl in enumerate(pls):
+            assert np.array_equal(pl.costs(), alone[k][0]), k
+            assert np.array_equal(pl.controls(), alone[k][1]), k
+    finally:
+        for pl in reversed(pls):
+            pl.close()

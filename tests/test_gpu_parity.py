@@ -456,6 +456,28 @@ def test_varying_reference_speed_and_repeated_waypoints(lanes, n_c):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("name,lanes", [("c1", 16), ("c4", 16), ("c0", 4), ("tiny", 1),
+                                        ("tiny", 8)])
+def test_occupancy_choice_bit_identical(name, lanes):
+    """The iteration kernel compiled for five waves per SIMD (tuned per
+    shape) computes the same bits as the default compilation (below 8 lanes
+    the request falls back to the default)."""
+    mppi = _mppi()
+    sc = scenes.tiny(K=3000, T=45, n_c=40, seed=5) if name == "tiny" else scenes.by_name(name)
+    p = sc["params"]
+    outs = []
+    for occ in (1, 0):
+        _say("occupancy", name, lanes, occ)
+        with mppi.Planner(p, lanes=lanes) as pl:
+            pl.set_occupancy(occ)
+            for _ in range(1 if name == "c4" else 2):
+                pl.step(sc["x0"], sc["waypoints"], sc["circles"])
+            outs.append((pl.costs(), pl.noise(), pl.controls(), pl.weights()))
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("name,lanes", [("c1", 16), ("c0", 4), ("tiny", 1)])
 def test_staging_choice_bit_identical(name, lanes):
     """The tiles' LDS copy of their perturbations (tuned per shape) and the
