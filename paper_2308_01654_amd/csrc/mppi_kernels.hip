@@ -86,6 +86,20 @@ __device__ __forceinline__ void st_g(float2* p, size_t i, float2 v)
     w.y = v.y;
     as_global(reinterpret_cast<f2v*>(p))[i] = w;
 }
+// A store written through the XCD's L2 to the device's coherence point (a
+// relaxed agent-scope atomic store; its bits are those of the plain store).
+// Each XCD has its own write-back L2, so the release at the end of a kernel
+// writes back every line still dirty there before a dependent kernel can
+// start; data written through is already out, and that release has less to
+// do.  Used for the applied perturbations, written once and read by the
+// host (and the next launch only through another kernel).
+__device__ __forceinline__ void st_wt(float2* p, size_t i, float2 v)
+{
+    const unsigned long long bits = (unsigned long long)__float_as_uint(v.x) |
+                                    ((unsigned long long)__float_as_uint(v.y) << 32);
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p) + i, bits, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // ----------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
@@ -762,6 +776,29 @@ __device__ __forceinline__ double wave_min(double v)
     return fmin(fmin(lane_d(v, 0), lane_d(v, 16)), fmin(lane_d(v, 32), lane_d(v, 48)));
 }
 
+// v plus the value of the lane 16 (32) apart, the same in both lanes of the
+// pair.  With both operands equal, the gfx950 permlane swap leaves each lane
+// its own value in one result and its partner's in the other (which is
+// which depends on the lane), so their sum is the pair's sum either way.
+__device__ __forceinline__ double add_lanes_16_apart(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    const double x = __builtin_bit_cast(double, ((long long)hi[0] << 32) | (long long)lo[0]);
+    const double y = __builtin_bit_cast(double, ((long long)hi[1] << 32) | (long long)lo[1]);
+    return x + y;
+}
+__device__ __forceinline__ double add_lanes_32_apart(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+    const double x = __builtin_bit_cast(double, ((long long)hi[0] << 32) | (long long)lo[0]);
+    const double y = __builtin_bit_cast(double, ((long long)hi[1] << 32) | (long long)lo[1]);
+    return x + y;
+}
+
 // M5: the 5-state model of eq. (5) -- the steering angle is part of the state
 // and the second control is the steering rate.
 template <int G, int NE, bool M5>
@@ -1004,7 +1041,7 @@ __device__ __forceinline__ void iteration_tile(const InstDesc& d, int tile, unsi
         // block's first wait on the vector-memory counter (loads and stores
         // share it and complete in order).
         if (act) {
-            if (valid) st_g(d.eps, (size_t)tm * K + k, make_float2(mea, med));
+            if (valid) st_wt(d.eps, (size_t)tm * K + k, make_float2(mea, med));
             if (L.eps_staged) {
                 s.eps[(2 * tm) * (SPB + 1) + grp] = mea;
                 s.eps[(2 * tm + 1) * (SPB + 1) + grp] = med;
@@ -1330,8 +1367,9 @@ __device__ __forceinline__ void iteration_tile(const InstDesc& d, int tile, unsi
 // instance.  Every workgroup forms the global minimum m and the node scales
 // exp(-(m_b - m)/lambda), Z and Q itself (node order, fixed trees), then
 // updates kCombineSteps steps of U: U_t += N_t / Z with N_t summed over the
-// nodes in node order (chunks of consecutive nodes, then the chunks in
-// order).  With smoothing it also updates the two steps on either side
+// nodes in a fixed order (each thread a chunk of consecutive nodes in order,
+// the chunks of a wave by a fixed butterfly, then the four waves in order).
+// With smoothing it also updates the two steps on either side
 // (from the controls the iteration kernel kept) and writes its own steps
 // after eq. (sg).  Workgroup 0 records the statistics and bumps the
 // iteration counter.  Nothing is written if no sample cost is finite.
@@ -1339,8 +1377,8 @@ template <int KH>
 __device__ void combine(const InstDesc& d, int cg)
 {
     extern __shared__ __align__(16) unsigned char csm[];
-    double* sc = reinterpret_cast<double*>(csm);   // [KH * kBlock] node scales
-    double* red = sc + KH * kBlock;                // [64] reductions
+    double* sc = reinterpret_cast<double*>(csm);   // [KH * kBlock + 16] node scales
+    double* red = sc + KH * kBlock + 16;           // [64] reductions
     double* part = red + 64;                       // [kBlock] column partials
     double* un = part + kBlock;                    // [16] updated worked columns
     const int tid = threadIdx.x;
@@ -1361,31 +1399,45 @@ __device__ void combine(const InstDesc& d, int cg)
     const double* heads = d.partials + partial_heads_offset(T, 0, d.n_tiles);
 
     // One round trip: the node heads (KH per thread, from the
-    // compact head array) and the first sixteen nodes of this thread's chunk
-    // of its worked column.
+    // compact head array), the controls sampled around and the first sixteen
+    // nodes of this thread's chunk of its worked column.  Every load is
+    // issued unconditionally at an index clamped into its array and the
+    // value is replaced by the neutral element afterwards, so the heads can
+    // be used while the row loads are still in flight and the sums below run
+    // without branches (an added +0.0 leaves a sum that started at +0.0
+    // unchanged, so the results are those of skipping the term).
     constexpr int kH = KH;
     double mh[kH], zh[kH], qh[kH];
 #pragma unroll
     for (int r = 0; r < kH; ++r) {
         const int i = tid + r * kBlock;
         const double* h = heads + kHeadDoubles * (size_t)min(i, n - 1) * span;
-        mh[r] = i < n ? ld_g(h, 0) : INFINITY;
-        zh[r] = i < n ? ld_g(h, 1) : 0.0;
-        qh[r] = i < n ? ld_g(h, 2) : 0.0;
+        mh[r] = ld_g(h, 0);
+        zh[r] = ld_g(h, 1);
+        qh[r] = ld_g(h, 2);
     }
     const int slot = tid % slots, chunk = tid / slots;
     const int per = (n + chunks - 1) / chunks;
     const int i0 = min(chunk * per, n), i1 = min(i0 + per, n);
     const bool worked = slot < ncol;
-    const double* src = rows + 2 * w0 + slot;
+    const double* src = rows + min(2 * w0 + slot, 2 * T - 1);
     // the controls the iteration sampled around (kept after the tile rows when
     // smoothing, since other workgroups rewrite U), loaded with the rest
     const double* u_old = d.smooth ? d.partials + (size_t)d.n_tiles * stride : d.U;
-    const double u_prev = tid < ncol ? ld_g(u_old, 2 * w0 + tid) : 0.0;
+    const double u_ld = ld_g(u_old, min(2 * w0 + tid, 2 * T - 1));
     double pv[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
-        pv[u] = (worked && i0 + u < i1) ? ld_g(src, (size_t)(i0 + u) * nstride) : 0.0;
+    for (int u = 0; u < 16; ++u) pv[u] = ld_g(src, (size_t)min(i0 + u, n - 1) * nstride);
+    // (z and q masked by a product, which keeps their loads ahead of the
+    // rows': a select lets the compiler sink them into the branch below)
+#pragma unroll
+    for (int r = 0; r < kH; ++r) {
+        const bool in = tid + r * kBlock < n;
+        const double keep = in ? 1.0 : 0.0;
+        mh[r] = in ? mh[r] : INFINITY;
+        zh[r] *= keep;
+        qh[r] *= keep;
+    }
 
     // global minimum
     double mloc = mh[0];
@@ -1402,17 +1454,17 @@ __device__ void combine(const InstDesc& d, int cg)
         if (cg == 0 && tid == 0) d.st->status = -4;  // MPPI_E_NONFINITE: U and n unchanged
         return;
     }
-    // node scales, Z and Q (thread, wave, then waves in order)
+    // node scales (every slot of the scale array written, 0 beyond the
+    // nodes and in the 16 slots of padding), Z and Q (thread, wave, then
+    // waves in order)
+    if (tid < 16) sc[kH * kBlock + tid] = 0.0;
     double zl = 0.0, ql = 0.0;
 #pragma unroll
     for (int r = 0; r < kH; ++r) {
-        const int i = tid + r * kBlock;
-        if (i < n) {
-            const double si = isfinite(mh[r]) ? exp(-(mh[r] - m) / d.lambda) : 0.0;
-            sc[i] = si;
-            zl += zh[r] * si;
-            ql += qh[r] * si * si;
-        }
+        const double si = isfinite(mh[r]) ? exp(-(mh[r] - m) / d.lambda) : 0.0;
+        sc[tid + r * kBlock] = si;
+        zl += zh[r] * si;
+        ql += qh[r] * si * si;
     }
     const double wz = wave_sum(zl), wq = wave_sum(ql);
     if ((tid & 63) == 0) {
@@ -1428,27 +1480,33 @@ __device__ void combine(const InstDesc& d, int cg)
     }
 
     // weighted perturbation sums of the worked columns, nodes in order
+    // (i0 + u and b + u stay below n + 16: the padding covers them)
     double acc = 0.0;
-    if (worked) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
-            if (i0 + u < i1) acc += pv[u] * sc[i0 + u];
-        for (int b = i0 + 16; b < i1; b += 16) {
+    for (int u = 0; u < 16; ++u) {
+        const double pu = (worked && i0 + u < i1) ? pv[u] : 0.0;
+        acc += pu * sc[i0 + u];
+    }
+    for (int b = i0 + 16; b < i1; b += 16) {
 #pragma unroll
-            for (int u = 0; u < 16; ++u) pv[u] = b + u < i1 ? ld_g(src, (size_t)(b + u) * nstride) : 0.0;
+        for (int u = 0; u < 16; ++u) pv[u] = ld_g(src, (size_t)min(b + u, n - 1) * nstride);
 #pragma unroll
-            for (int u = 0; u < 16; ++u)
-                if (b + u < i1) acc += pv[u] * sc[b + u];
+        for (int u = 0; u < 16; ++u) {
+            const double pu = (worked && b + u < i1) ? pv[u] : 0.0;
+            acc += pu * sc[b + u];
         }
     }
-    part[tid] = acc;
+    // the column's sum over the chunks: the chunks of a wave (lanes slots
+    // apart) by a fixed butterfly, then the four waves in order
+    if (slots == 8) acc += dpp_d<0x128>(acc);  // row_ror:8, lanes 8 apart in a row
+    acc = add_lanes_16_apart(acc);
+    acc = add_lanes_32_apart(acc);
+    if ((tid & 63) < slots) part[wv * 16 + (tid & 63)] = acc;
     __syncthreads();
     if (tid < ncol) {
-        double nsum = 0.0;
-#pragma unroll 4
-        for (int c = 0; c < chunks; ++c) nsum += part[c * slots + tid];
+        const double nsum = ((part[tid] + part[16 + tid]) + part[32 + tid]) + part[48 + tid];
         const int col = 2 * w0 + tid;
-        const double u = u_prev + nsum / z;
+        const double u = u_ld + nsum / z;
         if (d.smooth) un[tid] = u;
         else d.U[col] = u;
     }
