@@ -96,6 +96,18 @@ inline __host__ __device__ int combine_nodes(int n_tiles, size_t* span)
 // Steps of U each combine workgroup updates.
 constexpr int kCombineSteps = 4;
 inline __host__ __device__ int combine_groups(int T) { return (T + kCombineSteps - 1) / kCombineSteps; }
+// Step group of combine workgroup b.  A group's columns are 64 bytes of
+// each tile row, the other half of their 128-byte line belongs to the
+// neighbouring group; workgroups reach the 8 XCDs round robin (b and b + 8
+// share one), so groups 2p and 2p + 1 are given to two such blocks and the
+// second finds the lines in their XCD's L2 instead of fetching them again.
+// Blocks of groups beyond the horizon return at once; the grid is
+// combine_grid(groups) wide.
+inline __host__ __device__ int combine_group_of_block(int b)
+{
+    return 2 * ((b >> 4) * 8 + (b & 7)) + ((b >> 3) & 1);
+}
+inline __host__ __device__ int combine_grid(int groups) { return (groups + 15) / 16 * 16; }
 
 // Everything one launch needs to run one MPPI iteration of one instance.
 // Scene arrays are in the ego frame (x0's position subtracted) and float32.
