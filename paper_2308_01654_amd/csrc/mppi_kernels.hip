@@ -1577,24 +1577,34 @@ __device__ void combine_per_step(const InstDesc& d, int cg)
     const int b0 = min(chunk * per, n), b1 = min(b0 + per, n);
     const double* col = rows + 5 * (size_t)t;
     const double* u_old = d.smooth ? d.partials + (size_t)n * stride : d.U;
-    const double ua_prev = tid < nst ? u_old[2 * (w0 + tid)] : 0.0;
-    const double ud_prev = tid < nst ? u_old[2 * (w0 + tid) + 1] : 0.0;
-
-    // one round trip: the step-0 heads and the chunk's first rows
-    double m0 = INFINITY;
+    // One round trip: the step-0 heads, the controls sampled around and the
+    // chunk's first rows.  Loads are issued unconditionally at indices
+    // clamped into the arrays and the neutral values selected afterwards
+    // (+inf for a minimum; the sums below then add exact zeros), so that no
+    // load waits behind a branch.
+    const int uc = 2 * (w0 + min(tid, nst - 1));
+    const double ua_ld = ld_g(u_old, uc), ud_ld = ld_g(u_old, uc + 1);
+    double m0v[2];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        const int b = tid + r * kBlock;
-        if (b < n) m0 = fmin(m0, rows[(size_t)b * stride]);
-    }
-    for (int b = tid + 2 * kBlock; b < n; b += kBlock) m0 = fmin(m0, rows[(size_t)b * stride]);
+    for (int r = 0; r < 2; ++r) m0v[r] = ld_g(rows, (size_t)min(tid + r * kBlock, n - 1) * stride);
     double hv[kPsBatch][5];
 #pragma unroll
     for (int u = 0; u < kPsBatch; ++u) {
-        const bool on = worked && b0 + u < b1;
-        const double* h = col + (size_t)(on ? b0 + u : 0) * stride;
+        const double* h = col + (size_t)min(b0 + u, n - 1) * stride;
 #pragma unroll
-        for (int c = 0; c < 5; ++c) hv[u][c] = on ? h[c] : (c == 0 ? INFINITY : 0.0);
+        for (int c = 0; c < 5; ++c) hv[u][c] = ld_g(h, c);
+    }
+    double m0 = INFINITY;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) m0 = fmin(m0, tid + r * kBlock < n ? m0v[r] : INFINITY);
+    for (int b = tid + 2 * kBlock; b < n; b += kBlock) m0 = fmin(m0, rows[(size_t)b * stride]);
+#pragma unroll
+    for (int u = 0; u < kPsBatch; ++u) {
+        const bool on = worked && b0 + u < b1;
+        const double keep = on ? 1.0 : 0.0;
+        hv[u][0] = on ? hv[u][0] : INFINITY;
+#pragma unroll
+        for (int c = 1; c < 5; ++c) hv[u][c] *= keep;
     }
 
     // step 0: minimum over the tiles (every workgroup)
@@ -1629,19 +1639,22 @@ __device__ void combine_per_step(const InstDesc& d, int cg)
     __syncthreads();
 
     // shifted sums of the chunk's tiles in tile order
+    // (m is finite for a worked step, so a tile with m_b,t = +inf -- or a
+    // slot of the batch past the chunk -- gets exp(-inf) = +0 exactly and
+    // adds zeros: no branch per tile)
     double z = 0.0, qq = 0.0, na = 0.0, nd = 0.0;
     if (worked) {
         const double m = mt[slot];
+        const double lam = d.lambda;
         auto add = [&](const double (&h)[5]) {
-            const double sc = isfinite(h[0]) ? exp(-(h[0] - m) / d.lambda) : 0.0;
+            const double sc = exp(-(h[0] - m) / lam);
             z += h[1] * sc;
             qq += h[2] * sc * sc;
             na += h[3] * sc;
             nd += h[4] * sc;
         };
 #pragma unroll
-        for (int u = 0; u < kPsBatch; ++u)
-            if (b0 + u < b1) add(hv[u]);
+        for (int u = 0; u < kPsBatch; ++u) add(hv[u]);
         for (int b = b0 + kPsBatch; b < b1; ++b) {
             const double* hp = col + (size_t)b * stride;
             const double h[5] = {hp[0], hp[1], hp[2], hp[3], hp[4]};
@@ -1675,8 +1688,8 @@ __device__ void combine_per_step(const InstDesc& d, int cg)
             sd += pc[3];
         }
         const int tt = w0 + tid;
-        const double ua = ua_prev + sa / zt;
-        const double ud = ud_prev + sd / zt;
+        const double ua = ua_ld + sa / zt;
+        const double ud = ud_ld + sd / zt;
         if (d.smooth) {
             un[2 * tid] = ua;
             un[2 * tid + 1] = ud;
