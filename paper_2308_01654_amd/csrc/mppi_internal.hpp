@@ -96,18 +96,24 @@ inline __host__ __device__ int combine_nodes(int n_tiles, size_t* span)
 // Steps of U each combine workgroup updates.
 constexpr int kCombineSteps = 4;
 inline __host__ __device__ int combine_groups(int T) { return (T + kCombineSteps - 1) / kCombineSteps; }
-// Step group of combine workgroup b.  A group's columns are 64 bytes of
-// each tile row, the other half of their 128-byte line belongs to the
-// neighbouring group; workgroups reach the 8 XCDs round robin (b and b + 8
-// share one), so groups 2p and 2p + 1 are given to two such blocks and the
-// second finds the lines in their XCD's L2 instead of fetching them again.
-// Blocks of groups beyond the horizon return at once; the grid is
-// combine_grid(groups) wide.
-inline __host__ __device__ int combine_group_of_block(int b)
+// Step group of combine workgroup b of a grid `groups` wide.  A group's
+// columns are 64 bytes of each tile row, the other half of their 128-byte
+// line belongs to the neighbouring group; workgroups reach the 8 XCDs round
+// robin (b and b + 8 share one), so within every whole run of 16 groups,
+// groups 2p and 2p + 1 are given to two such blocks and the second finds
+// the lines in their XCD's L2 instead of fetching them again.  A last run
+// shorter than 16 keeps block b on group b.  A single instance's grid is
+// padded to whole runs (blocks past the horizon return at once); a batch's,
+// one row per instance, is not, to spare it the empty blocks.
+inline __host__ __device__ int combine_group_of_block(int b, int grid)
 {
-    return 2 * ((b >> 4) * 8 + (b & 7)) + ((b >> 3) & 1);
+    if ((b | 15) >= grid) return b;
+    return (b & ~15) + 2 * (b & 7) + ((b >> 3) & 1);
 }
-inline __host__ __device__ int combine_grid(int groups) { return (groups + 15) / 16 * 16; }
+inline __host__ __device__ int combine_grid(int groups, int n_inst)
+{
+    return n_inst == 1 ? (groups + 15) / 16 * 16 : groups;
+}
 
 // Everything one launch needs to run one MPPI iteration of one instance.
 // Scene arrays are in the ego frame (x0's position subtracted) and float32.

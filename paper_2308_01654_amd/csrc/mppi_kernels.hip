@@ -1724,7 +1724,7 @@ __device__ void combine_per_step(const InstDesc& d, int cg)
 template <int KH>
 __global__ __launch_bounds__(kBlock) void k_combine(InstDesc d0, const BatchHdr* __restrict__ hdr)
 {
-    const int cg = combine_group_of_block(blockIdx.x);
+    const int cg = combine_group_of_block(blockIdx.x, gridDim.x);
     if (!hdr) {
         if (d0.per_step) combine_per_step(d0, cg);
         else combine<KH>(d0, cg);
@@ -1745,12 +1745,12 @@ hipError_t launch_combine(const InstDesc* d0, const BatchHdr* hdr_dev, int group
     if (max_nodes <= kDirectSmall) {
         constexpr int KH = kDirectSmall / kBlock;
         const size_t smem = sizeof(double) * (KH * kBlock + 64 + 4 * kBlock + 8 + 16);
-        hipLaunchKernelGGL(k_combine<KH>, dim3(combine_grid(groups), n_inst), dim3(kBlock), smem, stream,
+        hipLaunchKernelGGL(k_combine<KH>, dim3(combine_grid(groups, n_inst), n_inst), dim3(kBlock), smem, stream,
                            d0 ? *d0 : zero, hdr_dev);
     } else {
         constexpr int KH = kDirect / kBlock;
         const size_t smem = sizeof(double) * (KH * kBlock + 64 + 4 * kBlock + 8 + 16);
-        hipLaunchKernelGGL(k_combine<KH>, dim3(combine_grid(groups), n_inst), dim3(kBlock), smem, stream,
+        hipLaunchKernelGGL(k_combine<KH>, dim3(combine_grid(groups, n_inst), n_inst), dim3(kBlock), smem, stream,
                            d0 ? *d0 : zero, hdr_dev);
     }
     return hipGetLastError();
