@@ -375,7 +375,7 @@ void handle_release(mppi_t* h)
     (void)hipFree(h->q);
     (void)hipFree(h->Stk);
     (void)hipFree(h->wbuf);
-    (void)hipFree(h->traj);
+    (void)hipHostFree(h->traj);
     (void)hipFree(h->st);
     (void)hipFree(h->scene);
     if (h->batch) {
@@ -416,10 +416,12 @@ mppi_status handle_create(const mppi_config* cfg, void* hip_stream, bool with_sc
         h->own_stream = true;
     }
     if ((e = hipMalloc((void**)&h->U, sizeof(double) * 2 * T)) != hipSuccess ||
-        (e = hipMalloc((void**)&h->traj, sizeof(double) * (5 * (size_t)(T + 1) + 2 * T))) !=
-            hipSuccess ||
         (e = hipMalloc((void**)&h->st, state_bytes(h->max_tiles))) != hipSuccess)
         return bail(MPPI_E_NOMEM, "hipMalloc", e);
+    if ((e = hipHostMalloc((void**)&h->traj, sizeof(double) * (5 * (size_t)(T + 1) + 2 * T),
+                           hipHostMallocCoherent)) != hipSuccess ||
+        (e = hipHostGetDevicePointer((void**)&h->traj_dev, h->traj, 0)) != hipSuccess)
+        return bail(MPPI_E_NOMEM, "hipHostMalloc", e);
     if (with_scratch) {
         struct { void** p; size_t n; } allocs[] = {
             {(void**)&h->S, sizeof(float) * K},
@@ -1055,17 +1057,13 @@ mppi_status mppi_get_trajectory(mppi_t* h, double* states, size_t n_states, doub
     a.d_min = c.u_min[1];
     a.d_max = c.u_max[1];
     a.v_max = c.v_max;
-    // states then controls, contiguous: one copy back
+    // states then controls, written by the kernel straight into the pinned
+    // host buffer: no copy back to wait for
     const size_t ns = cols * (T + 1), nu = (size_t)2 * T;
-    double* xs = h->traj;
-    double* us = h->traj + ns;
-    HIP_TRY(launch_trajectory(a, h->U, xs, us, h->stream));
-    std::vector<double> host(ns + nu);
-    HIP_TRY(hipMemcpyAsync(host.data(), xs, sizeof(double) * (ns + nu), hipMemcpyDeviceToHost,
-                           h->stream));
+    HIP_TRY(launch_trajectory(a, h->U, h->traj_dev, h->traj_dev + ns, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    if (states) memcpy(states, host.data(), sizeof(double) * ns);
-    if (controls) memcpy(controls, host.data() + ns, sizeof(double) * nu);
+    if (states) memcpy(states, h->traj, sizeof(double) * ns);
+    if (controls) memcpy(controls, h->traj + ns, sizeof(double) * nu);
     return MPPI_OK;
 }
 

@@ -83,7 +83,11 @@ struct mppi {
     float* q = nullptr;      // [T][K] stage costs (per-step weights)
     double* Stk = nullptr;   // [T][K] cost-to-go (per-step weights)
     double* wbuf = nullptr;  // [K] weights export
-    double* traj = nullptr;  // optimal trajectory: states [T+1][4], controls [T][2]
+    // optimal trajectory: states [T+1][4 or 5], controls [T][2], in pinned
+    // coherent host memory that k_trajectory writes directly (traj_dev is
+    // its device address)
+    double* traj = nullptr;
+    double* traj_dev = nullptr;
     mppi_impl::DevState* st = nullptr;
     unsigned char* scene = nullptr;
     size_t scene_cap = 0;
