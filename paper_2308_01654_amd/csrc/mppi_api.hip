@@ -376,6 +376,7 @@ void handle_release(mppi_t* h)
     (void)hipFree(h->Stk);
     (void)hipFree(h->wbuf);
     (void)hipHostFree(h->traj);
+    (void)hipHostFree(h->ctl_host);
     (void)hipFree(h->st);
     (void)hipFree(h->scene);
     if (h->batch) {
@@ -420,7 +421,10 @@ mppi_status handle_create(const mppi_config* cfg, void* hip_stream, bool with_sc
         return bail(MPPI_E_NOMEM, "hipMalloc", e);
     if ((e = hipHostMalloc((void**)&h->traj, sizeof(double) * (5 * (size_t)(T + 1) + 2 * T),
                            hipHostMallocCoherent)) != hipSuccess ||
-        (e = hipHostGetDevicePointer((void**)&h->traj_dev, h->traj, 0)) != hipSuccess)
+        (e = hipHostGetDevicePointer((void**)&h->traj_dev, h->traj, 0)) != hipSuccess ||
+        (e = hipHostMalloc((void**)&h->ctl_host, sizeof(double) * 2 * T + sizeof(DevState),
+                           hipHostMallocCoherent)) != hipSuccess ||
+        (e = hipHostGetDevicePointer((void**)&h->ctl_dev, h->ctl_host, 0)) != hipSuccess)
         return bail(MPPI_E_NOMEM, "hipHostMalloc", e);
     if (with_scratch) {
         struct { void** p; size_t n; } allocs[] = {
@@ -933,9 +937,16 @@ mppi_status mppi_get_controls(mppi_t* h, double* out, size_t n)
     if (s != MPPI_OK) return s;
     if (!out || n < (size_t)2 * h->cfg.T)
         return fail(MPPI_E_INVALID, "output buffer needs %d doubles", 2 * h->cfg.T);
+    // U and the state written by one small kernel straight into pinned host
+    // memory, then one synchronisation (no copies back to wait for)
+    const int nu = 2 * h->cfg.T;
+    HIP_TRY(launch_export_controls(h->U, nu, h->st, h->ctl_dev,
+                                   reinterpret_cast<DevState*>(h->ctl_dev + nu), h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    HIP_TRY(hipMemcpy(out, h->U, sizeof(double) * 2 * h->cfg.T, hipMemcpyDeviceToHost));
-    return sync_status(h);
+    memcpy(out, h->ctl_host, sizeof(double) * nu);
+    if (h->stepped && reinterpret_cast<const DevState*>(h->ctl_host + nu)->status != 0)
+        return fail(MPPI_E_NONFINITE, "every sample cost of the last step was non-finite");
+    return MPPI_OK;
 }
 
 mppi_status mppi_set_controls(mppi_t* h, const double* U, size_t n)

@@ -88,6 +88,10 @@ struct mppi {
     // its device address)
     double* traj = nullptr;
     double* traj_dev = nullptr;
+    // pinned coherent host buffer that k_export_controls writes: U [T][2],
+    // then the device state (ctl_dev: its device address)
+    double* ctl_host = nullptr;
+    double* ctl_dev = nullptr;
     mppi_impl::DevState* st = nullptr;
     unsigned char* scene = nullptr;
     size_t scene_cap = 0;

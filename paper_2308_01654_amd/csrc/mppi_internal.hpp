@@ -286,6 +286,9 @@ struct TrajArgs {
     int model;      // 1: 5-state model, states written with 5 columns
     double dt, wheelbase, a_min, a_max, d_min, d_max, v_max;
 };
+// U [n] and the device state into host memory the device can write (pinned).
+hipError_t launch_export_controls(const double* U, int n, const DevState* st, double* out_u,
+                                  DevState* out_st, hipStream_t stream);
 hipError_t launch_trajectory(const TrajArgs& a, const double* U, double* states, double* applied,
                              hipStream_t stream);
 hipError_t launch_shift(double* U, int T, int steps, hipStream_t stream);

@@ -2089,6 +2089,25 @@ __global__ void k_weights(const float* __restrict__ S, const double* __restrict_
     w[k] = isfinite(sk) ? exp(-(sk - st->s_min) / lambda) / st->z : 0.0;
 }
 
+// The nominal controls and the device state copied into the caller's pinned
+// host memory: one launch instead of two copies back.
+__global__ __launch_bounds__(kBlock) void k_export_controls(const double* __restrict__ U, int n,
+                                                            const DevState* __restrict__ st,
+                                                            double* __restrict__ out_u,
+                                                            DevState* __restrict__ out_st)
+{
+    for (int i = threadIdx.x; i < n; i += kBlock) out_u[i] = U[i];
+    if (threadIdx.x == 0) *out_st = *st;
+}
+
+hipError_t launch_export_controls(const double* U, int n, const DevState* st, double* out_u,
+                                  DevState* out_st, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_export_controls, dim3(1), dim3(kBlock), 0, stream, U, n, st, out_u,
+                       out_st);
+    return hipGetLastError();
+}
+
 hipError_t launch_trajectory(const TrajArgs& a, const double* U, double* states, double* applied,
                              hipStream_t stream)
 {
