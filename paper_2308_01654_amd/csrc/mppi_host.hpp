@@ -174,9 +174,10 @@ mppi_status handle_create(const mppi_config* cfg, void* hip_stream, bool with_sc
 void handle_release(mppi_t* h);
 // Enqueue one iteration of hs[0..n) as one launch per kernel variant on
 // `stream`.  scenes == nullptr: resident scenes.  extra: optional per-instance
-// scratch/shift/result slot.  gather_dev: optional device buffer receiving,
-// per instance with out_slot >= 0, U [2T] doubles followed by the status and
-// the iteration counter at slot * slot_doubles.  use_graph: capture the
+// scratch/shift/result slot.  gather_dev: optional buffer the device can
+// write (device memory, or the device address of pinned host memory)
+// receiving, per instance with out_slot >= 0, U [2T] doubles followed by the
+// status and the iteration counter at slot * slot_doubles.  use_graph: capture the
 // launch sequence per size class and replay it (repeated batches of one
 // shape); otherwise launch directly (batches whose composition changes).
 mppi_status batch_enqueue(BatchWs* ws, hipStream_t stream, mppi_t* const* hs, const double* x0s,

@@ -76,8 +76,11 @@ struct Vehicle {
 struct StreamCtx {
     hipStream_t s = nullptr;
     BatchWs* ws = nullptr;
-    double* gather_dev = nullptr;
+    // per-request results (U, status, iteration), written by the gather
+    // kernel straight into this pinned coherent host buffer (gather_hdev:
+    // its device address), so no copy back follows the batch
     double* gather_host = nullptr;
+    double* gather_hdev = nullptr;
     hipEvent_t done = nullptr;
     std::vector<Req*> batch;
     bool busy = false;
@@ -298,13 +301,9 @@ void scheduler_loop(mppi_server* srv)
         lk.unlock();
         // every batch has its own composition: direct launches, no graph
         mppi_status st = batch_enqueue(sc->ws, sc->s, hs.data(), x0s.data(), scs.data(), ex.data(),
-                                       n, nullptr, sc->gather_dev, kSlotDoubles, false);
+                                       n, nullptr, sc->gather_hdev, kSlotDoubles, false);
         hipError_t e = hipSuccess;
-        if (st == MPPI_OK)
-            e = hipMemcpyAsync(sc->gather_host, sc->gather_dev,
-                               sizeof(double) * kSlotDoubles * (size_t)n, hipMemcpyDeviceToHost,
-                               sc->s);
-        if (st == MPPI_OK && e == hipSuccess) e = hipEventRecord(sc->done, sc->s);
+        if (st == MPPI_OK) e = hipEventRecord(sc->done, sc->s);
         lk.lock();
         if (st != MPPI_OK || e != hipSuccess) {
             srv->sticky = MPPI_E_DEVICE;
@@ -353,7 +352,6 @@ void server_release(mppi_server* srv)
         }
         if (s->s) (void)hipStreamSynchronize(s->s);
         ws_destroy(s->ws);
-        (void)hipFree(s->gather_dev);
         if (s->gather_host) (void)hipHostFree(s->gather_host);
         if (s->done) (void)hipEventDestroy(s->done);
         if (s->s) (void)hipStreamDestroy(s->s);
@@ -403,8 +401,8 @@ mppi_status mppi_server_create(const mppi_server_config* cfg, mppi_server_t** ou
         e = hipStreamCreateWithFlags(&sc->s, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sc->done, hipEventDisableTiming);
         const size_t gb = sizeof(double) * kSlotDoubles * (size_t)srv->cfg.max_batch;
-        if (e == hipSuccess) e = hipMalloc((void**)&sc->gather_dev, gb);
-        if (e == hipSuccess) e = hipHostMalloc((void**)&sc->gather_host, gb, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&sc->gather_host, gb, hipHostMallocCoherent);
+        if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&sc->gather_hdev, sc->gather_host, 0);
         if (e == hipSuccess && ws_create(&sc->ws) != MPPI_OK) e = hipErrorOutOfMemory;
         srv->streams.push_back(std::move(sc));
     }
