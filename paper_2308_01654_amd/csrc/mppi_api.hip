@@ -347,12 +347,27 @@ static mppi_status launch_aux(mppi_t* h, F&& f)
     return record_end(h, 1, a);
 }
 
+// The device state after the handle's stream has drained: written by one
+// small kernel into the pinned host buffer, then one synchronisation.
+static mppi_status read_state(mppi_t* h, DevState* out)
+{
+    const int nu = 2 * h->cfg.T;
+    DevState* dst = reinterpret_cast<DevState*>(h->ctl_dev + nu);
+    HIP_TRY(launch_export_controls(h->U, 0, h->st, h->ctl_dev, dst, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    *out = *reinterpret_cast<const DevState*>(h->ctl_host + nu);
+    return MPPI_OK;
+}
+
 static mppi_status sync_status(mppi_t* h)
 {
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    if (!h->stepped) return MPPI_OK;
+    if (!h->stepped) {
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        return MPPI_OK;
+    }
     DevState st;
-    HIP_TRY(hipMemcpy(&st, h->st, sizeof st, hipMemcpyDeviceToHost));
+    const mppi_status s = read_state(h, &st);
+    if (s != MPPI_OK) return s;
     if (st.status != 0)
         return fail(MPPI_E_NONFINITE, "every sample cost of the last step was non-finite");
     return MPPI_OK;
@@ -1105,9 +1120,9 @@ mppi_status mppi_get_iter_stats(mppi_t* h, mppi_iter_stats* out)
     mppi_status s = usable(h);
     if (s != MPPI_OK) return s;
     if (!out) return fail(MPPI_E_INVALID, "out is NULL");
-    HIP_TRY(hipStreamSynchronize(h->stream));
     DevState st;
-    HIP_TRY(hipMemcpy(&st, h->st, sizeof st, hipMemcpyDeviceToHost));
+    s = read_state(h, &st);
+    if (s != MPPI_OK) return s;
     out->s_min = st.s_min;
     out->log_z = st.log_z;
     out->ess = st.ess;
