@@ -992,11 +992,14 @@ mppi_status mppi_get_state(mppi_t* h, double* U, size_t n, uint64_t* n_iter, uin
     if (s != MPPI_OK) return s;
     if (!U || n < (size_t)2 * h->cfg.T)
         return fail(MPPI_E_INVALID, "state buffer needs %d doubles", 2 * h->cfg.T);
+    // U and the state through the pinned export buffer (one small kernel,
+    // one synchronisation)
+    const int nu = 2 * h->cfg.T;
+    HIP_TRY(launch_export_controls(h->U, nu, h->st, h->ctl_dev,
+                                   reinterpret_cast<DevState*>(h->ctl_dev + nu), h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
-    DevState st;
-    HIP_TRY(hipMemcpy(&st, h->st, sizeof st, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(U, h->U, sizeof(double) * 2 * h->cfg.T, hipMemcpyDeviceToHost));
-    if (n_iter) *n_iter = st.n_iter;
+    memcpy(U, h->ctl_host, sizeof(double) * nu);
+    if (n_iter) *n_iter = reinterpret_cast<const DevState*>(h->ctl_host + nu)->n_iter;
     if (seed) *seed = h->cfg.seed;
     return MPPI_OK;
 }
