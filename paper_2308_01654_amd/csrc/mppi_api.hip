@@ -347,10 +347,34 @@ static mppi_status launch_aux(mppi_t* h, F&& f)
     return record_end(h, 1, a);
 }
 
+// The pinned, coherent host buffers the device writes results into (U and
+// the state; the optimal trajectory), made on first use so that handles
+// that never read them back -- a server's vehicles -- hold no pinned pages.
+static mppi_status host_buffers(mppi_t* h)
+{
+    if (h->ctl_host) return MPPI_OK;
+    const size_t T = (size_t)h->cfg.T;
+    hipError_t e;
+    if ((e = hipHostMalloc((void**)&h->traj, sizeof(double) * (5 * (T + 1) + 2 * T),
+                           hipHostMallocCoherent)) != hipSuccess ||
+        (e = hipHostGetDevicePointer((void**)&h->traj_dev, h->traj, 0)) != hipSuccess ||
+        (e = hipHostMalloc((void**)&h->ctl_host, sizeof(double) * 2 * T + sizeof(DevState),
+                           hipHostMallocCoherent)) != hipSuccess ||
+        (e = hipHostGetDevicePointer((void**)&h->ctl_dev, h->ctl_host, 0)) != hipSuccess) {
+        if (h->traj) (void)hipHostFree(h->traj);
+        if (h->ctl_host) (void)hipHostFree(h->ctl_host);
+        h->traj = h->traj_dev = h->ctl_host = h->ctl_dev = nullptr;
+        return fail(MPPI_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+    }
+    return MPPI_OK;
+}
+
 // The device state after the handle's stream has drained: written by one
 // small kernel into the pinned host buffer, then one synchronisation.
 static mppi_status read_state(mppi_t* h, DevState* out)
 {
+    const mppi_status s = host_buffers(h);
+    if (s != MPPI_OK) return s;
     const int nu = 2 * h->cfg.T;
     DevState* dst = reinterpret_cast<DevState*>(h->ctl_dev + nu);
     HIP_TRY(launch_export_controls(h->U, 0, h->st, h->ctl_dev, dst, h->stream));
@@ -390,8 +414,8 @@ void handle_release(mppi_t* h)
     (void)hipFree(h->q);
     (void)hipFree(h->Stk);
     (void)hipFree(h->wbuf);
-    (void)hipHostFree(h->traj);
-    (void)hipHostFree(h->ctl_host);
+    if (h->traj) (void)hipHostFree(h->traj);
+    if (h->ctl_host) (void)hipHostFree(h->ctl_host);
     (void)hipFree(h->st);
     (void)hipFree(h->scene);
     if (h->batch) {
@@ -434,13 +458,6 @@ mppi_status handle_create(const mppi_config* cfg, void* hip_stream, bool with_sc
     if ((e = hipMalloc((void**)&h->U, sizeof(double) * 2 * T)) != hipSuccess ||
         (e = hipMalloc((void**)&h->st, state_bytes(h->max_tiles))) != hipSuccess)
         return bail(MPPI_E_NOMEM, "hipMalloc", e);
-    if ((e = hipHostMalloc((void**)&h->traj, sizeof(double) * (5 * (size_t)(T + 1) + 2 * T),
-                           hipHostMallocCoherent)) != hipSuccess ||
-        (e = hipHostGetDevicePointer((void**)&h->traj_dev, h->traj, 0)) != hipSuccess ||
-        (e = hipHostMalloc((void**)&h->ctl_host, sizeof(double) * 2 * T + sizeof(DevState),
-                           hipHostMallocCoherent)) != hipSuccess ||
-        (e = hipHostGetDevicePointer((void**)&h->ctl_dev, h->ctl_host, 0)) != hipSuccess)
-        return bail(MPPI_E_NOMEM, "hipHostMalloc", e);
     if (with_scratch) {
         struct { void** p; size_t n; } allocs[] = {
             {(void**)&h->S, sizeof(float) * K},
@@ -954,6 +971,7 @@ mppi_status mppi_get_controls(mppi_t* h, double* out, size_t n)
         return fail(MPPI_E_INVALID, "output buffer needs %d doubles", 2 * h->cfg.T);
     // U and the state written by one small kernel straight into pinned host
     // memory, then one synchronisation (no copies back to wait for)
+    if ((s = host_buffers(h)) != MPPI_OK) return s;
     const int nu = 2 * h->cfg.T;
     HIP_TRY(launch_export_controls(h->U, nu, h->st, h->ctl_dev,
                                    reinterpret_cast<DevState*>(h->ctl_dev + nu), h->stream));
@@ -994,6 +1012,7 @@ mppi_status mppi_get_state(mppi_t* h, double* U, size_t n, uint64_t* n_iter, uin
         return fail(MPPI_E_INVALID, "state buffer needs %d doubles", 2 * h->cfg.T);
     // U and the state through the pinned export buffer (one small kernel,
     // one synchronisation)
+    if ((s = host_buffers(h)) != MPPI_OK) return s;
     const int nu = 2 * h->cfg.T;
     HIP_TRY(launch_export_controls(h->U, nu, h->st, h->ctl_dev,
                                    reinterpret_cast<DevState*>(h->ctl_dev + nu), h->stream));
@@ -1089,6 +1108,7 @@ mppi_status mppi_get_trajectory(mppi_t* h, double* states, size_t n_states, doub
     // states then controls, written by the kernel straight into the pinned
     // host buffer: no copy back to wait for
     const size_t ns = cols * (T + 1), nu = (size_t)2 * T;
+    if ((s = host_buffers(h)) != MPPI_OK) return s;
     HIP_TRY(launch_trajectory(a, h->U, h->traj_dev, h->traj_dev + ns, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     if (states) memcpy(states, h->traj, sizeof(double) * ns);
