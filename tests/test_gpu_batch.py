@@ -234,3 +234,36 @@ def test_batch_with_high_occupancy_instances():
     finally:
         for pl in reversed(pls):
             pl.close()
+
+
+@pytest.mark.parametrize("T", [60, 64, 65, 128, 132])
+def test_combine_step_group_runs(T):
+    """Horizons whose number of 4-step combine groups is just below, at and
+    just past a whole run of 16 (15, 16, 17, 32, 33 groups).  Alone, the
+    combine grid is padded to whole runs and paired workgroups share an
+    XCD; in a batch with a longer horizon (38 groups) the grid is not padded
+    and a short last run maps one to one.  Staged parity alone, and the
+    batched instance computes the alone bits over two iterations."""
+    mppi = _mppi()
+    sc = scenes.c2_instance(3, (2048, T, 12))
+    other = scenes.c2_instance(5, (1024, 150, 5))
+    p = sc["params"]
+    _say("group runs", T)
+    with mppi.Planner(p) as pl:
+        g = P.gpu_step(pl, sc)
+    P.assert_staged(P.staged(p, sc, g, n_iter=0))
+    alone = _run_alone(mppi, sc, 2)
+    lead = mppi.Planner(other["params"])
+    pls = [lead, mppi.Planner(p, hip_stream=lead.stream())]
+    try:
+        x0s = np.array([other["x0"], sc["x0"]])
+        arrays = [(other["waypoints"], other["circles"]), (sc["waypoints"], sc["circles"])]
+        for it in range(2):
+            mppi.step_batch(pls, x0s, arrays)
+            U, S, w = alone[it]
+            assert np.array_equal(pls[1].controls(), U), (T, it)
+            assert np.array_equal(pls[1].costs(), S), (T, it)
+            assert np.array_equal(pls[1].weights(), w), (T, it)
+    finally:
+        for q in reversed(pls):
+            q.close()
