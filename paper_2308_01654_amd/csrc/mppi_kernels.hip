@@ -1379,7 +1379,7 @@ __device__ void combine(const InstDesc& d, int cg)
     extern __shared__ __align__(16) unsigned char csm[];
     double* sc = reinterpret_cast<double*>(csm);   // [KH * kBlock + 16] node scales
     double* red = sc + KH * kBlock + 16;           // [64] reductions
-    double* part = red + 64;                       // [kBlock] column partials
+    double* part = red + 64;                       // [4 waves][16 slots] column partials
     double* un = part + kBlock;                    // [16] updated worked columns
     const int tid = threadIdx.x;
     const int T = d.T;
