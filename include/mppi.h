@@ -185,7 +185,12 @@ mppi_status mppi_step_resident(mppi_t* h, const double x0[4]);
 mppi_status mppi_step_batch(mppi_t* const* hs, const double* x0s, const mppi_scene* scenes,
                             int32_t n);
 
-/* Wait for the handle's stream; returns the status of the last step. */
+/* Wait for the handle's stream; returns the status of the last step.
+ * mppi_sync, mppi_get_controls, mppi_get_state, mppi_get_iter_stats and
+ * mppi_get_trajectory have the device write their results into a small
+ * pinned host buffer of the handle, made by the first of them that reads
+ * a result (mppi_sync reads one only once the handle has stepped);
+ * MPPI_E_NOMEM if it cannot be made. */
 mppi_status mppi_sync(mppi_t* h);
 
 /* Copy U (the nominal controls, [T][2] = (a, delta)) into out; n >= 2T.
