@@ -73,6 +73,21 @@ def load_traffic(n_launch_units):
 
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "counters_iteration_c1.json")
+TRACE_FILE = os.path.join(ROOT, "profiles", "trace_iteration_c1.json")
+
+
+def load_trace():
+    """Kernel-trace statistics of the iteration and combine kernels at the
+    benchmark workload (rocprofv3 --kernel-trace --stats of bench.py --probe),
+    if they were taken on the current kernel source."""
+    try:
+        with open(TRACE_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t
 
 
 def load_counters():
@@ -535,9 +550,19 @@ def main(argv=None):
             salu_instructions_per_wave=round(pw.get("SQ_INSTS_SALU", 0.0), 1),
             wave_quad_cycles=round(pw.get("SQ_WAVE_CYCLES", 0.0), 1),
             waiting_quad_cycles=round(pw.get("SQ_WAIT_INST_ANY", 0.0), 1))
+    tr = load_trace()
+    kernel_trace = None
+    if tr:
+        kt = tr["iteration"]["average_ns"] * 1e-9
+        kernel_trace = dict(
+            source="profiles/trace_iteration_c1.json (rocprofv3 --kernel-trace, %d dispatches)"
+                   % tr["iteration"]["calls"],
+            kernel_ms=round(kt * 1e3, 5), achieved=round(F * K * T / kt / 1e12, 3),
+            frac=round(F * K * T / kt / 1e12 / PEAK_FP32_TFLOPS, 4),
+            combine_ms=round(tr["combine"]["average_ns"] * 1e-6, 5))
     roofline = dict(bound="alu", achieved=round(achieved, 3), peak=PEAK_FP32_TFLOPS,
                     unit="TFLOP/s", frac=round(achieved / PEAK_FP32_TFLOPS, 4),
-                    traffic=load_traffic(K * T), executed=executed,
+                    traffic=load_traffic(K * T), executed=executed, kernel_trace=kernel_trace,
                     achieved_counts="algorithmic flops of full scans (the kernel culls them "
                                     "exactly; executed holds what the hardware counted)",
                     kernel="k_batch<G,NE,M5> (sampling, rollouts, costs, tile partials)",

@@ -10,6 +10,9 @@
     FP32 instruction mix.
 ``python -m paper_2308_01654_amd.profsum stats DIR``
     Kernel-trace statistics (``--kernel-trace --stats``) as a Markdown table.
+``python -m paper_2308_01654_amd.profsum trace DIR OUT.json``
+    The same statistics of the iteration and combine kernels as a record
+    (calls, average, minimum and maximum duration in ns).
 
 Every JSON record carries the hash of the kernel source it was taken on;
 bench.py reports a record only while that hash matches the source.
@@ -116,6 +119,30 @@ def stats(d):
             float(r["Percentage"]), r["MinNs"], r["MaxNs"]))
 
 
+def _stat_rows(d):
+    files = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError("no kernel_stats.csv under %s" % d)
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def trace(d, out):
+    rec = dict(kernel_source_sha256_16=kernel_source_hash())
+    for key, name in (("k_batch", "iteration"), ("k_combine", "combine")):
+        # the row of the kernel that ran most often (the benchmark's launches)
+        rows = [r for r in _stat_rows(d) if key in r["Name"]]
+        if not rows:
+            raise KeyError(key)
+        r = max(rows, key=lambda x: int(x["Calls"]))
+        rec[name] = dict(kernel=r["Name"], calls=int(r["Calls"]),
+                         average_ns=float(r["AverageNs"]), min_ns=float(r["MinNs"]),
+                         max_ns=float(r["MaxNs"]))
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 if __name__ == "__main__":
     cmd = sys.argv[1]
     if cmd == "traffic":
@@ -124,5 +151,7 @@ if __name__ == "__main__":
         counters(sys.argv[2:-1], sys.argv[-1])
     elif cmd == "stats":
         stats(sys.argv[2])
+    elif cmd == "trace":
+        trace(sys.argv[2], sys.argv[3])
     else:
         raise SystemExit(__doc__)

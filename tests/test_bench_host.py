@@ -44,3 +44,16 @@ def test_counter_summaries_only_for_their_kernel_source(tmp_path, monkeypatch):
     assert bench.load_traffic(1) is None
     f.write_text("not json")
     assert bench.load_traffic(1) is None
+
+
+def test_trace_record_only_for_its_kernel_source(tmp_path, monkeypatch):
+    rec = {"kernel_source_sha256_16": bench.kernel_source_hash(),
+           "iteration": {"average_ns": 1.0, "calls": 1}, "combine": {"average_ns": 1.0}}
+    f = tmp_path / "trace.json"
+    f.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.json"))
+    monkeypatch.setattr(bench, "TRACE_FILE", str(f))
+    assert bench.load_trace()["iteration"]["average_ns"] == 1.0
+    rec["kernel_source_sha256_16"] = "f" * 16
+    f.write_text(json.dumps(rec))
+    assert bench.load_trace() is None

@@ -59,3 +59,22 @@ def test_counters_per_wave_and_executed_flops(tmp_path):
     assert r["per_wave"]["SQ_INSTS_VALU"] == 10.0
     # an FMA instruction counts 2 flops in the counter; every lane of the wave counts
     assert r["executed_fp32_flop_per_dispatch"] == 64.0 * 1000.0
+
+
+def test_trace_record_of_the_most_frequent_launches(tmp_path):
+    d = tmp_path / "t"
+    d.mkdir()
+    with open(d / "run_kernel_stats.csv", "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(["Name", "Calls", "TotalDurationNs", "AverageNs", "Percentage", "MinNs", "MaxNs", "StdDev"])
+        w.writerow(["void mppi_impl::k_batch<16, 3, false>(...)", 200, 7000000, 35000.0, 80, 33000, 41000, 1])
+        w.writerow(["void mppi_impl::k_batch<8, 3, false>(...)", 3, 300, 100.0, 1, 90, 110, 1])
+        w.writerow(["void mppi_impl::k_combine<2>(...)", 200, 900000, 4500.0, 10, 4000, 5000, 1])
+        w.writerow(["mppi_impl::k_copy(...)", 3, 300000, 100000.0, 9, 99000, 101000, 1])
+    out = tmp_path / "trace.json"
+    profsum.trace(str(d), str(out))
+    r = json.loads(out.read_text())
+    assert r["iteration"]["calls"] == 200 and r["iteration"]["average_ns"] == 35000.0
+    assert "k_batch<16" in r["iteration"]["kernel"]
+    assert r["combine"]["average_ns"] == 4500.0
+    assert r["kernel_source_sha256_16"] == profsum.kernel_source_hash()
